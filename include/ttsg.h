@@ -1,0 +1,217 @@
+/*
+ * ttsg.h -- C ABI of the MI355X (gfx950) hot path of randomized sketched
+ * TT-GMRES (Bucci, Palitta, Robol: "Randomized sketched TT-GMRES for linear
+ * systems with tensor structure").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - A TT tensor of order d with mode sizes n[0..d-1] and ranks r[0..d]
+ *    (r[0] = r[d] = 1) is passed as an array of d DEVICE pointers; core k is a
+ *    row-major float64 array of shape r[k] x n[k] x r[k+1] (eq. tt-format of
+ *    Sec. 2.2, 0-based modes).  `n`, `r` and the pointer arrays live in HOST
+ *    memory; the cores themselves in device memory.
+ *  - A TT-matrix (operator) with ranks R[0..d] is an array of d DEVICE
+ *    pointers; core k has shape R[k] x n[k] x n[k] x R[k+1], row index first
+ *    (eq. operator tt-format of Sec. 2.2).  (A x)[i] = sum_j A[i, j] x[j].
+ *  - Merged ranks of a matrix-vector product put the vector rank outer and the
+ *    operator rank inner: index (a, alpha) -> a * R + alpha (Sec. 2.2).
+ *  - Khatri-Rao sketch factors S_k (Sec. 3.1): d DEVICE pointers, each an
+ *    s x n[k] row-major float64 array; row j of S is kron_k S_k[j, :].
+ *  - STTA sketch tensors (Sec. 3.3): the left Gaussian TT-DRM Y has ranks
+ *    rho[0..d] and cores for modes 0..d-2 (d-1 DEVICE pointers, core k is
+ *    rho[k] x n[k] x rho[k+1]); the right DRM X has ranks rx[0..d] and cores for
+ *    modes 1..d-1 (d-1 DEVICE pointers, entry k-1 holds the core of mode k,
+ *    rx[k] x n[k] x rx[k+1]).  rho[0] = rho[d] = rx[0] = rx[d] = 1.
+ *  - Every call is stream-ordered on `stream` (a hipStream_t; NULL = the
+ *    default stream).  Calls that must return data-dependent ranks synchronize
+ *    the stream before returning; the others do not.
+ *  - The caller owns all buffers it passes.  Scratch memory is taken from the
+ *    optional workspace (ws, ws_bytes); when ws is NULL the library allocates
+ *    what it needs with hipMallocAsync on `stream` and releases it before
+ *    returning.  Distinct workspaces make concurrent calls independent.
+ *  - Return value: 0 on success, > 0 a warning (TTSG_NOT_CONVERGED, ...),
+ *    < 0 an error (-TTSG_ERR_*).  No C++ exception crosses this boundary.
+ *    ttsg_last_error() returns a static description of the last failure on
+ *    the calling thread.
+ */
+#ifndef TTSG_H
+#define TTSG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* ttsg_stream_t; /* a hipStream_t */
+
+enum {
+    TTSG_OK = 0,
+    TTSG_NOT_CONVERGED = 1, /* iteration budget spent before the true residual met tol */
+    TTSG_BREAKDOWN = 2,     /* h_{k+1,k} = 0: the Krylov space is invariant, solution exact */
+    TTSG_ERR_ARG = 1,       /* returned negated: bad sizes, ranks or pointers */
+    TTSG_ERR_CAPACITY = 2,  /* an output capacity is smaller than required */
+    TTSG_ERR_WS = 3,        /* workspace too small */
+    TTSG_ERR_NONFINITE = 4, /* a NaN/Inf appeared in the iteration */
+    TTSG_ERR_HIP = 5        /* a HIP runtime call failed (see ttsg_last_error) */
+};
+
+/* Arithmetic of the contraction kernels. */
+typedef enum {
+    TTSG_PREC_F64 = 0,   /* everything in float64 (FP64 MFMA) */
+    TTSG_PREC_MIXED = 1, /* sketch/rounding contractions in float32 with float32
+                            accumulation; least squares, QR/SVD, recovery and the
+                            final solution in float64 */
+    TTSG_PREC_BF16 = 2   /* as MIXED, but the STTA sketch of A v_k and the
+                            orthogonalization coefficients use bfloat16 MFMA
+                            inputs with float32 accumulation */
+} ttsg_precision;
+
+/* ------------------------------------------------------------------------- */
+/* Library                                                                   */
+/* ------------------------------------------------------------------------- */
+
+/* Static, NUL-terminated description of the last error on this thread. */
+const char* ttsg_last_error(void);
+
+/* Version string of the library build. */
+const char* ttsg_version(void);
+
+/* ------------------------------------------------------------------------- */
+/* TT matrix-vector product (Sec. 2.2):                                      */
+/*   G_k[(a,al), i, (b,be)] = sum_j D_k[al, i, j, be] C_k[a, j, b]           */
+/* ------------------------------------------------------------------------- */
+/* y_cores[k] must hold (r[k]*R[k]) x n[k] x (r[k+1]*R[k+1]) float64 values.
+ * transpose != 0 applies the transposed operator (row and column swapped).
+ * Does not synchronize. */
+int ttsg_matvec(int32_t d, const int32_t* n, const int32_t* R, const double* const* A,
+                const int32_t* r, const double* const* x, int32_t transpose,
+                double* const* y, ttsg_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Khatri-Rao sketch (Sec. 3.1): w = S x, or w = S (A x) when A != NULL       */
+/* without forming A x.  (S x)_j = prod_k sum_i S_k[j, i] C_k[:, i, :].       */
+/* ------------------------------------------------------------------------- */
+/* w: DEVICE float64 array of length s.  R/A may be NULL (plain sketch).
+ * precision: TTSG_PREC_F64 or TTSG_PREC_MIXED (float32 contractions).
+ * Does not synchronize. */
+int ttsg_kr_sketch(int32_t d, const int32_t* n, int32_t s, const double* const* S,
+                   const int32_t* R, const double* const* A,
+                   const int32_t* r, const double* const* x,
+                   double* w, int32_t precision,
+                   void* ws, size_t ws_bytes, ttsg_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* STTA sketch (Sec. 3.3) of x, or of A x when A != NULL:                     */
+/*   Psi_k   = (Y_{<=k-1}^T (x) I) T_{<=k} X_{>k}   shape rho[k] x n[k] x rx[k+1] */
+/*   Omega_b = Y_{<=b}^T T_{<=b} X_{>b}             shape rho[b] x rx[b], b=1..d-1 */
+/* ------------------------------------------------------------------------- */
+/* Psi: d DEVICE pointers; Omega: d-1 DEVICE pointers (entry b-1 for bond b).
+ * Does not synchronize. */
+int ttsg_stta_sketch(int32_t d, const int32_t* n,
+                     const int32_t* rho, const double* const* Y,
+                     const int32_t* rx, const double* const* X,
+                     const int32_t* R, const double* const* A,
+                     const int32_t* r, const double* const* x,
+                     double* const* Psi, double* const* Omega, int32_t precision,
+                     void* ws, size_t ws_bytes, ttsg_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Randomized rounding (Sec. 3.3, STTA_sketch + STTA_recover):                */
+/* sketch x with (Y, X), recover C^_0 = Psi_0, C^_k = Omega_k^+ Psi_k (pseudo-  */
+/* inverse by FP64 SVD with relative cutoff rcond), then TT-SVD of the small  */
+/* recovered tensor at relative tolerance tol with every rank capped at       */
+/* maxrank (0 = no cap) (Sec. 2.2 rounding; cap of Sec. 4.2).                  */
+/* ------------------------------------------------------------------------- */
+/* out: d DEVICE pointers, core k with capacity rx[k] x n[k] x rx[k+1];
+ * out_r: HOST int32[d+1] receives the ranks of the result.
+ * Synchronizes `stream` (the ranks are data dependent). */
+int ttsg_round_rand(int32_t d, const int32_t* n,
+                    const int32_t* r, const double* const* x,
+                    const int32_t* rho, const double* const* Y,
+                    const int32_t* rx, const double* const* X,
+                    double tol, int32_t maxrank, double rcond,
+                    double* const* out, int32_t* out_r, int32_t precision,
+                    void* ws, size_t ws_bytes, ttsg_stream_t stream);
+
+/* Deterministic TT-SVD rounding (Sec. 2.2) of x at relative tolerance tol,
+ * ranks capped at maxrank (0 = none).  out cores have capacity r[k] x n[k] x
+ * r[k+1] (rounding never increases ranks).  Synchronizes `stream`. */
+int ttsg_round_svd(int32_t d, const int32_t* n, const int32_t* r, const double* const* x,
+                   double tol, int32_t maxrank, double* const* out, int32_t* out_r,
+                   void* ws, size_t ws_bytes, ttsg_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Sketched TT-GMRES (Alg. 4, enhanced TT-sGMRES)                             */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t maxit;       /* total iteration budget over all cycles */
+    int32_t restart;     /* cycle length m; 0 = maxit (restart of Sec. 3.4) */
+    int32_t q;           /* incomplete orthogonalization window (paper's l) */
+    int32_t maxrank;     /* rank cap of the basis vectors (0 = only rx caps) */
+    int32_t precision;   /* ttsg_precision */
+    int32_t max_cycles;  /* cap on restart cycles (0 = 50) */
+    double tol;          /* target true relative residual ||b - A x|| / ||b|| */
+    double round_tol;    /* basis rounding tolerance (eta * tol) */
+    double final_tol;    /* rounding tolerance of the solution (0 = round_tol) */
+    double stop_safety;  /* a cycle stops when ||W y - S r0|| <= stop_safety*tol*||S b|| */
+    double rcond;        /* relative cutoff of the pseudo-inverses in STTA_recover */
+} ttsg_sgmres_opts;
+
+typedef struct {
+    int32_t iterations;       /* total Krylov iterations */
+    int32_t cycles;           /* restart cycles run */
+    int32_t max_rank;         /* largest basis rank seen */
+    int32_t status;           /* same as the return value */
+    double true_residual;     /* FP64 ||b - A x|| / ||b|| of the returned x */
+    double sketched_residual; /* last ||W y - S r0|| / ||S b|| */
+    /* optional HOST arrays (may be NULL): per-iteration sketched residual and
+       basis rank (length >= maxit), per-cycle true residual (>= max_cycles),
+       and the seconds spent in each phase (length >= 8, see ttsg_phase). */
+    double* sketched_history;
+    int32_t* rank_history;
+    double* true_history;
+    double* phase_seconds;
+} ttsg_sgmres_info;
+
+/* Phases reported in info->phase_seconds (host wall clock with stream syncs
+ * only when phase timing is requested). */
+enum { TTSG_PH_KR = 0, TTSG_PH_INNER = 1, TTSG_PH_STTA = 2, TTSG_PH_RECOVER = 3,
+       TTSG_PH_TTSVD = 4, TTSG_PH_LS = 5, TTSG_PH_FINAL = 6, TTSG_PH_OTHER = 7 };
+
+/* Solve A x = b with x_0 = 0.  The sketches S (s rows), Y and X are supplied
+ * by the caller.  x: d DEVICE pointers with capacity rx[k] x n[k] x rx[k+1];
+ * x_r: HOST int32[d+1] receives the solution ranks.  Returns TTSG_OK when the
+ * FP64 true residual is <= tol, TTSG_NOT_CONVERGED when the budget ran out
+ * (x is then the last iterate), or a negative error.  Synchronizes `stream`. */
+int ttsg_sgmres_solve(int32_t d, const int32_t* n,
+                      const int32_t* R, const double* const* A,
+                      const int32_t* rb, const double* const* b,
+                      int32_t s, const double* const* S,
+                      const int32_t* rho, const double* const* Y,
+                      const int32_t* rx, const double* const* X,
+                      const ttsg_sgmres_opts* opts,
+                      double* const* x, int32_t* x_r,
+                      ttsg_sgmres_info* info,
+                      void* ws, size_t ws_bytes, ttsg_stream_t stream);
+
+/* FP64 true residual ||b - A x|| / ||b|| through TT arithmetic on the GPU
+ * (b - A x formed as a TT, its norm taken after QR orthogonalization).
+ * Synchronizes `stream`; result in *res. */
+int ttsg_true_residual(int32_t d, const int32_t* n,
+                       const int32_t* R, const double* const* A,
+                       const int32_t* rb, const double* const* b,
+                       const int32_t* r, const double* const* x,
+                       double* res, void* ws, size_t ws_bytes, ttsg_stream_t stream);
+
+/* <x, y> by a left-to-right environment sweep (Sec. 2.2).  Synchronizes. */
+int ttsg_dot(int32_t d, const int32_t* n, const int32_t* rxr, const double* const* x,
+             const int32_t* ryr, const double* const* y, double* out,
+             void* ws, size_t ws_bytes, ttsg_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTSG_H */
