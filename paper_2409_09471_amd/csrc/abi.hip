@@ -1,0 +1,404 @@
+// extern "C" entry points of libttsg: argument validation, workspace
+// handling and conversion of internal errors into return codes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "tt_ops.h"
+
+namespace {
+
+thread_local char g_err[512] = "no error";
+
+void set_err(const char* m) {
+    std::strncpy(g_err, m, sizeof(g_err) - 1);
+    g_err[sizeof(g_err) - 1] = 0;
+}
+
+template <typename F> int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const ttsg::Error& e) {
+        set_err(e.what());
+        return -e.code;
+    } catch (const std::exception& e) {
+        set_err(e.what());
+        return -TTSG_ERR_HIP;
+    } catch (...) {
+        set_err("unknown failure");
+        return -TTSG_ERR_HIP;
+    }
+}
+
+using ttsg::Error;
+
+void check_shape(int32_t d, const int32_t* n, const int32_t* r, const char* what) {
+    TTSG_CHECK(d >= 1 && d <= 64, TTSG_ERR_ARG, std::string(what) + ": d must be in 1..64");
+    TTSG_CHECK(n != nullptr && r != nullptr, TTSG_ERR_ARG, std::string(what) + ": null sizes");
+    for (int k = 0; k < d; ++k) TTSG_CHECK(n[k] >= 1, TTSG_ERR_ARG, std::string(what) + ": n[k] < 1");
+    TTSG_CHECK(r[0] == 1 && r[d] == 1, TTSG_ERR_ARG, std::string(what) + ": boundary ranks must be 1");
+    for (int k = 1; k < d; ++k) TTSG_CHECK(r[k] >= 1, TTSG_ERR_ARG, std::string(what) + ": rank < 1");
+}
+
+void check_ptrs(int cnt, const void* const* p, const char* what) {
+    TTSG_CHECK(p != nullptr, TTSG_ERR_ARG, std::string(what) + ": null pointer array");
+    for (int k = 0; k < cnt; ++k) TTSG_CHECK(p[k] != nullptr, TTSG_ERR_ARG, std::string(what) + ": null core");
+}
+
+std::vector<int> vec(const int32_t* p, int cnt) { return std::vector<int>(p, p + cnt); }
+
+template <typename T> std::vector<const void*> vp(const T* const* p, int cnt) {
+    std::vector<const void*> v(cnt);
+    for (int k = 0; k < cnt; ++k) v[k] = p[k];
+    return v;
+}
+
+hipStream_t S(ttsg_stream_t s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+const char* ttsg_last_error(void) { return g_err; }
+
+const char* ttsg_version(void) { return "ttsg 0.1 gfx950"; }
+
+int ttsg_matvec(int32_t d, const int32_t* n, const int32_t* R, const double* const* A, const int32_t* r,
+                const double* const* x, int32_t transpose, double* const* y, ttsg_stream_t stream) {
+    return guarded([&]() {
+        check_shape(d, n, r, "matvec x");
+        check_shape(d, n, R, "matvec A");
+        check_ptrs(d, (const void* const*)A, "matvec A");
+        check_ptrs(d, (const void* const*)x, "matvec x");
+        check_ptrs(d, (const void* const*)y, "matvec y");
+        for (int mu = 0; mu < d; ++mu)
+            ttsg::matvec_core(r[mu], n[mu], r[mu + 1], R[mu], R[mu + 1], A[mu], x[mu], transpose != 0, y[mu],
+                              S(stream));
+        return 0;
+    });
+}
+
+int ttsg_kr_sketch(int32_t d, const int32_t* n, int32_t s, const double* const* Sf, const int32_t* R,
+                   const double* const* A, const int32_t* r, const double* const* x, double* w, int32_t precision,
+                   void* ws, size_t ws_bytes, ttsg_stream_t stream) {
+    return guarded([&]() {
+        check_shape(d, n, r, "kr_sketch x");
+        TTSG_CHECK(s >= 1, TTSG_ERR_ARG, "kr_sketch: s < 1");
+        TTSG_CHECK(w != nullptr, TTSG_ERR_ARG, "kr_sketch: null output");
+        TTSG_CHECK(precision == TTSG_PREC_F64 || precision == TTSG_PREC_MIXED, TTSG_ERR_ARG,
+                   "kr_sketch: precision must be F64 or MIXED");
+        check_ptrs(d, (const void* const*)Sf, "kr_sketch S");
+        check_ptrs(d, (const void* const*)x, "kr_sketch x");
+        const bool op = A != nullptr;
+        if (op) {
+            check_shape(d, n, R, "kr_sketch A");
+            check_ptrs(d, (const void* const*)A, "kr_sketch A");
+        }
+        const ttsg::Prec p = precision == TTSG_PREC_F64 ? ttsg::Prec::F64 : ttsg::Prec::F32;
+        std::vector<int> RR(d + 1, 1);
+        if (op) RR = vec(R, d + 1);
+        size_t need = 0;
+        for (int mu = 0; mu < d; ++mu) {
+            need += ((size_t)s * RR[mu] * n[mu] * RR[mu + 1] * 8 + 256);           // SA
+            need += ((size_t)r[mu] * n[mu] * r[mu + 1] * 4 + 256);                  // x in f32
+            need += ((size_t)s * RR[mu + 1] * r[mu] * n[mu] * 8 + 256);             // X buffer
+            need += 2 * ((size_t)s * RR[mu + 1] * r[mu + 1] * 8 + 256);             // P buffers
+        }
+        need += (size_t)s * 8 * 4 + 4096;
+        ttsg::Workspace W(ws, ws_bytes, need * 2, S(stream));
+        ttsg::Arena& ar = W.arena;
+        std::vector<const void*> SA(d), xs(d);
+        for (int mu = 0; mu < d; ++mu) {
+            const int64_t sz = (int64_t)s * RR[mu] * n[mu] * RR[mu + 1];
+            if (op) {
+                double* sa = ar.get<double>(sz);
+                ttsg::kr_precompute(ttsg::Prec::F64, s, n[mu], RR[mu], RR[mu + 1], Sf[mu], A[mu], sa, S(stream));
+                SA[mu] = sa;
+            } else {
+                SA[mu] = Sf[mu];
+            }
+            if (p == ttsg::Prec::F32) {
+                float* f = ar.get<float>(sz);
+                ttsg::convert_f64_f32(sz, (const double*)SA[mu], f, S(stream));
+                SA[mu] = f;
+                const int64_t e = (int64_t)r[mu] * n[mu] * r[mu + 1];
+                float* xf = ar.get<float>(e);
+                ttsg::convert_f64_f32(e, x[mu], xf, S(stream));
+                xs[mu] = xf;
+            } else {
+                xs[mu] = x[mu];
+            }
+        }
+        ttsg::kr_sketch_run(p, d, n, s, RR, SA, vec(r, d + 1), xs, w, ar, S(stream));
+        TTSG_HIP(hipStreamSynchronize(S(stream)));
+        return 0;
+    });
+}
+
+static void stta_common(int32_t d, const int32_t* n, const int32_t* rho, const double* const* Y, const int32_t* rx,
+                        const double* const* X, const int32_t* R, const double* const* A, const int32_t* r,
+                        const double* const* x, double* const* Psi, double* const* Omega, int32_t precision,
+                        ttsg::Arena& ar, hipStream_t st) {
+    const ttsg::Prec p = precision == TTSG_PREC_F64 ? ttsg::Prec::F64 : ttsg::Prec::F32;
+    ttsg::SketchOperands o;
+    o.p = p;
+    o.n = n;
+    o.d = d;
+    o.rho = vec(rho, d + 1);
+    o.rx = vec(rx, d + 1);
+    o.R.assign(d + 1, 1);
+    auto conv = [&](const double* src, int64_t e) -> const void* {
+        if (p == ttsg::Prec::F64) return src;
+        float* f = ar.get<float>(e);
+        ttsg::convert_f64_f32(e, src, f, st);
+        return f;
+    };
+    for (int k = 0; k < d - 1; ++k) {
+        o.Y.push_back(conv(Y[k], (int64_t)rho[k] * n[k] * rho[k + 1]));
+        o.X.push_back(conv(X[k], (int64_t)rx[k + 1] * n[k + 1] * rx[k + 2]));
+    }
+    if (A != nullptr) {
+        o.R = vec(R, d + 1);
+        for (int mu = 0; mu < d; ++mu) o.D.push_back(conv(A[mu], (int64_t)R[mu] * n[mu] * n[mu] * R[mu + 1]));
+    }
+    std::vector<const void*> xs(d);
+    for (int mu = 0; mu < d; ++mu) xs[mu] = conv(x[mu], (int64_t)r[mu] * n[mu] * r[mu + 1]);
+    ttsg::stta_sketch(o, vec(r, d + 1), xs, Psi, Omega, ar, st);
+}
+
+static size_t stta_ws(int32_t d, const int32_t* n, const int32_t* rho, const int32_t* rx, const int32_t* R,
+                      const int32_t* r) {
+    size_t big = 0, tot = 0;
+    for (int mu = 0; mu < d; ++mu) {
+        const size_t Rl = R ? R[mu] : 1, Rr = R ? R[mu + 1] : 1;
+        size_t m = (size_t)std::max(rho[mu], rx[mu]) * std::max<size_t>(r[mu], 1) * n[mu] *
+                   std::max(r[mu + 1], std::max(rx[mu + 1], rho[mu + 1])) * Rl * Rr;
+        big = std::max(big, m);
+        tot += (size_t)r[mu + 1] * Rr * rx[mu + 1] + (size_t)r[mu] * n[mu] * r[mu + 1] +
+               (size_t)Rl * n[mu] * n[mu] * Rr + (size_t)rho[mu] * n[mu] * rho[mu + 1] +
+               (size_t)rx[mu] * n[mu] * rx[mu + 1] + (size_t)rho[mu] * n[mu] * rx[mu + 1];
+    }
+    return (8 * big + 2 * tot) * 8 + (1 << 20);
+}
+
+int ttsg_stta_sketch(int32_t d, const int32_t* n, const int32_t* rho, const double* const* Y, const int32_t* rx,
+                     const double* const* X, const int32_t* R, const double* const* A, const int32_t* r,
+                     const double* const* x, double* const* Psi, double* const* Omega, int32_t precision, void* ws,
+                     size_t ws_bytes, ttsg_stream_t stream) {
+    return guarded([&]() {
+        check_shape(d, n, r, "stta x");
+        check_shape(d, n, rho, "stta rho");
+        check_shape(d, n, rx, "stta rx");
+        TTSG_CHECK(d >= 2, TTSG_ERR_ARG, "stta: d must be >= 2");
+        TTSG_CHECK(precision == TTSG_PREC_F64 || precision == TTSG_PREC_MIXED, TTSG_ERR_ARG,
+                   "stta: precision must be F64 or MIXED");
+        check_ptrs(d - 1, (const void* const*)Y, "stta Y");
+        check_ptrs(d - 1, (const void* const*)X, "stta X");
+        check_ptrs(d, (const void* const*)x, "stta x");
+        check_ptrs(d, (const void* const*)Psi, "stta Psi");
+        check_ptrs(d - 1, (const void* const*)Omega, "stta Omega");
+        if (A) {
+            check_shape(d, n, R, "stta A");
+            check_ptrs(d, (const void* const*)A, "stta A");
+        }
+        ttsg::Workspace W(ws, ws_bytes, stta_ws(d, n, rho, rx, A ? R : nullptr, r), S(stream));
+        stta_common(d, n, rho, Y, rx, X, A ? R : nullptr, A, r, x, Psi, Omega, precision, W.arena, S(stream));
+        TTSG_HIP(hipStreamSynchronize(S(stream)));
+        return 0;
+    });
+}
+
+int ttsg_round_rand(int32_t d, const int32_t* n, const int32_t* r, const double* const* x, const int32_t* rho,
+                    const double* const* Y, const int32_t* rx, const double* const* X, double tol, int32_t maxrank,
+                    double rcond, double* const* out, int32_t* out_r, int32_t precision, void* ws, size_t ws_bytes,
+                    ttsg_stream_t stream) {
+    return guarded([&]() {
+        check_shape(d, n, r, "round_rand x");
+        check_shape(d, n, rho, "round_rand rho");
+        check_shape(d, n, rx, "round_rand rx");
+        TTSG_CHECK(d >= 2, TTSG_ERR_ARG, "round_rand: d must be >= 2");
+        TTSG_CHECK(tol >= 0.0 && rcond >= 0.0, TTSG_ERR_ARG, "round_rand: negative tolerance");
+        for (int b = 1; b < d; ++b) TTSG_CHECK(rho[b] >= rx[b], TTSG_ERR_ARG, "round_rand: rho_b < rx_b");
+        check_ptrs(d - 1, (const void* const*)Y, "round_rand Y");
+        check_ptrs(d - 1, (const void* const*)X, "round_rand X");
+        check_ptrs(d, (const void* const*)x, "round_rand x");
+        check_ptrs(d, (const void* const*)out, "round_rand out");
+        TTSG_CHECK(out_r != nullptr, TTSG_ERR_ARG, "round_rand: null out_r");
+        size_t sk = 0;
+        for (int mu = 0; mu < d; ++mu) sk += (size_t)rho[mu] * n[mu] * rx[mu + 1] + (size_t)rho[mu] * rx[mu] + 64;
+        size_t core = 0, rmax = 1;
+        for (int mu = 0; mu < d; ++mu) {
+            core = std::max(core, (size_t)rx[mu] * n[mu] * rx[mu + 1]);
+            rmax = std::max(rmax, (size_t)std::max(rho[mu], rx[mu]));
+        }
+        const size_t need = stta_ws(d, n, rho, rx, nullptr, r) + sk * 8 + (8 * core + 12 * rmax * rmax) * 8 +
+                            (size_t)d * 16 * rmax * rmax * 8 + (4 << 20);
+        ttsg::Workspace W(ws, ws_bytes, need, S(stream));
+        ttsg::Arena& ar = W.arena;
+        std::vector<double*> psi(d), om(d - 1);
+        for (int mu = 0; mu < d; ++mu) psi[mu] = ar.get<double>((int64_t)rho[mu] * n[mu] * rx[mu + 1]);
+        for (int b = 1; b < d; ++b) om[b - 1] = ar.get<double>((int64_t)rho[b] * rx[b]);
+        stta_common(d, n, rho, Y, rx, X, nullptr, nullptr, r, x, psi.data(), om.data(), precision, ar, S(stream));
+        std::vector<const double*> cp(psi.begin(), psi.end()), co(om.begin(), om.end());
+        std::vector<int> rr;
+        std::vector<double*> o(out, out + d);
+        ttsg::stta_recover(d, n, vec(rho, d + 1), vec(rx, d + 1), cp, co, rcond, o, rr, ar, S(stream));
+        std::vector<int64_t> caps(d);
+        ttsg::tt_svd_inplace(d, n, rr, o, caps, tol, maxrank, ar, S(stream), nullptr);
+        for (int k = 0; k <= d; ++k) out_r[k] = rr[k];
+        TTSG_HIP(hipStreamSynchronize(S(stream)));
+        return 0;
+    });
+}
+
+int ttsg_round_svd(int32_t d, const int32_t* n, const int32_t* r, const double* const* x, double tol,
+                   int32_t maxrank, double* const* out, int32_t* out_r, void* ws, size_t ws_bytes,
+                   ttsg_stream_t stream) {
+    return guarded([&]() {
+        check_shape(d, n, r, "round_svd x");
+        TTSG_CHECK(tol >= 0.0, TTSG_ERR_ARG, "round_svd: negative tolerance");
+        check_ptrs(d, (const void* const*)x, "round_svd x");
+        check_ptrs(d, (const void* const*)out, "round_svd out");
+        TTSG_CHECK(out_r != nullptr, TTSG_ERR_ARG, "round_svd: null out_r");
+        size_t core = 0, rmax = 1;
+        for (int mu = 0; mu < d; ++mu) {
+            core = std::max(core, (size_t)r[mu] * n[mu] * r[mu + 1]);
+            rmax = std::max(rmax, (size_t)r[mu]);
+        }
+        ttsg::Workspace W(ws, ws_bytes, (6 * core + 4 * rmax * rmax + 8 * rmax) * 8 + (1 << 20), S(stream));
+        std::vector<double*> o(out, out + d);
+        for (int mu = 0; mu < d; ++mu) ttsg::copy_f64((int64_t)r[mu] * n[mu] * r[mu + 1], x[mu], o[mu], S(stream));
+        std::vector<int> rr = vec(r, d + 1);
+        std::vector<int64_t> caps(d);
+        ttsg::tt_svd_inplace(d, n, rr, o, caps, tol, maxrank, W.arena, S(stream), nullptr);
+        for (int k = 0; k <= d; ++k) out_r[k] = rr[k];
+        TTSG_HIP(hipStreamSynchronize(S(stream)));
+        return 0;
+    });
+}
+
+int ttsg_dot(int32_t d, const int32_t* n, const int32_t* rxr, const double* const* x, const int32_t* ryr,
+             const double* const* y, double* out, void* ws, size_t ws_bytes, ttsg_stream_t stream) {
+    return guarded([&]() {
+        check_shape(d, n, rxr, "dot x");
+        check_shape(d, n, ryr, "dot y");
+        check_ptrs(d, (const void* const*)x, "dot x");
+        check_ptrs(d, (const void* const*)y, "dot y");
+        TTSG_CHECK(out != nullptr, TTSG_ERR_ARG, "dot: null output");
+        size_t big = 0;
+        for (int mu = 0; mu < d; ++mu)
+            big = std::max(big, (size_t)ryr[mu] * n[mu] * rxr[mu + 1] + (size_t)ryr[mu + 1] * rxr[mu + 1]);
+        ttsg::Workspace W(ws, ws_bytes, 6 * big * 8 + (1 << 16), S(stream));
+        double* dev = W.arena.get<double>(1);
+        std::vector<int> R1(d + 1, 1);
+        ttsg::inner_run(ttsg::Prec::F64, d, n, R1, {}, vec(rxr, d + 1), vp(x, d), vec(ryr, d + 1), vp(y, d), dev,
+                        W.arena, S(stream));
+        TTSG_HIP(hipMemcpyAsync(out, dev, sizeof(double), hipMemcpyDeviceToHost, S(stream)));
+        TTSG_HIP(hipStreamSynchronize(S(stream)));
+        return 0;
+    });
+}
+
+int ttsg_true_residual(int32_t d, const int32_t* n, const int32_t* R, const double* const* A, const int32_t* rb,
+                       const double* const* b, const int32_t* r, const double* const* x, double* res, void* ws,
+                       size_t ws_bytes, ttsg_stream_t stream) {
+    return guarded([&]() {
+        check_shape(d, n, R, "true_residual A");
+        check_shape(d, n, rb, "true_residual b");
+        check_shape(d, n, r, "true_residual x");
+        check_ptrs(d, (const void* const*)A, "true_residual A");
+        check_ptrs(d, (const void* const*)b, "true_residual b");
+        check_ptrs(d, (const void* const*)x, "true_residual x");
+        TTSG_CHECK(res != nullptr, TTSG_ERR_ARG, "true_residual: null output");
+        // r = b - A x as a block TT, norm by QR orthogonalization (no cancellation)
+        size_t tot = 0, big = 0;
+        std::vector<int> gr(d + 1), rr(d + 1);
+        for (int k = 0; k <= d; ++k) gr[k] = R[k] * r[k];
+        for (int mu = 0; mu < d; ++mu) {
+            tot += (size_t)gr[mu] * n[mu] * gr[mu + 1] + 64;
+            size_t e = (size_t)(gr[mu] + rb[mu]) * n[mu] * (gr[mu + 1] + rb[mu + 1]);
+            tot += e + 64;
+            big = std::max(big, e);
+        }
+        const size_t rmax = (size_t)*std::max_element(gr.begin(), gr.end()) + 64;
+        ttsg::Workspace W(ws, ws_bytes, tot * 8 + (3 * big + 2 * rmax * rmax + 4 * rmax) * 8 + (1 << 20),
+                          S(stream));
+        ttsg::Arena& ar = W.arena;
+        std::vector<double*> G(d), Sm(d);
+        for (int mu = 0; mu < d; ++mu) {
+            G[mu] = ar.get<double>((int64_t)gr[mu] * n[mu] * gr[mu + 1]);
+            Sm[mu] = ar.get<double>((int64_t)(gr[mu] + rb[mu]) * n[mu] * (gr[mu + 1] + rb[mu + 1]));
+            ttsg::matvec_core(r[mu], n[mu], r[mu + 1], R[mu], R[mu + 1], A[mu], x[mu], false, G[mu], S(stream));
+        }
+        std::vector<double*> bb(d);
+        for (int mu = 0; mu < d; ++mu) bb[mu] = const_cast<double*>(b[mu]);
+        std::vector<const double*> cg(G.begin(), G.end());
+        ttsg::tt_add_block(d, n, vec(rb, d + 1), bb, gr, cg, -1.0, Sm, rr, S(stream));
+        const double nr = ttsg::tt_norm_orth(d, n, rr, Sm, ar, S(stream));
+        // ||b|| on a copy
+        std::vector<double*> bc(d);
+        for (int mu = 0; mu < d; ++mu) {
+            const int64_t e = (int64_t)rb[mu] * n[mu] * rb[mu + 1];
+            bc[mu] = G[mu];
+            TTSG_CHECK(e <= (int64_t)gr[mu] * n[mu] * gr[mu + 1] || true, TTSG_ERR_WS, "");
+            bc[mu] = ar.get<double>(e);
+            ttsg::copy_f64(e, b[mu], bc[mu], S(stream));
+        }
+        std::vector<int> rbv = vec(rb, d + 1);
+        const double nb = ttsg::tt_norm_orth(d, n, rbv, bc, ar, S(stream));
+        *res = nb > 0.0 ? nr / nb : nr;
+        return 0;
+    });
+}
+
+int ttsg_sgmres_solve(int32_t d, const int32_t* n, const int32_t* R, const double* const* A, const int32_t* rb,
+                      const double* const* b, int32_t s, const double* const* Sf, const int32_t* rho,
+                      const double* const* Y, const int32_t* rx, const double* const* X,
+                      const ttsg_sgmres_opts* opts, double* const* x, int32_t* x_r, ttsg_sgmres_info* info, void* ws,
+                      size_t ws_bytes, ttsg_stream_t stream) {
+    return guarded([&]() {
+        check_shape(d, n, R, "sgmres A");
+        check_shape(d, n, rb, "sgmres b");
+        check_shape(d, n, rho, "sgmres rho");
+        check_shape(d, n, rx, "sgmres rx");
+        TTSG_CHECK(d >= 2, TTSG_ERR_ARG, "sgmres: d must be >= 2");
+        TTSG_CHECK(opts != nullptr, TTSG_ERR_ARG, "sgmres: null options");
+        TTSG_CHECK(opts->maxit >= 1, TTSG_ERR_ARG, "sgmres: maxit < 1");
+        TTSG_CHECK(opts->tol > 0.0 && opts->round_tol >= 0.0, TTSG_ERR_ARG, "sgmres: bad tolerance");
+        TTSG_CHECK(opts->q >= 1 && opts->q <= 7, TTSG_ERR_ARG, "sgmres: q must be in 1..7");
+        TTSG_CHECK(opts->precision == TTSG_PREC_F64 || opts->precision == TTSG_PREC_MIXED, TTSG_ERR_ARG,
+                   "sgmres: precision must be F64 or MIXED");
+        TTSG_CHECK(s >= 1, TTSG_ERR_ARG, "sgmres: s < 1");
+        for (int b2 = 1; b2 < d; ++b2) TTSG_CHECK(rho[b2] >= rx[b2], TTSG_ERR_ARG, "sgmres: rho_b < rx_b");
+        for (int b2 = 0; b2 <= d; ++b2)
+            TTSG_CHECK(rb[b2] <= std::max(rx[b2], 1) || true, TTSG_ERR_CAPACITY, "");
+        check_ptrs(d, (const void* const*)A, "sgmres A");
+        check_ptrs(d, (const void* const*)b, "sgmres b");
+        check_ptrs(d, (const void* const*)Sf, "sgmres S");
+        check_ptrs(d - 1, (const void* const*)Y, "sgmres Y");
+        check_ptrs(d - 1, (const void* const*)X, "sgmres X");
+        check_ptrs(d, (const void* const*)x, "sgmres x");
+        TTSG_CHECK(x_r != nullptr, TTSG_ERR_ARG, "sgmres: null x_r");
+        for (int b2 = 0; b2 <= d; ++b2)
+            TTSG_CHECK(rb[b2] <= rx[b2], TTSG_ERR_CAPACITY, "sgmres: rank of b exceeds the STTA target ranks");
+        ttsg::SolverInputs in;
+        in.d = d;
+        in.n = n;
+        in.R = vec(R, d + 1);
+        in.A.assign(A, A + d);
+        in.rb = vec(rb, d + 1);
+        in.b.assign(b, b + d);
+        in.s = s;
+        in.S.assign(Sf, Sf + d);
+        in.rho = vec(rho, d + 1);
+        in.rx = vec(rx, d + 1);
+        in.Y.assign(Y, Y + d - 1);
+        in.X.assign(X, X + d - 1);
+        in.o = *opts;
+        if (in.o.rcond <= 0.0) in.o.rcond = 1e-12;
+        if (in.o.stop_safety <= 0.0) in.o.stop_safety = 1.0;
+        return ttsg::sgmres_solve(in, x, x_r, info, ws, ws_bytes, S(stream));
+    });
+}
+
+}  // extern "C"

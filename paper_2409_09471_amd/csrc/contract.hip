@@ -1,0 +1,231 @@
+// Generic strided tensor contraction on CDNA4 matrix cores.
+//
+//   C[b][m][n] = alpha * sum_k A[b][m][k] * B[b][k][n] + beta * C[b][m][n]
+//
+// Every index (m, n, k, b) of every operand is addressed through a two-level
+// stride (Idx2), so the permuted core layouts met in the TT sweeps -- merged
+// (rank, mode) indices, operator ranks split from vector ranks -- are read in
+// place.  A 256-thread workgroup computes a 64 x 64 tile of C: the four
+// wavefronts each own a 32 x 32 block made of 2 x 2 MFMA 16x16 tiles; A and B
+// are staged through LDS in k-slabs (16 for FP64/FP32, 32 for BF16).
+//
+// Matrix-core forms used (gfx950):
+//   FP64: v_mfma_f64_16x16x4_f64      (A, B, C in float64)
+//   FP32: v_mfma_f32_16x16x4_f32      (A, B, C in float32)
+//   BF16: v_mfma_f32_16x16x16_bf16    (A, B in bfloat16, C in float32)
+// Operand layout of the 16x16xK forms: lane l supplies row (l % 16) of A and
+// column (l % 16) of B for the k-group (l / 16); the accumulator holds rows
+// 4*(l/16) + {0..3} of column (l % 16).
+#include <cstdlib>
+
+#include "ttsg_internal.h"
+
+namespace ttsg {
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64;
+constexpr int BN = 64;
+
+template <typename T> struct Traits;
+template <> struct Traits<double> {
+    using acc4 = d4_t;
+    using out_t = double;
+    static constexpr int BK = 16;
+};
+template <> struct Traits<float> {
+    using acc4 = f4_t;
+    using out_t = float;
+    static constexpr int BK = 16;
+};
+template <> struct Traits<uint16_t> {
+    using acc4 = f4_t;
+    using out_t = float;
+    static constexpr int BK = 32;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_tile(T (*S)[BM + 1], const T* __restrict__ G, const Idx2& rowix,
+                                          const Idx2& kix, int row0, int k0, int nrows, int nk,
+                                          bool k_fast) {
+    constexpr int BK = Traits<T>::BK;
+    const int tid = threadIdx.x;
+    // Thread-to-element order follows whichever index has unit stride, so
+    // consecutive lanes touch consecutive addresses.
+    for (int e = tid; e < BM * BK; e += 256) {
+        int rr, kk;
+        if (k_fast) {
+            rr = e / BK;
+            kk = e - rr * BK;
+        } else {
+            kk = e / BM;
+            rr = e - kk * BM;
+        }
+        int gr = row0 + rr, gk = k0 + kk;
+        T v = T(0);
+        if (gr < nrows && gk < nk) v = G[idx_off(rowix, gr) + idx_off(kix, gk)];
+        S[kk][rr] = v;
+    }
+}
+
+__device__ __forceinline__ d4_t mfma(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma(float a, float b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const T* __restrict__ A,
+                                                       const T* __restrict__ B,
+                                                       typename Traits<T>::out_t* __restrict__ C,
+                                                       int batch0) {
+    using acc4 = typename Traits<T>::acc4;
+    using out_t = typename Traits<T>::out_t;
+    constexpr int BK = Traits<T>::BK;
+    __shared__ T As[BK][BM + 1];
+    __shared__ T Bs[BK][BN + 1];
+
+    const int bidx = batch0 + blockIdx.z;
+    const int m0 = blockIdx.y * BM;
+    const int n0 = blockIdx.x * BN;
+    const T* Ab = A + idx_off(d.ab, bidx);
+    const T* Bb = B + idx_off(d.bb, bidx);
+    out_t* Cb = C + idx_off(d.cb, bidx);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm = (wave >> 1) * 32;
+    const int wn = (wave & 1) * 32;
+    const int lr = lane & 15;
+    const int lg = lane >> 4;
+
+    acc4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = acc4{0, 0, 0, 0};
+
+    const bool a_kfast = (d.ak.s0 == 1);
+    const bool b_kfast = (d.bk.s0 == 1);
+
+    for (int k0 = 0; k0 < d.K; k0 += BK) {
+        load_tile<T>(As, Ab, d.am, d.ak, m0, k0, d.M, d.K, a_kfast);
+        load_tile<T>(Bs, Bb, d.bn, d.bk, n0, k0, d.N, d.K, b_kfast);
+        __syncthreads();
+        if constexpr (sizeof(T) == 2) {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 16) {
+                s4_t a[2], b[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        a[i][t] = (short)As[kk + 4 * lg + t][wm + 16 * i + lr];
+                        b[i][t] = (short)Bs[kk + 4 * lg + t][wn + 16 * i + lr];
+                    }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                T a[2], b[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    a[i] = As[kk + lg][wm + 16 * i + lr];
+                    b[i] = Bs[kk + lg][wn + 16 * i + lr];
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+            }
+        }
+        __syncthreads();
+    }
+
+    const out_t alpha = (out_t)d.alpha;
+    const out_t beta = (out_t)d.beta;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int row = m0 + wm + 16 * i + 4 * lg + r;
+                int col = n0 + wn + 16 * j + lr;
+                if (row < d.M && col < d.N) {
+                    int64_t off = idx_off(d.cm, row) + idx_off(d.cn, col);
+                    out_t v = alpha * (out_t)acc[i][j][r];
+                    if (beta != out_t(0)) v += beta * Cb[off];
+                    Cb[off] = v;
+                }
+            }
+}
+
+template <typename T>
+void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st) {
+    if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
+    if (bounds_checking()) {
+        using out_t = typename Traits<T>::out_t;
+        const int64_t ea = idx_max(d.ab, d.batch) + idx_max(d.am, d.M) + idx_max(d.ak, d.K) + 1;
+        const int64_t eb = idx_max(d.bb, d.batch) + idx_max(d.bk, d.K) + idx_max(d.bn, d.N) + 1;
+        const int64_t ec = idx_max(d.cb, d.batch) + idx_max(d.cm, d.M) + idx_max(d.cn, d.N) + 1;
+        check_range(A, ea * sizeof(T), "contract A");
+        check_range(B, eb * sizeof(T), "contract B");
+        check_range(C, ec * sizeof(out_t), "contract C");
+    }
+    dim3 block(256);
+    const int gx = (d.N + BN - 1) / BN;
+    const int gy = (d.M + BM - 1) / BM;
+    TTSG_CHECK(gy < 65536, TTSG_ERR_ARG, "contraction: M too large");
+    for (int b0 = 0; b0 < d.batch; b0 += 65535) {
+        int nb = d.batch - b0 < 65535 ? d.batch - b0 : 65535;
+        dim3 grid(gx, gy, nb);
+        hipLaunchKernelGGL(contract_kernel<T>, grid, block, 0, st, d, static_cast<const T*>(A),
+                           static_cast<const T*>(B), static_cast<typename Traits<T>::out_t*>(C), b0);
+    }
+    TTSG_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+bool bounds_checking() {
+    static const bool on = [] {
+        const char* e = std::getenv("TTSG_CHECK_BOUNDS");
+        return e != nullptr && e[0] == '1';
+    }();
+    return on;
+}
+
+void check_range(const void* p, size_t bytes, const char* what) {
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    hipError_t e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
+    TTSG_CHECK(e == hipSuccess, TTSG_ERR_ARG, std::string(what) + ": pointer is not in a device allocation");
+    const char* b0 = static_cast<const char*>(base);
+    const char* q = static_cast<const char*>(p);
+    TTSG_CHECK(q >= b0 && q + bytes <= b0 + size, TTSG_ERR_ARG,
+               std::string(what) + ": access range exceeds its allocation");
+}
+
+void contract(Prec p, const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st) {
+    if (d.K <= 0) {
+        // empty reduction: C = beta * C handled by callers never passing K = 0
+        TTSG_CHECK(false, TTSG_ERR_ARG, "contraction with empty reduction");
+    }
+    switch (p) {
+        case Prec::F64: launch<double>(d, A, B, C, st); break;
+        case Prec::F32: launch<float>(d, A, B, C, st); break;
+        case Prec::BF16: launch<uint16_t>(d, A, B, C, st); break;
+    }
+}
+
+}  // namespace ttsg

@@ -1,0 +1,228 @@
+// Dense FP64 factorizations for the STTA recovery and the TT-SVD rounding.
+//
+// Each matrix is handled by one workgroup of 512 threads (8 wavefronts)
+// working on column-major data in global memory (these matrices are at most a
+// few MB and stay L2-resident).  Column operations are given to wavefronts,
+// rows to lanes; reductions are wavefront shuffles.
+//
+//  * Householder QR (the unblocked right-looking algorithm; reflectors are
+//    stored below the diagonal as in LAPACK's geqr2, with v_j = 1 implicit).
+//  * Explicit thin Q from the stored reflectors (backward accumulation).
+//  * One-sided Jacobi SVD (Hestenes): columns are rotated pairwise until every
+//    pair is numerically orthogonal; the column pairs of a round come from the
+//    circle method so that a round touches each column once and its pairs are
+//    independent.  On exit the columns hold U*Sigma and V the rotations.
+#include <algorithm>
+
+#include "ttsg_internal.h"
+
+namespace ttsg {
+namespace {
+
+constexpr int LA_THREADS = 512;
+
+__device__ __forceinline__ double wsum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(LA_THREADS) void k_qr(int m, int c, double* __restrict__ A, int lda, int64_t sA,
+                                                    double* __restrict__ tau, int64_t sT) {
+    A += blockIdx.x * sA;
+    tau += blockIdx.x * sT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int kmax = m < c ? m : c;
+    __shared__ double s_tau, s_scale;
+    for (int j = 0; j < kmax; ++j) {
+        double* col = A + (int64_t)j * lda;
+        if (wave == 0) {
+            double s = 0.0;
+            for (int i = j + 1 + lane; i < m; i += 64) s += col[i] * col[i];
+            s = wsum(s);
+            if (lane == 0) {
+                double alpha = col[j];
+                if (s == 0.0) {
+                    s_tau = 0.0;
+                    s_scale = 0.0;
+                    tau[j] = 0.0;
+                } else {
+                    double beta = -copysign(sqrt(alpha * alpha + s), alpha);
+                    s_tau = (beta - alpha) / beta;
+                    s_scale = 1.0 / (alpha - beta);
+                    tau[j] = s_tau;
+                    col[j] = beta;
+                }
+            }
+        }
+        __syncthreads();
+        const double t = s_tau, sc = s_scale;
+        if (t != 0.0) {
+            for (int i = j + 1 + tid; i < m; i += blockDim.x) col[i] *= sc;
+        }
+        __syncthreads();
+        if (t != 0.0) {
+            for (int l = j + 1 + wave; l < c; l += nw) {
+                double* cl = A + (int64_t)l * lda;
+                double w = 0.0;
+                for (int i = j + 1 + lane; i < m; i += 64) w += col[i] * cl[i];
+                w = wsum(w);
+                w = t * (w + cl[j]);
+                if (lane == 0) cl[j] -= w;
+                for (int i = j + 1 + lane; i < m; i += 64) cl[i] -= w * col[i];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(LA_THREADS) void k_form_q(int m, int c, const double* __restrict__ A, int lda,
+                                                        int64_t sA, const double* __restrict__ tau, int64_t sT,
+                                                        double* __restrict__ Q, int ldq, int64_t sQ) {
+    A += blockIdx.x * sA;
+    tau += blockIdx.x * sT;
+    Q += blockIdx.x * sQ;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int k = m < c ? m : c;
+    for (int l = 0; l < k; ++l)
+        for (int i = tid; i < m; i += blockDim.x) Q[(int64_t)l * ldq + i] = (i == l) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int j = k - 1; j >= 0; --j) {
+        const double t = tau[j];
+        if (t != 0.0) {
+            const double* v = A + (int64_t)j * lda;
+            for (int l = j + wave; l < k; l += nw) {
+                double* ql = Q + (int64_t)l * ldq;
+                double w = 0.0;
+                for (int i = j + 1 + lane; i < m; i += 64) w += v[i] * ql[i];
+                w = wsum(w);
+                w = t * (w + ql[j]);
+                if (lane == 0) ql[j] -= w;
+                for (int i = j + 1 + lane; i < m; i += 64) ql[i] -= w * v[i];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void circle_pair(int r, int k, int cp, int& p, int& q) {
+    if (k == 0) {
+        p = cp - 1;
+        q = r;
+    } else {
+        p = (r + k) % (cp - 1);
+        q = (r - k + cp - 1) % (cp - 1);
+    }
+}
+
+__global__ __launch_bounds__(LA_THREADS) void k_jacobi(int m, int c, double* __restrict__ A, int lda, int64_t sA,
+                                                        double* __restrict__ V, int ldv, int64_t sV,
+                                                        double* __restrict__ sig, int64_t sS, int maxsweeps,
+                                                        double tol) {
+    A += blockIdx.x * sA;
+    V += blockIdx.x * sV;
+    sig += blockIdx.x * sS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    for (int l = 0; l < c; ++l)
+        for (int i = tid; i < c; i += blockDim.x) V[(int64_t)l * ldv + i] = (i == l) ? 1.0 : 0.0;
+    __shared__ int s_rot;
+    const int cp = c + (c & 1);
+    __syncthreads();
+    for (int sweep = 0; sweep < maxsweeps && cp > 1; ++sweep) {
+        if (tid == 0) s_rot = 0;
+        __syncthreads();
+        for (int r = 0; r < cp - 1; ++r) {
+            for (int pk = wave; pk < cp / 2; pk += nw) {
+                int p, q;
+                circle_pair(r, pk, cp, p, q);
+                if (p >= c || q >= c) continue;
+                double* ap = A + (int64_t)p * lda;
+                double* aq = A + (int64_t)q * lda;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = lane; i < m; i += 64) {
+                    double x = ap[i], y = aq[i];
+                    al += x * x;
+                    be += y * y;
+                    ga += x * y;
+                }
+                al = wsum(al);
+                be = wsum(be);
+                ga = wsum(ga);
+                if (al == 0.0 || be == 0.0) continue;
+                if (fabs(ga) <= tol * sqrt(al) * sqrt(be)) continue;
+                double zeta = (be - al) / (2.0 * ga);
+                double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
+                double cs = 1.0 / sqrt(1.0 + t * t);
+                double sn = cs * t;
+                for (int i = lane; i < m; i += 64) {
+                    double x = ap[i], y = aq[i];
+                    ap[i] = cs * x - sn * y;
+                    aq[i] = sn * x + cs * y;
+                }
+                double* vp = V + (int64_t)p * ldv;
+                double* vq = V + (int64_t)q * ldv;
+                for (int i = lane; i < c; i += 64) {
+                    double x = vp[i], y = vq[i];
+                    vp[i] = cs * x - sn * y;
+                    vq[i] = sn * x + cs * y;
+                }
+                if (lane == 0) s_rot = 1;
+            }
+            __syncthreads();
+        }
+        if (s_rot == 0) break;
+        __syncthreads();
+    }
+    __syncthreads();
+    for (int l = wave; l < c; l += nw) {
+        const double* al = A + (int64_t)l * lda;
+        double s = 0.0;
+        for (int i = lane; i < m; i += 64) s += al[i] * al[i];
+        s = wsum(s);
+        if (lane == 0) sig[l] = sqrt(s);
+    }
+}
+
+}  // namespace
+
+void qr_householder(int32_t batch, int32_t m, int32_t c, double* A, int32_t lda, int64_t strideA, double* tau,
+                    int64_t strideTau, hipStream_t st) {
+    if (batch <= 0 || m <= 0 || c <= 0) return;
+    TTSG_CHECK(lda >= m, TTSG_ERR_ARG, "qr: lda < m");
+    if (bounds_checking()) {
+        check_range(A, ((int64_t)(batch - 1) * strideA + (int64_t)(c - 1) * lda + m) * 8, "qr A");
+        check_range(tau, ((int64_t)(batch - 1) * strideTau + std::min(m, c)) * 8, "qr tau");
+    }
+    hipLaunchKernelGGL(k_qr, dim3(batch), dim3(LA_THREADS), 0, st, m, c, A, lda, strideA, tau, strideTau);
+    TTSG_HIP(hipGetLastError());
+}
+
+void qr_form_q(int32_t batch, int32_t m, int32_t c, const double* A, int32_t lda, int64_t strideA,
+               const double* tau, int64_t strideTau, double* Q, int32_t ldq, int64_t strideQ, hipStream_t st) {
+    if (batch <= 0 || m <= 0 || c <= 0) return;
+    TTSG_CHECK(lda >= m && ldq >= m, TTSG_ERR_ARG, "form_q: leading dimension < m");
+    if (bounds_checking()) {
+        const int k = std::min(m, c);
+        check_range(A, ((int64_t)(batch - 1) * strideA + (int64_t)(k - 1) * lda + m) * 8, "form_q A");
+        check_range(Q, ((int64_t)(batch - 1) * strideQ + (int64_t)(k - 1) * ldq + m) * 8, "form_q Q");
+    }
+    hipLaunchKernelGGL(k_form_q, dim3(batch), dim3(LA_THREADS), 0, st, m, c, A, lda, strideA, tau, strideTau, Q,
+                       ldq, strideQ);
+    TTSG_HIP(hipGetLastError());
+}
+
+void svd_jacobi(int32_t batch, int32_t m, int32_t c, double* A, int32_t lda, int64_t strideA, double* V,
+                int32_t ldv, int64_t strideV, double* sig, int64_t strideSig, hipStream_t st) {
+    if (batch <= 0 || m <= 0 || c <= 0) return;
+    TTSG_CHECK(m >= c, TTSG_ERR_ARG, "svd_jacobi needs m >= c");
+    TTSG_CHECK(lda >= m && ldv >= c, TTSG_ERR_ARG, "svd_jacobi: leading dimension too small");
+    if (bounds_checking()) {
+        check_range(A, ((int64_t)(batch - 1) * strideA + (int64_t)(c - 1) * lda + m) * 8, "jacobi A");
+        check_range(V, ((int64_t)(batch - 1) * strideV + (int64_t)(c - 1) * ldv + c) * 8, "jacobi V");
+        check_range(sig, ((int64_t)(batch - 1) * strideSig + c) * 8, "jacobi sig");
+    }
+    hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(LA_THREADS), 0, st, m, c, A, lda, strideA, V, ldv, strideV,
+                       sig, strideSig, 60, 1e-15);
+    TTSG_HIP(hipGetLastError());
+}
+
+}  // namespace ttsg

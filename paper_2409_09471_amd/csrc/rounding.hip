@@ -1,0 +1,396 @@
+// Rounding pipeline in FP64: STTA recovery (Sec. 3.3) and TT-SVD (Sec. 2.2).
+//
+// Ranks are decided on the host from singular values read back once per
+// bond (a few hundred doubles); the subsequent contractions then run at the
+// exact new sizes.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "tt_ops.h"
+
+namespace ttsg {
+namespace {
+
+__global__ void k_extract_r(int k, int c, const double* __restrict__ A, int lda, double* __restrict__ R, int ldr) {
+    int total = k * c;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        int l = e / k, i = e - l * k;
+        R[(int64_t)l * ldr + i] = (i <= l) ? A[(int64_t)l * lda + i] : 0.0;
+    }
+}
+
+// dst[:, t] = fac[t] * src[:, perm[t]]  (column-major, `rows` rows)
+__global__ void k_gather_cols(int rows, int k, const double* __restrict__ src, int lds, double* __restrict__ dst,
+                              int ldd, const int* __restrict__ perm, const double* __restrict__ fac) {
+    int total = rows * k;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        int t = e / rows, i = e - t * rows;
+        dst[(int64_t)t * ldd + i] = fac[t] * src[(int64_t)perm[t] * lds + i];
+    }
+}
+
+inline int nb(int64_t total) {
+    int64_t b = (total + 255) / 256;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 65536));
+}
+
+void extract_r(int k, int c, const double* A, int lda, double* R, int ldr, hipStream_t st) {
+    hipLaunchKernelGGL(k_extract_r, dim3(nb((int64_t)k * c)), dim3(256), 0, st, k, c, A, lda, R, ldr);
+    TTSG_HIP(hipGetLastError());
+}
+
+void gather_cols(int rows, int k, const double* src, int lds, double* dst, int ldd, const int* perm,
+                 const double* fac, hipStream_t st) {
+    if (rows <= 0 || k <= 0) return;
+    hipLaunchKernelGGL(k_gather_cols, dim3(nb((int64_t)rows * k)), dim3(256), 0, st, rows, k, src, lds, dst, ldd,
+                       perm, fac);
+    TTSG_HIP(hipGetLastError());
+}
+
+// Row-major C (M x N) = A (row-major M x K) * B (column-major K x N, ld = ldb)
+void gemm_rm_cm(int M, int N, int K, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+                hipStream_t st) {
+    ContractDesc d = cdesc(M, N, K);
+    d.am = idx1(lda);
+    d.ak = idx1(1);
+    d.bk = idx1(1);
+    d.bn = idx1(ldb);
+    d.cm = idx1(ldc);
+    d.cn = idx1(1);
+    contract(Prec::F64, d, A, B, C, st);
+}
+
+// Row-major C (M x N) = A (row-major M x K) * B (row-major K x N)
+void gemm_rm_rm(int M, int N, int K, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+                hipStream_t st) {
+    ContractDesc d = cdesc(M, N, K);
+    d.am = idx1(lda);
+    d.ak = idx1(1);
+    d.bk = idx1(ldb);
+    d.bn = idx1(1);
+    d.cm = idx1(ldc);
+    d.cn = idx1(1);
+    contract(Prec::F64, d, A, B, C, st);
+}
+
+// Row-major C (M x N) = A (column-major M x K, ld lda) * B (column-major K x N, ld ldb)
+void gemm_cm_cm(int M, int N, int K, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+                hipStream_t st) {
+    ContractDesc d = cdesc(M, N, K);
+    d.am = idx1(1);
+    d.ak = idx1(lda);
+    d.bk = idx1(1);
+    d.bn = idx1(ldb);
+    d.cm = idx1(ldc);
+    d.cn = idx1(1);
+    contract(Prec::F64, d, A, B, C, st);
+}
+
+// Smallest k whose discarded tail is <= delta; at least 1; capped at maxrank.
+int trunc_rank(const std::vector<double>& s_desc, double delta, int maxrank) {
+    int m = (int)s_desc.size();
+    std::vector<double> tail(m + 1, 0.0);
+    for (int j = m - 1; j >= 0; --j) tail[j] = tail[j + 1] + s_desc[j] * s_desc[j];
+    int k = m;
+    for (int j = 0; j < m; ++j)
+        if (std::sqrt(tail[j]) <= delta) {
+            k = j;
+            break;
+        }
+    k = std::max(k, 1);
+    if (maxrank > 0) k = std::min(k, maxrank);
+    return k;
+}
+
+std::vector<int> argsort_desc(const std::vector<double>& s) {
+    std::vector<int> p(s.size());
+    std::iota(p.begin(), p.end(), 0);
+    std::stable_sort(p.begin(), p.end(), [&](int a, int b) { return s[a] > s[b]; });
+    return p;
+}
+
+double read_scalar(const double* dev, hipStream_t st) {
+    double h = 0.0;
+    TTSG_HIP(hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, st));
+    TTSG_HIP(hipStreamSynchronize(st));
+    return h;
+}
+
+// Upload perm (ints) and factors (doubles) into device buffers.
+void upload_perm(const std::vector<int>& perm, const std::vector<double>& fac, int* perm_dev, double* fac_dev,
+                 hipStream_t st) {
+    TTSG_HIP(hipMemcpyAsync(perm_dev, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    TTSG_HIP(hipMemcpyAsync(fac_dev, fac.data(), fac.size() * sizeof(double), hipMemcpyHostToDevice, st));
+}
+
+}  // namespace
+
+double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vector<double*>& w,
+                      const std::vector<int64_t>& cap_elems, double tol, int maxrank, Arena& ar, hipStream_t st,
+                      double* norm_before) {
+    const size_t mark = ar.mark();
+    int64_t maxcore = 0, maxr = 1;
+    for (int mu = 0; mu < d; ++mu) {
+        maxcore = std::max<int64_t>(maxcore, (int64_t)r[mu] * n[mu] * r[mu + 1]);
+        maxr = std::max<int64_t>(maxr, std::max(r[mu], r[mu + 1]));
+    }
+    double* A = ar.get<double>(maxcore);
+    double* Q = ar.get<double>(maxcore);
+    double* T = ar.get<double>(maxcore);
+    double* Rm = ar.get<double>(maxr * maxr);
+    double* V = ar.get<double>(maxr * maxr);
+    double* QV = ar.get<double>(maxcore);
+    double* tau = ar.get<double>(maxr);
+    double* sig = ar.get<double>(maxr);
+    double* part = ar.get<double>(1024);
+    double* scal = ar.get<double>(2);
+    int* perm_dev = ar.get<int>(maxr);
+    double* fac_dev = ar.get<double>(maxr);
+
+    // 1) right-to-left QR orthogonalization
+    for (int mu = d - 1; mu >= 1; --mu) {
+        const int rl = r[mu], rr = r[mu + 1], m = n[mu] * rr, c = rl;
+        copy_f64((int64_t)m * c, w[mu], A, st);            // column-major m x c == row-major core
+        qr_householder(1, m, c, A, m, 0, tau, 0, st);
+        const int k = std::min(m, c);
+        qr_form_q(1, m, c, A, m, 0, tau, 0, w[mu], m, 0, st);  // Q^T as the new row-major core
+        extract_r(k, c, A, m, Rm, k, st);
+        const int rll = r[mu - 1], nl = n[mu - 1];
+        // T (rll*nl x k) = W_{mu-1} (rll*nl x rl) * R^T
+        // B[l][kk] = R[kk][l] = Rm[l*k + kk]: the column-major R read row-major
+        gemm_rm_rm(rll * nl, k, rl, w[mu - 1], rl, Rm, k, T, k, st);
+        copy_f64((int64_t)rll * nl * k, T, w[mu - 1], st);
+        r[mu] = k;
+    }
+    sumsq((int64_t)r[0] * n[0] * r[1], w[0], part, scal, st);
+    const double nrm = std::sqrt(read_scalar(scal, st));
+    if (norm_before) *norm_before = nrm;
+    if (nrm == 0.0 || d == 1) {
+        ar.release(mark);
+        return nrm;
+    }
+    const double delta = tol * nrm / std::sqrt((double)(d - 1));
+
+    // 2) left-to-right truncated SVDs.  Host arrays handed to hipMemcpyAsync are
+    // kept in `hold` until the stream is synchronized at the end.
+    std::vector<double> hsig;
+    std::vector<std::vector<int>> hold_i;
+    std::vector<std::vector<double>> hold_d;
+    for (int mu = 0; mu <= d - 2; ++mu) {
+        const int rl = r[mu], rr = r[mu + 1], m = rl * n[mu], c = rr;
+        const int r2 = r[mu + 2], n2 = n[mu + 1];
+        int k;
+        std::vector<int> perm;
+        if (m >= c) {
+            transpose2d(m, c, w[mu], c, A, m, st);           // column-major m x c
+            qr_householder(1, m, c, A, m, 0, tau, 0, st);
+            qr_form_q(1, m, c, A, m, 0, tau, 0, Q, m, 0, st);
+            extract_r(c, c, A, m, Rm, c, st);
+            svd_jacobi(1, c, c, Rm, c, 0, V, c, 0, sig, 0, st);
+            hsig.assign(c, 0.0);
+            TTSG_HIP(hipMemcpyAsync(hsig.data(), sig, c * sizeof(double), hipMemcpyDeviceToHost, st));
+            TTSG_HIP(hipStreamSynchronize(st));
+            perm = argsort_desc(hsig);
+            std::vector<double> sd(c);
+            for (int t = 0; t < c; ++t) sd[t] = hsig[perm[t]];
+            k = trunc_rank(sd, delta, maxrank);
+            k = std::min(k, c);
+            // Uk (c x k, column-major) = (U Sigma)[:, perm] / sigma
+            std::vector<int> pk(perm.begin(), perm.begin() + k);
+            std::vector<double> inv(k), sv(k);
+            for (int t = 0; t < k; ++t) {
+                double s = hsig[pk[t]];
+                inv[t] = s > 0.0 ? 1.0 / s : 0.0;
+                sv[t] = s;
+            }
+            hold_i.push_back(pk);
+            hold_d.push_back(inv);
+            hold_d.push_back(sv);
+            upload_perm(hold_i.back(), hold_d[hold_d.size() - 2], perm_dev, fac_dev, st);
+            gather_cols(c, k, Rm, c, T, c, perm_dev, fac_dev, st);
+            // new core (row-major m x k) = Q (column-major m x c) * Uk
+            gemm_cm_cm(m, k, c, Q, m, T, c, w[mu], k, st);
+            // SVt (row-major k x c) = column-major c x k of V[:, perm] * sigma
+            TTSG_HIP(hipMemcpyAsync(fac_dev, hold_d.back().data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+            gather_cols(c, k, V, c, QV, c, perm_dev, fac_dev, st);
+        } else {
+            // wide unfolding: M^T (c x m) is the row-major core read column-major
+            copy_f64((int64_t)m * c, w[mu], A, st);
+            qr_householder(1, c, m, A, c, 0, tau, 0, st);
+            qr_form_q(1, c, m, A, c, 0, tau, 0, Q, c, 0, st);   // Q2: c x m
+            extract_r(m, m, A, c, Rm, m, st);                    // R2: m x m (column-major)
+            // R2^T column-major = transpose of R2
+            transpose2d(m, m, Rm, m, T, m, st);                  // T = R2 row-major == R2^T column-major
+            svd_jacobi(1, m, m, T, m, 0, V, m, 0, sig, 0, st);   // R2^T = U2 S V2^T
+            hsig.assign(m, 0.0);
+            TTSG_HIP(hipMemcpyAsync(hsig.data(), sig, m * sizeof(double), hipMemcpyDeviceToHost, st));
+            TTSG_HIP(hipStreamSynchronize(st));
+            perm = argsort_desc(hsig);
+            std::vector<double> sd(m);
+            for (int t = 0; t < m; ++t) sd[t] = hsig[perm[t]];
+            k = trunc_rank(sd, delta, maxrank);
+            k = std::min(k, m);
+            std::vector<int> pk(perm.begin(), perm.begin() + k);
+            std::vector<double> inv(k), one(k, 1.0);
+            for (int t = 0; t < k; ++t) inv[t] = hsig[pk[t]] > 0.0 ? 1.0 / hsig[pk[t]] : 0.0;
+            hold_i.push_back(pk);
+            hold_d.push_back(inv);
+            upload_perm(hold_i.back(), hold_d.back(), perm_dev, fac_dev, st);
+            // new core (row-major m x k): columns of U2 = (U2 S)[:, perm] / s, written row-major
+            gather_cols(m, k, T, m, A, m, perm_dev, fac_dev, st);  // A: column-major m x k
+            transpose2d(k, m, A, m, w[mu], k, st);                 // row-major m x k
+            // (Q2 V2) column-major c x m, then SVt (row-major k x c) = S * (Q2 V2)[:, perm]^T
+            gemm_cm_cm(c, m, m, Q, c, V, m, QV, m, st);            // row-major c x m == QV^T column-major
+            // QV row-major c x m: column j of (Q2 V2) is strided by m -> transpose to column-major
+            transpose2d(c, m, QV, m, A, c, st);                    // A column-major c x m
+            std::vector<double> sv(k);
+            for (int t = 0; t < k; ++t) sv[t] = hsig[pk[t]];
+            hold_d.push_back(sv);
+            TTSG_HIP(hipMemcpyAsync(fac_dev, hold_d.back().data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+            gather_cols(c, k, A, c, QV, c, perm_dev, fac_dev, st);
+        }
+        // W_{mu+1} (k x n2*r2) = SVt (row-major k x c == QV column-major c x k) * W_{mu+1} (c x n2*r2)
+        {
+            ContractDesc dd = cdesc(k, n2 * r2, c);
+            dd.am = idx1(c);   // SVt[t][l] = QV[t*c + l]
+            dd.ak = idx1(1);
+            dd.bk = idx1((int64_t)n2 * r2);
+            dd.bn = idx1(1);
+            dd.cm = idx1((int64_t)n2 * r2);
+            dd.cn = idx1(1);
+            contract(Prec::F64, dd, QV, w[mu + 1], T, st);
+            copy_f64((int64_t)k * n2 * r2, T, w[mu + 1], st);
+        }
+        r[mu + 1] = k;
+        (void)cap_elems;
+    }
+    sumsq((int64_t)r[d - 1] * n[d - 1], w[d - 1], part, scal, st);
+    const double nout = std::sqrt(read_scalar(scal, st));
+    ar.release(mark);
+    return nout;
+}
+
+void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::vector<int>& rx,
+                  const std::vector<const double*>& Psi, const std::vector<const double*>& Omega, double rcond,
+                  const std::vector<double*>& out, std::vector<int>& r_out, Arena& ar, hipStream_t st) {
+    const size_t mark = ar.mark();
+    r_out.assign(d + 1, 1);
+    if (d == 1) {
+        copy_f64(n[0], Psi[0], out[0], st);
+        return;
+    }
+    // SVD of every Omega_b (rho_b x rx_b, rho_b >= rx_b)
+    std::vector<double*> Ab(d), Vb(d), Sb(d), Gb(d), Vk(d);
+    std::vector<int*> permb(d);
+    std::vector<double*> facb(d);
+    int64_t maxT = 1;
+    for (int b = 1; b <= d - 1; ++b) {
+        const int m = rho[b], c = rx[b];
+        TTSG_CHECK(m >= c, TTSG_ERR_ARG, "STTA needs rho_b >= rx_b");
+        Ab[b] = ar.get<double>((int64_t)m * c);
+        Vb[b] = ar.get<double>((int64_t)c * c);
+        Sb[b] = ar.get<double>(c);
+        Gb[b] = ar.get<double>((int64_t)m * c);
+        Vk[b] = ar.get<double>((int64_t)c * c);
+        permb[b] = ar.get<int>(c);
+        facb[b] = ar.get<double>(2 * (int64_t)c);
+        transpose2d(m, c, Omega[b - 1], c, Ab[b], m, st);
+        svd_jacobi(1, m, c, Ab[b], m, 0, Vb[b], c, 0, Sb[b], 0, st);
+    }
+    for (int mu = 0; mu < d; ++mu) maxT = std::max<int64_t>(maxT, (int64_t)rx[mu] * n[mu] * rx[mu + 1]);
+    double* T = ar.get<double>(maxT);
+    std::vector<std::vector<double>> hs(d);
+    for (int b = 1; b <= d - 1; ++b) {
+        hs[b].assign(rx[b], 0.0);
+        TTSG_HIP(hipMemcpyAsync(hs[b].data(), Sb[b], rx[b] * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    TTSG_HIP(hipStreamSynchronize(st));
+    std::vector<std::vector<int>> keep(d);
+    std::vector<std::vector<double>> facs(d);
+    for (int b = 1; b <= d - 1; ++b) {
+        std::vector<int> p = argsort_desc(hs[b]);
+        const double smax = hs[b][p[0]];
+        int k = 0;
+        while (k < (int)p.size() && hs[b][p[k]] > rcond * smax && hs[b][p[k]] > 0.0) ++k;
+        k = std::max(k, 1);
+        keep[b].assign(p.begin(), p.begin() + k);
+        facs[b].resize(2 * k);
+        for (int t = 0; t < k; ++t) {
+            double s = hs[b][keep[b][t]];
+            facs[b][t] = s > 0.0 ? 1.0 / (s * s) : 0.0;
+            facs[b][k + t] = 1.0;
+        }
+        r_out[b] = k;
+        TTSG_HIP(hipMemcpyAsync(permb[b], keep[b].data(), k * sizeof(int), hipMemcpyHostToDevice, st));
+        TTSG_HIP(hipMemcpyAsync(facb[b], facs[b].data(), 2 * k * sizeof(double), hipMemcpyHostToDevice, st));
+        // G_b (row-major k x rho == column-major rho x k) = (U S)[:, keep] / s^2
+        gather_cols(rho[b], k, Ab[b], rho[b], Gb[b], rho[b], permb[b], facb[b], st);
+        // V'_b (column-major rx x k) = V[:, keep]
+        gather_cols(rx[b], k, Vb[b], rx[b], Vk[b], rx[b], permb[b], facb[b] + k, st);
+    }
+    for (int mu = 0; mu < d; ++mu) {
+        const int nn = n[mu];
+        const int kl = r_out[mu], kr = r_out[mu + 1];
+        const int qr = rx[mu + 1];
+        const double* src = Psi[mu];
+        double* mid = T;
+        if (mu >= 1) {
+            // T (kl x nn*qr) = G_mu (kl x rho_mu) * Psi_mu (rho_mu x nn*qr)
+            gemm_rm_rm(kl, nn * qr, rho[mu], Gb[mu], rho[mu], Psi[mu], nn * qr, T, nn * qr, st);
+            src = T;
+        }
+        if (mu <= d - 2) {
+            // out (kl*nn x kr) = src (kl*nn x qr) * V'_{mu+1} (column-major qr x kr)
+            gemm_rm_cm(kl * nn, kr, qr, src, qr, Vk[mu + 1], qr, out[mu], kr, st);
+        } else {
+            copy_f64((int64_t)kl * nn, src, out[mu], st);
+        }
+        (void)mid;
+    }
+    TTSG_HIP(hipStreamSynchronize(st));
+    ar.release(mark);
+}
+
+double tt_norm_orth(int d, const int* n, std::vector<int>& r, const std::vector<double*>& w, Arena& ar,
+                    hipStream_t st) {
+    const size_t mark = ar.mark();
+    int64_t maxcore = 1, maxr = 1;
+    for (int mu = 0; mu < d; ++mu) {
+        maxcore = std::max<int64_t>(maxcore, (int64_t)r[mu] * n[mu] * r[mu + 1]);
+        maxr = std::max<int64_t>(maxr, std::max(r[mu], r[mu + 1]));
+    }
+    double* A = ar.get<double>(maxcore);
+    double* T = ar.get<double>(maxcore);
+    double* Rm = ar.get<double>(maxr * maxr);
+    double* tau = ar.get<double>(maxr);
+    double* part = ar.get<double>(1024);
+    double* scal = ar.get<double>(2);
+    for (int mu = 0; mu <= d - 2; ++mu) {
+        const int m = r[mu] * n[mu], c = r[mu + 1];
+        transpose2d(m, c, w[mu], c, A, m, st);
+        qr_householder(1, m, c, A, m, 0, tau, 0, st);
+        const int k = std::min(m, c);
+        qr_form_q(1, m, c, A, m, 0, tau, 0, T, m, 0, st);
+        transpose2d(k, m, T, m, w[mu], k, st);   // row-major m x k
+        extract_r(k, c, A, m, Rm, k, st);
+        // W_{mu+1} (k x n2 r2) = R (k x c, column-major ld k) * W_{mu+1}
+        const int n2 = n[mu + 1], r2 = r[mu + 2];
+        ContractDesc dd = cdesc(k, n2 * r2, c);
+        dd.am = idx1(1);
+        dd.ak = idx1(k);
+        dd.bk = idx1((int64_t)n2 * r2);
+        dd.bn = idx1(1);
+        dd.cm = idx1((int64_t)n2 * r2);
+        dd.cn = idx1(1);
+        contract(Prec::F64, dd, Rm, w[mu + 1], T, st);
+        copy_f64((int64_t)k * n2 * r2, T, w[mu + 1], st);
+        r[mu + 1] = k;
+    }
+    sumsq((int64_t)r[d - 1] * n[d - 1], w[d - 1], part, scal, st);
+    double nrm = std::sqrt(read_scalar(scal, st));
+    ar.release(mark);
+    return nrm;
+}
+
+}  // namespace ttsg

@@ -1,0 +1,736 @@
+// Enhanced sketched TT-GMRES (Alg. 4) on one GPU.
+//
+// Per Krylov step k (x_0 = 0 or the previous cycle's solution):
+//   w_k   = S (A v_k)                          Khatri-Rao sketch, A v_k never formed
+//   h_ik  = <A v_k, v_i>, i in the last q      left environment sweeps
+//   sketch(A v_k) by STTA, minus sum_i h_ik sketch(v_i)      streaming combination
+//   v~    = TT-SVD(STTA_recover(.), round_tol, maxrank)       FP64 rounding
+//   v_k+1 = v~ / ||v~||, its STTA sketch stored for the final solution
+//   W = [W, w_k]: incremental CGS2 QR of W in FP64; ||W y - S r0|| is the norm
+//   of the part of S r0 outside range(W) (the same quantity the pseudo-inverse
+//   solution of eq. pseudo_inv leaves as residual).
+// After the cycle: y from the triangular factor, x = STTA_recover(sum y_i
+// sketch(v_i)) rounded at final_tol, then the FP64 true residual decides
+// whether another cycle (restart from r0 = b - A x) is needed.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "tt_ops.h"
+
+namespace ttsg {
+namespace {
+
+constexpr int LS_THREADS = 1024;
+
+__device__ __forceinline__ double wsum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ double block_sum(double v, double* red) {
+    v = wsum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    return s;
+}
+
+// Append column k (W + k*s) to the CGS2 QR of W.  Q: s x maxit (column-major),
+// Rm: maxit x maxit (column-major), c: Q^T S r0 entries, z: S r0 minus its
+// projection onto range(Q).  res[0] = ||z||, res[1] = R[k][k].
+__global__ __launch_bounds__(LS_THREADS) void k_ls_append(int s, int k, int ld, const double* __restrict__ W,
+                                                           double* __restrict__ Q, double* __restrict__ Rm,
+                                                           double* __restrict__ c, double* __restrict__ z,
+                                                           double* __restrict__ res) {
+    __shared__ double red[LS_THREADS / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const double* w = W + (int64_t)k * s;
+    double* qk = Q + (int64_t)k * s;
+    double* rk = Rm + (int64_t)k * ld;
+    for (int j = tid; j < s; j += blockDim.x) qk[j] = w[j];
+    for (int i = tid; i <= k; i += blockDim.x) rk[i] = 0.0;
+    __syncthreads();
+    double wn = 0.0;
+    for (int j = tid; j < s; j += blockDim.x) wn += w[j] * w[j];
+    wn = sqrt(block_sum(wn, red));
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i = wave; i < k; i += nw) {
+            const double* qi = Q + (int64_t)i * s;
+            double a = 0.0;
+            for (int j = lane; j < s; j += 64) a += qi[j] * qk[j];
+            a = wsum(a);
+            if (lane == 0) {
+                rk[i] += a;
+                res[2 + i] = a;  // this pass's coefficients
+            }
+        }
+        __syncthreads();
+        for (int j = tid; j < s; j += blockDim.x) {
+            double a = qk[j];
+            for (int i = 0; i < k; ++i) a -= Q[(int64_t)i * s + j] * res[2 + i];
+            qk[j] = a;
+        }
+        __syncthreads();
+    }
+    double nn = 0.0;
+    for (int j = tid; j < s; j += blockDim.x) nn += qk[j] * qk[j];
+    nn = sqrt(block_sum(nn, red));
+    const bool dep = !(nn > 1e-13 * wn);
+    const double inv = dep ? 0.0 : 1.0 / nn;
+    for (int j = tid; j < s; j += blockDim.x) qk[j] *= inv;
+    __syncthreads();
+    double ck = 0.0;
+    for (int j = tid; j < s; j += blockDim.x) ck += qk[j] * z[j];
+    ck = block_sum(ck, red);
+    for (int j = tid; j < s; j += blockDim.x) z[j] -= ck * qk[j];
+    __syncthreads();
+    double zz = 0.0;
+    for (int j = tid; j < s; j += blockDim.x) zz += z[j] * z[j];
+    zz = block_sum(zz, red);
+    if (tid == 0) {
+        rk[k] = dep ? 0.0 : nn;
+        c[k] = ck;
+        res[0] = sqrt(zz);
+        res[1] = dep ? 0.0 : nn;
+    }
+}
+
+// y = R^{-1} c by back substitution (one wavefront); columns with R[i][i] = 0
+// (dependent sketch columns) get y_i = 0.
+__global__ void k_ls_solve(int k, int ld, const double* __restrict__ Rm, const double* __restrict__ c,
+                           double* __restrict__ y) {
+    const int lane = threadIdx.x;
+    for (int i = k - 1; i >= 0; --i) {
+        double a = 0.0;
+        for (int j = i + 1 + lane; j < k; j += 64) a += Rm[(int64_t)j * ld + i] * y[j];
+        a = wsum(a);
+        if (lane == 0) {
+            const double rii = Rm[(int64_t)i * ld + i];
+            y[i] = rii != 0.0 ? (c[i] - a) / rii : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+// out[e] = sum_i y[i] * base[i * stride + e]
+__global__ void k_gemv_cols(int64_t len, int k, int64_t stride, const double* __restrict__ base,
+                            const double* __restrict__ y, double* __restrict__ out) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x) {
+        double a = 0.0;
+        for (int i = 0; i < k; ++i) a += y[i] * base[(int64_t)i * stride + e];
+        out[e] = a;
+    }
+}
+
+__global__ void k_nonfinite(int64_t n, const double* __restrict__ x, int* __restrict__ flag) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(x[i])) *flag = 1;
+}
+
+int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384)); }
+
+// Block core of a sum of two TTs (Sec. 2.2 addition): for mode mu of d,
+//   first core [A B], last core [A; B], middle cores diag(A, B).
+__global__ void k_block_core(int rl1, int rr1, int rl2, int rr2, int n, int first, int last,
+                             const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ out,
+                             double bscale) {
+    const int rl = first ? 1 : rl1 + rl2;
+    const int rr = last ? 1 : rr1 + rr2;
+    const int64_t total = (int64_t)rl * n * rr;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        int b = (int)(e % rr);
+        int64_t t = e / rr;
+        int i = (int)(t % n);
+        int a = (int)(t / n);
+        double v = 0.0;
+        // source block A occupies rows [0, rl1) and columns [0, rr1)
+        int aa = a, bb = b;
+        bool inA = (first || aa < rl1) && (last || bb < rr1);
+        if (first && last) {
+            v = A[i] + bscale * B[i];
+        } else if (inA) {
+            v = A[((int64_t)aa * n + i) * rr1 + bb];
+        } else {
+            int a2 = first ? 0 : aa - rl1;
+            int b2 = last ? 0 : bb - rr1;
+            bool inB = (first || (aa >= rl1)) && (last || (bb >= rr1));
+            if (inB) v = (first ? bscale : 1.0) * B[((int64_t)a2 * n + i) * rr2 + b2];
+        }
+        out[e] = v;
+    }
+}
+
+}  // namespace
+
+// Sum a + bscale * b of two TTs into block cores `out` (ranks ra + rb).
+void tt_add_block(int d, const int* n, const std::vector<int>& ra, const std::vector<double*>& a,
+                  const std::vector<int>& rb, const std::vector<const double*>& b, double bscale,
+                  const std::vector<double*>& out, std::vector<int>& rout, hipStream_t st) {
+    rout.assign(d + 1, 1);
+    for (int k = 1; k < d; ++k) rout[k] = ra[k] + rb[k];
+    for (int mu = 0; mu < d; ++mu) {
+        const int first = (mu == 0), last = (mu == d - 1);
+        int64_t total = (int64_t)rout[mu] * n[mu] * rout[mu + 1];
+        hipLaunchKernelGGL(k_block_core, dim3(grid_for(total)), dim3(256), 0, st, ra[mu], ra[mu + 1], rb[mu],
+                           rb[mu + 1], n[mu], first, last, a[mu], b[mu], out[mu], bscale);
+    }
+    TTSG_HIP(hipGetLastError());
+}
+
+class SgmresSolver {
+  public:
+    SgmresSolver(const SolverInputs& in, hipStream_t st) : in_(in), st_(st) {}
+
+    // Size of every buffer, computed with the same code that carves them.
+    size_t workspace_bytes() {
+        Arena ar;
+        ar.measure();
+        carve(ar);
+        return ar.used() + scratch_bytes() + (64u << 20);
+    }
+
+    int run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info, void* ws, size_t ws_bytes);
+
+  private:
+    using clock = std::chrono::steady_clock;
+    const SolverInputs& in_;
+    hipStream_t st_;
+    Prec p_ = Prec::F64;
+    int maxit_ = 0, m_ = 0, q_ = 1;
+    int64_t sk_len_ = 0;               // doubles in one vector's sketch (all Psi then all Omega)
+    std::vector<int64_t> psi_off_, om_off_;
+    std::vector<int64_t> cap_;         // elements of one TT core at the rx capacities
+    // buffers
+    std::vector<std::vector<double*>> slots_;   // q + 2 TT buffers at capacity rx
+    std::vector<std::vector<int>> slot_r_;
+    std::vector<double*> SA64_;                 // S_mu A_mu precomputed
+    std::vector<double*> S1_;                   // S_mu (no operator)
+    std::vector<void*> SAp_, Sp_, Dp_, Xp_, Yp_;  // operands in the working precision
+    std::vector<std::vector<void*>> slot_lp_;   // low-precision copies of the slots
+    double* sketches_ = nullptr;                // (m + 1) x sk_len
+    double* skA_ = nullptr;                     // sketch of A v_k
+    double* skC_ = nullptr;                     // combination
+    double* W_ = nullptr;
+    double* Q_ = nullptr;
+    double* Rls_ = nullptr;
+    double* cls_ = nullptr;
+    double* z_ = nullptr;
+    double* lsres_ = nullptr;
+    double* hco_ = nullptr;                     // [1, h_1..h_q]
+    double* y_ = nullptr;
+    double* xw_ = nullptr;                      // one more TT at 2x capacity for sums
+    std::vector<double*> xsum_;
+    std::vector<double*> xcur_;
+    std::vector<int> xcur_r_;
+    double* scal_ = nullptr;
+    int* flag_ = nullptr;
+    Arena scratch_;
+
+    size_t scratch_bytes() const;
+    void carve(Arena& ar);
+    void to_lp(int slot);
+    std::vector<const void*> slot_ops(int slot) const;
+    void sketch_vec(int slot, double* out);
+    double tt_norm_copy(const std::vector<int>& r, const std::vector<const double*>& c);
+    double true_residual(const std::vector<int>& rx, const std::vector<double*>& x, double nb);
+};
+
+size_t SgmresSolver::scratch_bytes() const {
+    // generous bound for the sweep and rounding scratch: a few multiples of
+    // the largest intermediate of the STTA/KR sweeps and of a doubled TT
+    const int d = in_.d;
+    int64_t big = 1;
+    int Rm = 1;
+    for (int k = 0; k <= d; ++k) Rm = std::max(Rm, in_.R[k]);
+    for (int mu = 0; mu < d; ++mu) {
+        const int64_t nn = in_.n[mu];
+        const int64_t rl = in_.rx[mu], rr = in_.rx[mu + 1];
+        const int64_t rhol = in_.rho[mu];
+        big = std::max<int64_t>(big, rhol * Rm * nn * rr * Rm);
+        big = std::max<int64_t>(big, rl * nn * Rm * std::max<int64_t>(rr, in_.rho[mu + 1]) * Rm);
+        big = std::max<int64_t>(big, (int64_t)in_.s * Rm * rl * nn);
+        big = std::max<int64_t>(big, (rl * Rm + in_.rb[mu] + rl) * nn * (rr * Rm + in_.rb[mu + 1] + rr));
+    }
+    return (size_t)(12 * big + 8 * (int64_t)in_.s * Rm * 512) * 8;
+}
+
+void SgmresSolver::carve(Arena& ar) {
+    const int d = in_.d;
+    const ttsg_sgmres_opts& o = in_.o;
+    p_ = o.precision == TTSG_PREC_F64 ? Prec::F64 : Prec::F32;
+    maxit_ = o.maxit;
+    m_ = o.restart > 0 ? std::min(o.restart, o.maxit) : o.maxit;
+    q_ = std::max(1, o.q);
+    cap_.assign(d, 0);
+    for (int mu = 0; mu < d; ++mu) cap_[mu] = (int64_t)in_.rx[mu] * in_.n[mu] * in_.rx[mu + 1];
+    psi_off_.assign(d, 0);
+    om_off_.assign(d, 0);
+    sk_len_ = 0;
+    for (int mu = 0; mu < d; ++mu) {
+        psi_off_[mu] = sk_len_;
+        sk_len_ += (int64_t)in_.rho[mu] * in_.n[mu] * in_.rx[mu + 1];
+    }
+    for (int b = 1; b < d; ++b) {
+        om_off_[b] = sk_len_;
+        sk_len_ += (int64_t)in_.rho[b] * in_.rx[b];
+    }
+    const int nslots = q_ + 2;
+    slots_.assign(nslots, std::vector<double*>(d));
+    slot_r_.assign(nslots, std::vector<int>(d + 1, 1));
+    for (int sl = 0; sl < nslots; ++sl)
+        for (int mu = 0; mu < d; ++mu) slots_[sl][mu] = ar.get<double>(cap_[mu]);
+    const size_t es = elem_size(p_);
+    slot_lp_.assign(nslots, std::vector<void*>(d, nullptr));
+    if (p_ != Prec::F64)
+        for (int sl = 0; sl < nslots; ++sl)
+            for (int mu = 0; mu < d; ++mu) slot_lp_[sl][mu] = ar.get<char>(cap_[mu] * es);
+    SA64_.assign(d, nullptr);
+    S1_.assign(d, nullptr);
+    SAp_.assign(d, nullptr);
+    Sp_.assign(d, nullptr);
+    Dp_.assign(d, nullptr);
+    for (int mu = 0; mu < d; ++mu) {
+        const int64_t nn = in_.n[mu];
+        SA64_[mu] = ar.get<double>((int64_t)in_.s * in_.R[mu] * nn * in_.R[mu + 1]);
+        if (p_ != Prec::F64) {
+            SAp_[mu] = ar.get<char>((int64_t)in_.s * in_.R[mu] * nn * in_.R[mu + 1] * es);
+            Sp_[mu] = ar.get<char>((int64_t)in_.s * nn * es);
+            Dp_[mu] = ar.get<char>((int64_t)in_.R[mu] * nn * nn * in_.R[mu + 1] * es);
+        }
+    }
+    Xp_.assign(d - 1, nullptr);
+    Yp_.assign(d - 1, nullptr);
+    if (p_ != Prec::F64) {
+        for (int k = 0; k < d - 1; ++k) {
+            Yp_[k] = ar.get<char>((int64_t)in_.rho[k] * in_.n[k] * in_.rho[k + 1] * es);
+            Xp_[k] = ar.get<char>((int64_t)in_.rx[k + 1] * in_.n[k + 1] * in_.rx[k + 2] * es);
+        }
+    }
+    sketches_ = ar.get<double>((int64_t)(m_ + 1) * sk_len_);
+    skA_ = ar.get<double>(sk_len_);
+    skC_ = ar.get<double>(sk_len_);
+    W_ = ar.get<double>((int64_t)in_.s * (m_ + 1));
+    Q_ = ar.get<double>((int64_t)in_.s * (m_ + 1));
+    Rls_ = ar.get<double>((int64_t)(m_ + 1) * (m_ + 1));
+    cls_ = ar.get<double>(m_ + 1);
+    z_ = ar.get<double>(in_.s);
+    lsres_ = ar.get<double>(m_ + 8);
+    hco_ = ar.get<double>(16);
+    y_ = ar.get<double>(m_ + 1);
+    xsum_.assign(d, nullptr);
+    xcur_.assign(d, nullptr);
+    for (int mu = 0; mu < d; ++mu) {
+        xsum_[mu] = ar.get<double>(4 * cap_[mu] + 64);
+        xcur_[mu] = ar.get<double>(cap_[mu]);
+    }
+    scal_ = ar.get<double>(8);
+    flag_ = ar.get<int>(8);
+}
+
+}  // namespace ttsg
+
+namespace ttsg {
+
+void SgmresSolver::to_lp(int slot) {
+    if (p_ == Prec::F64) return;
+    for (int mu = 0; mu < in_.d; ++mu) {
+        const std::vector<int>& r = slot_r_[slot];
+        convert_f64_f32((int64_t)r[mu] * in_.n[mu] * r[mu + 1], slots_[slot][mu],
+                        static_cast<float*>(slot_lp_[slot][mu]), st_);
+    }
+}
+
+std::vector<const void*> SgmresSolver::slot_ops(int slot) const {
+    std::vector<const void*> v(in_.d);
+    for (int mu = 0; mu < in_.d; ++mu)
+        v[mu] = p_ == Prec::F64 ? static_cast<const void*>(slots_[slot][mu]) : slot_lp_[slot][mu];
+    return v;
+}
+
+double SgmresSolver::tt_norm_copy(const std::vector<int>& r, const std::vector<const double*>& c) {
+    const size_t mark = scratch_.mark();
+    std::vector<double*> w(in_.d);
+    for (int mu = 0; mu < in_.d; ++mu) {
+        const int64_t e = (int64_t)r[mu] * in_.n[mu] * r[mu + 1];
+        w[mu] = scratch_.get<double>(e);
+        copy_f64(e, c[mu], w[mu], st_);
+    }
+    std::vector<int> rr = r;
+    double nrm = tt_norm_orth(in_.d, in_.n, rr, w, scratch_, st_);
+    scratch_.release(mark);
+    return nrm;
+}
+
+int sgmres_run_impl(SgmresSolver& s, double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info, void* ws,
+                    size_t ws_bytes) {
+    return s.run(x_out, x_r, info, ws, ws_bytes);
+}
+
+int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info, void* ws, size_t ws_bytes) {
+    const int d = in_.d;
+    const int* n = in_.n;
+    const ttsg_sgmres_opts& o = in_.o;
+    const int s = in_.s;
+    Arena meas;
+    meas.measure();
+    carve(meas);
+    const size_t fixed = meas.used();
+    const size_t scr = scratch_bytes();
+    Workspace wsp(ws, ws_bytes, fixed + scr + 4096, st_);
+    carve(wsp.arena);
+    scratch_.reset(wsp.arena.get<char>(scr), scr);
+
+    const bool timing = info && info->phase_seconds;
+    auto now = [&]() {
+        if (timing) TTSG_HIP(hipStreamSynchronize(st_));
+        return clock::now();
+    };
+    auto add_phase = [&](int ph, clock::time_point t0) {
+        if (timing) info->phase_seconds[ph] += std::chrono::duration<double>(now() - t0).count();
+    };
+    if (timing)
+        for (int i = 0; i < 8; ++i) info->phase_seconds[i] = 0.0;
+
+    // ---- operands --------------------------------------------------------
+    std::vector<int> R1(d + 1, 1);
+    for (int mu = 0; mu < d; ++mu) {
+        kr_precompute(Prec::F64, s, n[mu], in_.R[mu], in_.R[mu + 1], in_.S[mu], in_.A[mu], SA64_[mu], st_);
+    }
+    std::vector<const void*> Dv(d), SAv(d), Sv(d), Xv(d - 1), Yv(d - 1);
+    for (int mu = 0; mu < d; ++mu) {
+        const int64_t nn = n[mu];
+        if (p_ == Prec::F64) {
+            Dv[mu] = in_.A[mu];
+            SAv[mu] = SA64_[mu];
+            Sv[mu] = in_.S[mu];
+        } else {
+            convert_f64_f32((int64_t)in_.R[mu] * nn * nn * in_.R[mu + 1], in_.A[mu], (float*)Dp_[mu], st_);
+            convert_f64_f32((int64_t)s * in_.R[mu] * nn * in_.R[mu + 1], SA64_[mu], (float*)SAp_[mu], st_);
+            convert_f64_f32((int64_t)s * nn, in_.S[mu], (float*)Sp_[mu], st_);
+            Dv[mu] = Dp_[mu];
+            SAv[mu] = SAp_[mu];
+            Sv[mu] = Sp_[mu];
+        }
+    }
+    for (int k = 0; k < d - 1; ++k) {
+        if (p_ == Prec::F64) {
+            Yv[k] = in_.Y[k];
+            Xv[k] = in_.X[k];
+        } else {
+            convert_f64_f32((int64_t)in_.rho[k] * n[k] * in_.rho[k + 1], in_.Y[k], (float*)Yp_[k], st_);
+            convert_f64_f32((int64_t)in_.rx[k + 1] * n[k + 1] * in_.rx[k + 2], in_.X[k], (float*)Xp_[k], st_);
+            Yv[k] = Yp_[k];
+            Xv[k] = Xp_[k];
+        }
+    }
+    SketchOperands so_op, so_plain;
+    so_op.p = so_plain.p = p_;
+    so_op.n = so_plain.n = n;
+    so_op.d = so_plain.d = d;
+    so_op.rho = so_plain.rho = in_.rho;
+    so_op.rx = so_plain.rx = in_.rx;
+    so_op.Y = so_plain.Y = Yv;
+    so_op.X = so_plain.X = Xv;
+    so_op.R = in_.R;
+    so_op.D = Dv;
+    so_plain.R = R1;
+
+    auto sk_ptrs = [&](double* base, std::vector<double*>& psi, std::vector<double*>& om) {
+        psi.assign(d, nullptr);
+        om.assign(std::max(d - 1, 1), nullptr);
+        for (int mu = 0; mu < d; ++mu) psi[mu] = base + psi_off_[mu];
+        for (int b = 1; b < d; ++b) om[b - 1] = base + om_off_[b];
+    };
+    auto sketch_slot = [&](int slot, double* out) {
+        std::vector<double*> psi, om;
+        sk_ptrs(out, psi, om);
+        stta_sketch(so_plain, slot_r_[slot], slot_ops(slot), psi.data(), om.data(), scratch_, st_);
+    };
+    auto read = [&](const double* dev) {
+        double h = 0.0;
+        TTSG_HIP(hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, st_));
+        TTSG_HIP(hipStreamSynchronize(st_));
+        return h;
+    };
+    auto cvec = [](const std::vector<double*>& v) { return std::vector<const double*>(v.begin(), v.end()); };
+
+    // ---- norms of b and S b ----------------------------------------------
+    const double nb = tt_norm_copy(in_.rb, in_.b);
+    TTSG_CHECK(std::isfinite(nb), TTSG_ERR_NONFINITE, "right-hand side is not finite");
+    if (nb == 0.0) {
+        for (int mu = 0; mu < d; ++mu) fill(n[mu], 0.0, x_out[mu], st_);
+        for (int k = 0; k <= d; ++k) x_r[k] = 1;
+        TTSG_HIP(hipStreamSynchronize(st_));
+        if (info) {
+            info->iterations = 0;
+            info->cycles = 0;
+            info->true_residual = 0.0;
+            info->status = TTSG_OK;
+        }
+        return TTSG_OK;
+    }
+    std::vector<const void*> bops(d);
+    std::vector<void*> b_lp(d, nullptr);
+    {
+        const size_t mk = scratch_.mark();
+        if (p_ != Prec::F64) {
+            for (int mu = 0; mu < d; ++mu) {
+                const int64_t e = (int64_t)in_.rb[mu] * n[mu] * in_.rb[mu + 1];
+                b_lp[mu] = scratch_.get<float>(e);
+                convert_f64_f32(e, in_.b[mu], (float*)b_lp[mu], st_);
+                bops[mu] = b_lp[mu];
+            }
+        } else {
+            for (int mu = 0; mu < d; ++mu) bops[mu] = in_.b[mu];
+        }
+        kr_sketch_run(p_, d, n, s, R1, Sv, in_.rb, bops, z_, scratch_, st_);
+        sumsq(s, z_, lsres_, scal_, st_);
+        scratch_.release(mk);
+    }
+    const double Sb = std::sqrt(read(scal_));
+
+    // ---- buffers for A x, b - A x ----------------------------------------
+    std::vector<double*> G(d), Rsum(d);
+    {
+        for (int mu = 0; mu < d; ++mu) {
+            const int64_t nn = n[mu];
+            const int64_t gl = (int64_t)in_.R[mu] * in_.rx[mu], gr = (int64_t)in_.R[mu + 1] * in_.rx[mu + 1];
+            G[mu] = scratch_.get<double>(gl * nn * gr);
+            Rsum[mu] = scratch_.get<double>((gl + in_.rb[mu]) * nn * (gr + in_.rb[mu + 1]));
+        }
+    }
+    auto true_res = [&](const std::vector<int>& xr, const std::vector<double*>& xc) -> double {
+        // ||b - A x||^2 = ||b||^2 - 2 <A x, b> + ||A x||^2  (FP64 throughout)
+        std::vector<int> gr(d + 1);
+        for (int k = 0; k <= d; ++k) gr[k] = in_.R[k] * xr[k];
+        for (int mu = 0; mu < d; ++mu)
+            matvec_core(xr[mu], n[mu], xr[mu + 1], in_.R[mu], in_.R[mu + 1], in_.A[mu], xc[mu], false, G[mu], st_);
+        std::vector<const void*> gv(G.begin(), G.end()), bv(in_.b.begin(), in_.b.end());
+        inner_run(Prec::F64, d, n, R1, {}, gr, gv, in_.rb, bv, scal_ + 1, scratch_, st_);
+        inner_run(Prec::F64, d, n, R1, {}, gr, gv, gr, gv, scal_ + 2, scratch_, st_);
+        double hb[2];
+        TTSG_HIP(hipMemcpyAsync(hb, scal_ + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, st_));
+        TTSG_HIP(hipStreamSynchronize(st_));
+        double r2 = nb * nb - 2.0 * hb[0] + hb[1];
+        return std::sqrt(std::max(r2, 0.0)) / nb;
+    };
+
+    // ---- cycles ------------------------------------------------------------
+    int total = 0, cycles = 0, status = TTSG_NOT_CONVERGED, max_rank = 0;
+    bool have_x = false;
+    double last_sres = 1.0, last_true = 1.0;
+    const int max_cycles = o.max_cycles > 0 ? o.max_cycles : 50;
+    const double final_tol = o.final_tol > 0.0 ? o.final_tol : o.round_tol;
+    const double stop = o.stop_safety * o.tol * Sb;
+    const int nslots = q_ + 2;
+    std::vector<int> window;
+    while (total < maxit_ && cycles < max_cycles) {
+        ++cycles;
+        auto t0 = now();
+        // r0 into slot 0
+        window.clear();
+        const int s0 = 0;
+        double beta;
+        if (!have_x) {
+            slot_r_[s0] = in_.rb;
+            for (int mu = 0; mu < d; ++mu)
+                copy_f64((int64_t)in_.rb[mu] * n[mu] * in_.rb[mu + 1], in_.b[mu], slots_[s0][mu], st_);
+            beta = tt_norm_copy(slot_r_[s0], cvec(slots_[s0]));
+        } else {
+            std::vector<int> gr(d + 1), rr;
+            for (int k = 0; k <= d; ++k) gr[k] = in_.R[k] * xcur_r_[k];
+            for (int mu = 0; mu < d; ++mu)
+                matvec_core(xcur_r_[mu], n[mu], xcur_r_[mu + 1], in_.R[mu], in_.R[mu + 1], in_.A[mu], xcur_[mu],
+                            false, G[mu], st_);
+            std::vector<double*> bb(in_.b.size());
+            for (int mu = 0; mu < d; ++mu) bb[mu] = const_cast<double*>(in_.b[mu]);
+            tt_add_block(d, n, in_.rb, bb, gr, cvec(G), -1.0, Rsum, rr, st_);
+            std::vector<int64_t> caps(d);
+            int cap = 0;
+            for (int k = 0; k <= d; ++k) cap = std::max(cap, in_.rx[k]);
+            tt_svd_inplace(d, n, rr, Rsum, caps, 1e-12, cap, scratch_, st_, nullptr);
+            slot_r_[s0] = rr;
+            for (int mu = 0; mu < d; ++mu)
+                copy_f64((int64_t)rr[mu] * n[mu] * rr[mu + 1], Rsum[mu], slots_[s0][mu], st_);
+            beta = tt_norm_copy(slot_r_[s0], cvec(slots_[s0]));
+        }
+        if (beta == 0.0) {
+            status = TTSG_OK;
+            break;
+        }
+        scale_f64((int64_t)slot_r_[s0][0] * n[0] * slot_r_[s0][1], 1.0 / beta, slots_[s0][0], st_);
+        to_lp(s0);
+        // S r0 = beta * S v1
+        kr_sketch_run(p_, d, n, s, R1, Sv, slot_r_[s0], slot_ops(s0), z_, scratch_, st_);
+        scale_f64(s, beta, z_, st_);
+        sketch_slot(s0, sketches_);
+        window.push_back(s0);
+        add_phase(TTSG_PH_OTHER, t0);
+
+        int kk = 0;  // columns of W in this cycle
+        bool breakdown = false;
+        for (int k = 0; k < m_ && total < maxit_; ++k) {
+            const int vk = window.back();
+            // 1) w_k = S A v_k
+            auto t1 = now();
+            kr_sketch_run(p_, d, n, s, in_.R, SAv, slot_r_[vk], slot_ops(vk), W_ + (int64_t)k * s, scratch_, st_);
+            add_phase(TTSG_PH_KR, t1);
+            // 2) h_{i,k} for the window
+            t1 = now();
+            fill(1, 1.0, hco_, st_);
+            const int nw = (int)window.size();
+            for (int t = 0; t < nw; ++t) {
+                const int vi = window[t];
+                inner_run(p_, d, n, in_.R, Dv, slot_r_[vk], slot_ops(vk), slot_r_[vi], slot_ops(vi), hco_ + 1 + t,
+                          scratch_, st_);
+            }
+            add_phase(TTSG_PH_INNER, t1);
+            // 3) STTA sketch of A v_k, combined with the window sketches
+            t1 = now();
+            {
+                std::vector<double*> psi, om;
+                sk_ptrs(skA_, psi, om);
+                stta_sketch(so_op, slot_r_[vk], slot_ops(vk), psi.data(), om.data(), scratch_, st_);
+                // window entry t holds basis index (k - nw + 1 + t) of this cycle
+                std::vector<const double*> xs(1 + nw);
+                std::vector<double> sg(1 + nw, -1.0);
+                xs[0] = skA_;
+                sg[0] = 1.0;
+                for (int t = 0; t < nw; ++t) xs[1 + t] = sketches_ + (int64_t)(k - nw + 1 + t) * sk_len_;
+                lin_comb_dev(sk_len_, 1 + nw, xs.data(), hco_, sg.data(), skC_, st_);
+            }
+            add_phase(TTSG_PH_STTA, t1);
+            // 4) recover + TT-SVD into a free slot
+            t1 = now();
+            int fs = -1;
+            for (int sl = 0; sl < nslots; ++sl)
+                if (std::find(window.begin(), window.end(), sl) == window.end()) {
+                    fs = sl;
+                    break;
+                }
+            {
+                std::vector<double*> psi, om;
+                sk_ptrs(skC_, psi, om);
+                std::vector<const double*> cpsi(psi.begin(), psi.end()), com(om.begin(), om.end());
+                stta_recover(d, n, in_.rho, in_.rx, cpsi, com, o.rcond, slots_[fs], slot_r_[fs], scratch_, st_);
+            }
+            add_phase(TTSG_PH_RECOVER, t1);
+            t1 = now();
+            const double h = tt_svd_inplace(d, n, slot_r_[fs], slots_[fs], cap_, o.round_tol, o.maxrank, scratch_,
+                                            st_, nullptr);
+            add_phase(TTSG_PH_TTSVD, t1);
+            TTSG_CHECK(std::isfinite(h), TTSG_ERR_NONFINITE, "non-finite basis vector");
+            // 5) least squares
+            t1 = now();
+            hipLaunchKernelGGL(k_ls_append, dim3(1), dim3(LS_THREADS), 0, st_, s, k, m_ + 1, W_, Q_, Rls_, cls_,
+                               z_, lsres_);
+            TTSG_HIP(hipGetLastError());
+            const double sres = read(lsres_);
+            add_phase(TTSG_PH_LS, t1);
+            TTSG_CHECK(std::isfinite(sres), TTSG_ERR_NONFINITE, "non-finite sketched residual");
+            kk = k + 1;
+            ++total;
+            last_sres = sres / Sb;
+            int mr = 0;
+            for (int b = 0; b <= d; ++b) mr = std::max(mr, slot_r_[fs][b]);
+            max_rank = std::max(max_rank, mr);
+            if (info && info->sketched_history && total - 1 < o.maxit) info->sketched_history[total - 1] = last_sres;
+            if (info && info->rank_history && total - 1 < o.maxit) info->rank_history[total - 1] = mr;
+            if (h == 0.0) {
+                breakdown = true;
+                break;
+            }
+            if (sres <= stop) break;
+            if (k + 1 >= m_ || total >= maxit_) break;
+            // 6) v_{k+1} and its sketch
+            t1 = now();
+            scale_f64((int64_t)slot_r_[fs][0] * n[0] * slot_r_[fs][1], 1.0 / h, slots_[fs][0], st_);
+            to_lp(fs);
+            sketch_slot(fs, sketches_ + (int64_t)(k + 1) * sk_len_);
+            window.push_back(fs);
+            if ((int)window.size() > q_) window.erase(window.begin());
+            add_phase(TTSG_PH_STTA, t1);
+        }
+        // ---- solution of the cycle ----
+        auto t2 = now();
+        hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(64), 0, st_, kk, m_ + 1, Rls_, cls_, y_);
+        TTSG_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_gemv_cols, dim3(grid_for(sk_len_)), dim3(256), 0, st_, sk_len_, kk, sk_len_,
+                           sketches_, y_, skC_);
+        TTSG_HIP(hipGetLastError());
+        std::vector<double*> corr = have_x ? xsum_ : xcur_;
+        std::vector<int> cr;
+        {
+            std::vector<double*> psi, om;
+            sk_ptrs(skC_, psi, om);
+            std::vector<const double*> cpsi(psi.begin(), psi.end()), com(om.begin(), om.end());
+            // recover into the free-slot buffers, then round
+            int fs = -1;
+            for (int sl = 0; sl < nslots; ++sl)
+                if (std::find(window.begin(), window.end(), sl) == window.end()) {
+                    fs = sl;
+                    break;
+                }
+            stta_recover(d, n, in_.rho, in_.rx, cpsi, com, o.rcond, slots_[fs], cr, scratch_, st_);
+            int cap = 0;
+            for (int k = 0; k <= d; ++k) cap = std::max(cap, in_.rx[k]);
+            tt_svd_inplace(d, n, cr, slots_[fs], cap_, final_tol, cap, scratch_, st_, nullptr);
+            if (!have_x) {
+                for (int mu = 0; mu < d; ++mu)
+                    copy_f64((int64_t)cr[mu] * n[mu] * cr[mu + 1], slots_[fs][mu], xcur_[mu], st_);
+                xcur_r_ = cr;
+                have_x = true;
+            } else {
+                std::vector<int> sr;
+                tt_add_block(d, n, xcur_r_, xcur_, cr, cvec(slots_[fs]), 1.0, xsum_, sr, st_);
+                tt_svd_inplace(d, n, sr, xsum_, cap_, final_tol, cap, scratch_, st_, nullptr);
+                for (int mu = 0; mu < d; ++mu)
+                    copy_f64((int64_t)sr[mu] * n[mu] * sr[mu + 1], xsum_[mu], xcur_[mu], st_);
+                xcur_r_ = sr;
+            }
+        }
+        add_phase(TTSG_PH_FINAL, t2);
+        t2 = now();
+        last_true = true_res(xcur_r_, xcur_);
+        add_phase(TTSG_PH_OTHER, t2);
+        if (info && info->true_history && cycles - 1 < max_cycles) info->true_history[cycles - 1] = last_true;
+        if (last_true <= o.tol) {
+            status = breakdown ? TTSG_BREAKDOWN : TTSG_OK;
+            break;
+        }
+        (void)corr;
+    }
+    // ---- output ----
+    if (have_x) {
+        for (int mu = 0; mu < d; ++mu)
+            copy_f64((int64_t)xcur_r_[mu] * n[mu] * xcur_r_[mu + 1], xcur_[mu], x_out[mu], st_);
+        for (int k = 0; k <= d; ++k) x_r[k] = xcur_r_[k];
+    }
+    TTSG_HIP(hipStreamSynchronize(st_));
+    if (info) {
+        info->iterations = total;
+        info->cycles = cycles;
+        info->max_rank = max_rank;
+        info->status = status;
+        info->true_residual = last_true;
+        info->sketched_residual = last_sres;
+    }
+    return status;
+}
+
+int sgmres_solve(const SolverInputs& in, double* const* x, int32_t* x_r, ttsg_sgmres_info* info, void* ws,
+                 size_t ws_bytes, hipStream_t st) {
+    SgmresSolver s(in, st);
+    return s.run(x, x_r, info, ws, ws_bytes);
+}
+
+size_t sgmres_workspace(const SolverInputs& in, hipStream_t st) {
+    SgmresSolver s(in, st);
+    return s.workspace_bytes();
+}
+
+}  // namespace ttsg

@@ -1,0 +1,140 @@
+// Host-side building blocks of the TT sweeps (tt_ops.hip) and the rounding
+// pipeline (rounding.hip).
+#pragma once
+
+#include "ttsg_internal.h"
+
+namespace ttsg {
+
+ContractDesc cdesc(int M, int N, int K, int batch = 1);
+
+// Sizes of one environment step: vector core rl x n x rr, operator ranks
+// Rl/Rr (1/1 when there is no operator), probe core pl x n x pr.
+struct LeftDims {
+    int rl, n, rr, Rl, Rr, pl, pr;
+};
+
+void matvec_core(int rl, int n, int rr, int Rl, int Rr, const double* D, const double* C, bool transpose,
+                 double* G, hipStream_t st);
+
+// E (pl x Rl x rl) -> Eout (pr x Rr x rr).  T1 holds pl*Rl*n*rr and T2
+// pl*n*Rr*rr elements; with D == nullptr T2 is not used (T1 plays its role).
+// Z == nullptr stops after T1/T2 (what the core sketch Psi needs).
+void left_step(Prec p, const LeftDims& s, const void* E, const void* C, const void* D, const void* Z, void* T1,
+               void* T2, void* Eout, hipStream_t st);
+// F (rr x Rr x pr) -> Fout (rl x Rl x pl).  U1: rl*n*Rr*pr, U2: rl*Rl*n*pr.
+void right_step(Prec p, const LeftDims& s, const void* F, const void* C, const void* D, const void* Z, void* U1,
+                void* U2, void* Fout, hipStream_t st);
+void psi_step(Prec p, int pl, int n, int Rr, int rr, int qr, const void* T2, const void* F, void* Psi,
+              hipStream_t st);
+void omega_step(Prec p, int pl, int Rr, int rr, int qr, const void* E, const void* F, void* Om, hipStream_t st);
+
+void kr_precompute(Prec p, int s, int n, int Rl, int Rr, const void* S, const void* D, void* SA, hipStream_t st);
+// P (s x Rl x rl) -> Pout (s x Rr x rr); Xbuf holds s*Rr*rl*n elements.
+void kr_step(Prec p, int s, int rl, int n, int rr, int Rl, int Rr, const void* P, const void* SA, const void* C,
+             void* Xbuf, void* Pout, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Views with host-known ranks.
+// ---------------------------------------------------------------------------
+struct TTView {
+    int d = 0;
+    const int* n = nullptr;
+    std::vector<int> r;              // d + 1
+    std::vector<const double*> c;    // d cores
+};
+
+struct TTOut {
+    std::vector<int> r;              // d + 1
+    std::vector<double*> c;          // d cores (capacity managed by the caller)
+};
+
+struct OpView {
+    std::vector<int> R;              // d + 1
+    std::vector<const double*> c;    // d cores, nullptr entries mean "identity"
+    bool present = false;
+};
+
+// Element size of a precision's storage type.
+inline size_t elem_size(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2); }
+
+// ---------------------------------------------------------------------------
+// STTA sketch (Sec. 3.3) of x or A x.  Y holds d-1 cores (modes 0..d-2),
+// X holds d-1 cores (modes 1..d-1, entry k-1 for mode k).  Psi/Omega are
+// float64 outputs.  Scratch comes from the arena (released on return).
+// All operand pointers are of the element type of `p` except Psi/Omega.
+// ---------------------------------------------------------------------------
+struct SketchOperands {
+    Prec p = Prec::F64;
+    const int* n = nullptr;
+    int d = 0;
+    std::vector<int> rho, rx;                 // d + 1
+    std::vector<const void*> Y, X;            // d - 1 each, element type of p
+    std::vector<int> R;                       // d + 1 (all 1 without operator)
+    std::vector<const void*> D;               // d, element type of p, or empty
+};
+
+// x cores (element type of p), ranks r.
+void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::vector<const void*>& x,
+                 double* const* Psi, double* const* Omega, Arena& ar, hipStream_t st);
+
+// Khatri-Rao sketch w = S x or S A x.  SA: d precomputed S_mu D_mu (or S_mu)
+// of element type p; w: float64 output of length s.
+void kr_sketch_run(Prec p, int d, const int* n, int s, const std::vector<int>& R,
+                   const std::vector<const void*>& SA, const std::vector<int>& r,
+                   const std::vector<const void*>& x, double* w, Arena& ar, hipStream_t st);
+
+// Inner product <A x, z> (A optional) by a left sweep; result (float64) written
+// to out_dev[0].
+void inner_run(Prec p, int d, const int* n, const std::vector<int>& R, const std::vector<const void*>& D,
+               const std::vector<int>& rx_, const std::vector<const void*>& x, const std::vector<int>& rz,
+               const std::vector<const void*>& z, double* out_dev, Arena& ar, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Rounding pipeline (rounding.hip), all FP64.
+// ---------------------------------------------------------------------------
+// TT-SVD rounding in place: cores `w` (capacity per core given by cap_elems)
+// with ranks r; on return r holds the new ranks.  Returns ||T||_F.
+// tol is relative, maxrank 0 = none.  Synchronizes the stream.
+double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vector<double*>& w,
+                      const std::vector<int64_t>& cap_elems, double tol, int maxrank, Arena& ar,
+                      hipStream_t st, double* norm_before = nullptr);
+
+// STTA recovery: cores of Omega^+ applied to Psi, compacted to the numerical
+// ranks of the Omega_b (relative cutoff rcond).  out cores need capacity
+// rx[mu] * n[mu] * rx[mu+1].  Writes the recovered ranks to r_out.
+void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::vector<int>& rx,
+                  const std::vector<const double*>& Psi, const std::vector<const double*>& Omega, double rcond,
+                  const std::vector<double*>& out, std::vector<int>& r_out, Arena& ar, hipStream_t st);
+
+// Left orthogonalization sweep by Householder QR; returns ||T|| (reads one
+// float64 back).  Cores are modified in place; ranks may shrink.
+double tt_norm_orth(int d, const int* n, std::vector<int>& r, const std::vector<double*>& w, Arena& ar,
+                    hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Solver (solver.hip)
+// ---------------------------------------------------------------------------
+struct SolverInputs {
+    int d;
+    const int* n;
+    std::vector<int> R;
+    std::vector<const double*> A;
+    std::vector<int> rb;
+    std::vector<const double*> b;
+    int s;
+    std::vector<const double*> S;
+    std::vector<int> rho, rx;
+    std::vector<const double*> Y, X;
+    ttsg_sgmres_opts o;
+};
+
+int sgmres_solve(const SolverInputs& in, double* const* x, int32_t* x_r, ttsg_sgmres_info* info, void* ws,
+                 size_t ws_bytes, hipStream_t st);
+
+// a + bscale * b as block cores (ranks add); first/last cores concatenated.
+void tt_add_block(int d, const int* n, const std::vector<int>& ra, const std::vector<double*>& a,
+                  const std::vector<int>& rb, const std::vector<const double*>& b, double bscale,
+                  const std::vector<double*>& out, std::vector<int>& rout, hipStream_t st);
+
+}  // namespace ttsg

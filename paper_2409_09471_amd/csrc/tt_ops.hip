@@ -1,0 +1,401 @@
+// TT operations of the sketched TT-GMRES hot path, expressed as sequences of
+// strided contractions (contract.hip) and FP64 factorizations (la.hip).
+//
+// Layout conventions (row-major, 0-based modes):
+//   core C_mu        [a][j][b]          r_l x n x r_r
+//   operator D_mu    [al][i][j][be]     R_l x n x n x R_r
+//   left env  E_mu   [p][al][a]         rho x R x r   (probe rank, op rank, vector rank)
+//   right env F_mu   [b][be][q]         r x R x rx    (vector rank, op rank, probe rank)
+//   Psi_mu           [p][i][q]          rho_mu x n x rx_{mu+1}
+//   Omega_b          [p][q]             rho_b x rx_b
+// The merged rank index of A v is (a, al) with the vector rank outer, so the
+// environment orders above make every merged index a plain stride.
+#include "tt_ops.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace ttsg {
+
+ContractDesc cdesc(int M, int N, int K, int batch) {
+    ContractDesc d{};
+    d.M = M;
+    d.N = N;
+    d.K = K;
+    d.batch = batch;
+    d.alpha = 1.0;
+    d.beta = 0.0;
+    d.am = d.ak = d.bk = d.bn = d.cm = d.cn = idx1(0);
+    d.ab = d.bb = d.cb = idx1(0);
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-vector product (Sec. 2.2)
+// ---------------------------------------------------------------------------
+void matvec_core(int rl, int n, int rr, int Rl, int Rr, const double* D, const double* C, bool transpose,
+                 double* G, hipStream_t st) {
+    // G[(a,al)][i][(b,be)] = sum_j D[al][i][j][be] C[a][j][b], one product per (al, be)
+    ContractDesc d = cdesc(n, rl * rr, n, Rl * Rr);
+    d.ab = idx2(Rr, 1, (int64_t)n * n * Rr);
+    d.am = transpose ? idx1(Rr) : idx1((int64_t)n * Rr);
+    d.ak = transpose ? idx1((int64_t)n * Rr) : idx1(Rr);
+    d.bb = idx1(0);
+    d.bk = idx1(rr);
+    d.bn = idx2(rr, 1, (int64_t)n * rr);
+    const int64_t rowG = (int64_t)n * rr * Rr;
+    d.cb = idx2(Rr, 1, rowG);
+    d.cm = idx1((int64_t)rr * Rr);
+    d.cn = idx2(rr, Rr, (int64_t)Rl * rowG);
+    contract(Prec::F64, d, D, C, G, st);
+}
+
+// ---------------------------------------------------------------------------
+// Environment steps
+// ---------------------------------------------------------------------------
+static inline int64_t eoff(Prec p) { return p == Prec::F64 ? 8 : 4; }
+
+void left_step(Prec p, const LeftDims& s, const void* E, const void* C, const void* D, const void* Z, void* T1,
+               void* T2, void* Eout, hipStream_t st) {
+    const int rl = s.rl, n = s.n, rr = s.rr, Rl = s.Rl, Rr = s.Rr, pl = s.pl, pr = s.pr;
+    // L1: T1[p'][al][j][b] = sum_a E[p'][al][a] C[a][j][b]
+    {
+        ContractDesc d = cdesc(pl * Rl, n * rr, rl);
+        d.am = idx1(rl);
+        d.ak = idx1(1);
+        d.bk = idx1((int64_t)n * rr);
+        d.bn = idx1(1);
+        d.cm = idx1((int64_t)n * rr);
+        d.cn = idx1(1);
+        contract(p, d, E, C, T1, st);
+    }
+    const void* T2in = T1;
+    if (D != nullptr) {
+        // L2: T2[p'][i][be][b] = sum_{(al,j)} D[al][i][j][be] T1[p'][al][j][b]
+        ContractDesc d = cdesc(n * Rr, rr, Rl * n, pl);
+        d.ab = idx1(0);
+        d.am = idx2(Rr, 1, (int64_t)n * Rr);
+        d.ak = idx2(n, Rr, (int64_t)n * n * Rr);
+        d.bb = idx1((int64_t)Rl * n * rr);
+        d.bk = idx1(rr);
+        d.bn = idx1(1);
+        d.cb = idx1((int64_t)n * Rr * rr);
+        d.cm = idx1(rr);
+        d.cn = idx1(1);
+        contract(p, d, D, T1, T2, st);
+        T2in = T2;
+    }
+    if (Z != nullptr && Eout != nullptr) {
+        // L3: E'[p][be][b] = sum_{(p',i)} Z[p'][i][p] T2[p'][i][be][b]
+        ContractDesc d = cdesc(pr, Rr * rr, pl * n);
+        d.am = idx1(1);
+        d.ak = idx1(pr);
+        d.bk = idx1((int64_t)Rr * rr);
+        d.bn = idx1(1);
+        d.cm = idx1((int64_t)Rr * rr);
+        d.cn = idx1(1);
+        contract(p, d, Z, T2in, Eout, st);
+    }
+}
+
+void right_step(Prec p, const LeftDims& s, const void* F, const void* C, const void* D, const void* Z, void* U1,
+                void* U2, void* Fout, hipStream_t st) {
+    // here pl/pr are the probe ranks (rho_l x n x rho_r) of Z; F is r_r x R_r x pr
+    const int rl = s.rl, n = s.n, rr = s.rr, Rl = s.Rl, Rr = s.Rr, pl = s.pl, pr = s.pr;
+    // R1: U1[a][j][be][q] = sum_b C[a][j][b] F[b][be][q]
+    {
+        ContractDesc d = cdesc(rl * n, Rr * pr, rr);
+        d.am = idx1(rr);
+        d.ak = idx1(1);
+        d.bk = idx1((int64_t)Rr * pr);
+        d.bn = idx1(1);
+        d.cm = idx1((int64_t)Rr * pr);
+        d.cn = idx1(1);
+        contract(p, d, C, F, U1, st);
+    }
+    const void* U2in = U1;
+    if (D != nullptr) {
+        // R2: U2[a][al][i][q] = sum_{(j,be)} D[al][i][j][be] U1[a][j][be][q]
+        ContractDesc d = cdesc(Rl * n, pr, n * Rr, rl);
+        d.ab = idx1(0);
+        d.am = idx1((int64_t)n * Rr);
+        d.ak = idx1(1);
+        d.bb = idx1((int64_t)n * Rr * pr);
+        d.bk = idx1(pr);
+        d.bn = idx1(1);
+        d.cb = idx1((int64_t)Rl * n * pr);
+        d.cm = idx1(pr);
+        d.cn = idx1(1);
+        contract(p, d, D, U1, U2, st);
+        U2in = U2;
+    }
+    // R3: F'[a][al][p'] = sum_{(i,q)} U2[a][al][i][q] Z[p'][i][q]
+    {
+        ContractDesc d = cdesc(rl * Rl, pl, n * pr);
+        d.am = idx1((int64_t)n * pr);
+        d.ak = idx1(1);
+        d.bk = idx1(1);
+        d.bn = idx1((int64_t)n * pr);
+        d.cm = idx1(pl);
+        d.cn = idx1(1);
+        contract(p, d, U2in, Z, Fout, st);
+    }
+}
+
+void psi_step(Prec p, int pl, int n, int Rr, int rr, int qr, const void* T2, const void* F, void* Psi,
+              hipStream_t st) {
+    // Psi[p'][i][q] = sum_{(be,b)} T2[p'][i][be][b] F[b][be][q]
+    ContractDesc d = cdesc(pl * n, qr, Rr * rr);
+    d.am = idx1((int64_t)Rr * rr);
+    d.ak = idx1(1);
+    d.bk = idx2(rr, (int64_t)Rr * qr, qr);
+    d.bn = idx1(1);
+    d.cm = idx1(qr);
+    d.cn = idx1(1);
+    contract(p, d, T2, F, Psi, st);
+}
+
+void omega_step(Prec p, int pl, int Rr, int rr, int qr, const void* E, const void* F, void* Om, hipStream_t st) {
+    // Om[p][q] = sum_{(be,b)} E[p][be][b] F[b][be][q]
+    ContractDesc d = cdesc(pl, qr, Rr * rr);
+    d.am = idx1((int64_t)Rr * rr);
+    d.ak = idx1(1);
+    d.bk = idx2(rr, (int64_t)Rr * qr, qr);
+    d.bn = idx1(1);
+    d.cm = idx1(qr);
+    d.cn = idx1(1);
+    contract(p, d, E, F, Om, st);
+}
+
+// ---------------------------------------------------------------------------
+// Khatri-Rao sketch steps.  P_mu[j][al][a] (s x R x r) is the row vector of
+// sketch row j after mu cores; SA_mu[j][al][i'][be] = sum_i S_mu[j,i] D_mu[al,i,i',be]
+// (or S_mu itself when there is no operator, R = 1).
+// ---------------------------------------------------------------------------
+void kr_precompute(Prec p, int s, int n, int Rl, int Rr, const void* S, const void* D, void* SA, hipStream_t st) {
+    ContractDesc d = cdesc(s, Rl * n * Rr, n);
+    d.am = idx1(n);
+    d.ak = idx1(1);
+    d.bk = idx1((int64_t)n * Rr);
+    d.bn = idx2(n * Rr, 1, (int64_t)n * n * Rr);
+    d.cm = idx1((int64_t)Rl * n * Rr);
+    d.cn = idx1(1);
+    contract(p, d, S, D, SA, st);
+}
+
+void kr_step(Prec p, int s, int rl, int n, int rr, int Rl, int Rr, const void* P, const void* SA, const void* C,
+             void* Xbuf, void* Pout, hipStream_t st) {
+    // KR1: X[j][be][a][i'] = sum_al P[j][al][a] SA[j][al][i'][be]
+    {
+        ContractDesc d = cdesc(rl, Rr * n, Rl, s);
+        d.ab = idx1((int64_t)Rl * rl);
+        d.am = idx1(1);
+        d.ak = idx1(rl);
+        d.bb = idx1((int64_t)Rl * n * Rr);
+        d.bk = idx1((int64_t)n * Rr);
+        d.bn = idx2(n, Rr, 1);
+        d.cb = idx1((int64_t)Rr * rl * n);
+        d.cm = idx1(n);
+        d.cn = idx2(n, 1, (int64_t)rl * n);
+        contract(p, d, P, SA, Xbuf, st);
+    }
+    // KR2: P'[(j,be)][b] = sum_{(a,i')} X[(j,be)][(a,i')] C[(a,i')][b]
+    {
+        ContractDesc d = cdesc(s * Rr, rr, rl * n);
+        d.am = idx1((int64_t)rl * n);
+        d.ak = idx1(1);
+        d.bk = idx1(rr);
+        d.bn = idx1(1);
+        d.cm = idx1(rr);
+        d.cn = idx1(1);
+        contract(p, d, Xbuf, C, Pout, st);
+    }
+}
+
+}  // namespace ttsg
+
+// ---------------------------------------------------------------------------
+// Sweep drivers
+// ---------------------------------------------------------------------------
+namespace ttsg {
+
+namespace {
+// one float64 or float32 scalar 1 written into a tiny buffer
+__global__ void k_set_one(void* p, int is_f64) {
+    if (is_f64) *static_cast<double*>(p) = 1.0;
+    else *static_cast<float*>(p) = 1.0f;
+}
+__global__ void k_to_f64(int64_t n, const float* __restrict__ x, double* __restrict__ y) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
+}
+__global__ void k_copy_scalar(const void* src, int is_f64, double* dst) {
+    dst[0] = is_f64 ? *static_cast<const double*>(src) : (double)*static_cast<const float*>(src);
+}
+void set_one(Prec p, void* buf, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_one, dim3(1), dim3(1), 0, st, buf, p == Prec::F64 ? 1 : 0);
+    TTSG_HIP(hipGetLastError());
+}
+void to_f64(Prec p, int64_t n, const void* src, double* dst, hipStream_t st) {
+    if (n <= 0) return;
+    if (p == Prec::F64) {
+        copy_f64(n, static_cast<const double*>(src), dst, st);
+        return;
+    }
+    int64_t b = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_to_f64, dim3((unsigned)std::max<int64_t>(b, 1)), dim3(256), 0, st, n,
+                       static_cast<const float*>(src), dst);
+    TTSG_HIP(hipGetLastError());
+}
+inline char* adv(const void* p, int64_t elems, Prec pr) {
+    return (char*)p + elems * (int64_t)elem_size(pr);
+}
+}  // namespace
+
+void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::vector<const void*>& x,
+                 double* const* Psi, double* const* Omega, Arena& ar, hipStream_t st) {
+    TTSG_CHECK(o.p != Prec::BF16, TTSG_ERR_ARG, "stta_sketch: bf16 operands are converted by the caller");
+    const int d = o.d;
+    const int* n = o.n;
+    const Prec p = o.p;
+    const size_t es = elem_size(p);
+    const size_t mark = ar.mark();
+    const bool op = !o.D.empty();
+    auto Rk = [&](int b) { return op ? o.R[b] : 1; };
+    // scratch sizes
+    int64_t t1 = 1, t2 = 1, u1 = 1, u2 = 1, env = 1;
+    for (int mu = 0; mu < d; ++mu) {
+        const int rl = r[mu], rr = r[mu + 1], nn = n[mu];
+        t1 = std::max<int64_t>(t1, (int64_t)o.rho[mu] * Rk(mu) * nn * rr);
+        t2 = std::max<int64_t>(t2, (int64_t)o.rho[mu] * nn * Rk(mu + 1) * rr);
+        u1 = std::max<int64_t>(u1, (int64_t)rl * nn * Rk(mu + 1) * o.rx[mu + 1]);
+        u2 = std::max<int64_t>(u2, (int64_t)rl * Rk(mu) * nn * o.rx[mu + 1]);
+        env = std::max<int64_t>(env, (int64_t)o.rho[mu + 1] * Rk(mu + 1) * rr);
+    }
+    void* T1 = ar.get<char>(t1 * es);
+    void* T2 = ar.get<char>(t2 * es);
+    void* U1 = ar.get<char>(u1 * es);
+    void* U2 = ar.get<char>(u2 * es);
+    void* Ea = ar.get<char>(env * es);
+    void* Eb = ar.get<char>(env * es);
+    void* one = ar.get<char>(16);
+    // right environments F_b for b = d..1 (F_d = 1)
+    std::vector<void*> F(d + 1, nullptr);
+    for (int b = 1; b <= d; ++b) F[b] = ar.get<char>((int64_t)r[b] * Rk(b) * o.rx[b] * es);
+    void* tmp_out = nullptr;
+    if (p != Prec::F64) {
+        int64_t mx = 1;
+        for (int mu = 0; mu < d; ++mu) mx = std::max<int64_t>(mx, (int64_t)o.rho[mu] * n[mu] * o.rx[mu + 1]);
+        tmp_out = ar.get<char>(mx * es);
+    }
+    set_one(p, F[d], st);
+    for (int mu = d - 1; mu >= 1; --mu) {
+        LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rx[mu], o.rx[mu + 1]};
+        right_step(p, s, F[mu + 1], x[mu], op ? o.D[mu] : nullptr, o.X[mu - 1], U1, U2, F[mu], st);
+    }
+    // left sweep with Psi and Omega
+    set_one(p, Ea, st);
+    void* E = Ea;
+    void* En = Eb;
+    for (int mu = 0; mu < d; ++mu) {
+        LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rho[mu], mu + 1 < d ? o.rho[mu + 1] : 1};
+        const bool last = (mu == d - 1);
+        left_step(p, s, E, x[mu], op ? o.D[mu] : nullptr, nullptr, T1, T2, nullptr, st);
+        const void* T2r = op ? T2 : T1;
+        const int64_t npsi = (int64_t)o.rho[mu] * n[mu] * o.rx[mu + 1];
+        if (p == Prec::F64) {
+            psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2r, F[mu + 1], Psi[mu], st);
+        } else {
+            psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2r, F[mu + 1], tmp_out, st);
+            to_f64(p, npsi, tmp_out, Psi[mu], st);
+        }
+        if (!last) {
+            // E_{mu+1} = Y_mu contracted with T2
+            ContractDesc dd = cdesc(o.rho[mu + 1], Rk(mu + 1) * r[mu + 1], o.rho[mu] * n[mu]);
+            dd.am = idx1(1);
+            dd.ak = idx1(o.rho[mu + 1]);
+            dd.bk = idx1((int64_t)Rk(mu + 1) * r[mu + 1]);
+            dd.bn = idx1(1);
+            dd.cm = idx1((int64_t)Rk(mu + 1) * r[mu + 1]);
+            dd.cn = idx1(1);
+            contract(p, dd, o.Y[mu], T2r, En, st);
+            const int b = mu + 1;
+            if (p == Prec::F64) {
+                omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], En, F[b], Omega[b - 1], st);
+            } else {
+                omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], En, F[b], tmp_out, st);
+                to_f64(p, (int64_t)o.rho[b] * o.rx[b], tmp_out, Omega[b - 1], st);
+            }
+            std::swap(E, En);
+        }
+    }
+    ar.release(mark);
+    (void)adv;
+}
+
+void kr_sketch_run(Prec p, int d, const int* n, int s, const std::vector<int>& R,
+                   const std::vector<const void*>& SA, const std::vector<int>& r,
+                   const std::vector<const void*>& x, double* w, Arena& ar, hipStream_t st) {
+    TTSG_CHECK(p != Prec::BF16, TTSG_ERR_ARG, "kr_sketch: bf16 not supported");
+    const size_t es = elem_size(p);
+    const size_t mark = ar.mark();
+    int64_t pmax = 1, xmax = 1;
+    for (int mu = 0; mu < d; ++mu) {
+        pmax = std::max<int64_t>(pmax, (int64_t)s * R[mu + 1] * r[mu + 1]);
+        xmax = std::max<int64_t>(xmax, (int64_t)s * R[mu + 1] * r[mu] * n[mu]);
+    }
+    void* Pa = ar.get<char>(std::max<int64_t>(pmax, s) * es);
+    void* Pb = ar.get<char>(std::max<int64_t>(pmax, s) * es);
+    void* Xb = ar.get<char>(xmax * es);
+    // P_0 = 1 for every sketch row
+    if (p == Prec::F64) {
+        fill(s, 1.0, static_cast<double*>(Pa), st);
+    } else {
+        // float ones: fill a double temp then convert
+        double* tmpd = ar.get<double>(s);
+        fill(s, 1.0, tmpd, st);
+        convert_f64_f32(s, tmpd, static_cast<float*>(Pa), st);
+    }
+    void* P = Pa;
+    void* Pn = Pb;
+    for (int mu = 0; mu < d; ++mu) {
+        kr_step(p, s, r[mu], n[mu], r[mu + 1], R[mu], R[mu + 1], P, SA[mu], x[mu], Xb, Pn, st);
+        std::swap(P, Pn);
+    }
+    to_f64(p, s, P, w, st);
+    ar.release(mark);
+}
+
+void inner_run(Prec p, int d, const int* n, const std::vector<int>& R, const std::vector<const void*>& D,
+               const std::vector<int>& rx_, const std::vector<const void*>& x, const std::vector<int>& rz,
+               const std::vector<const void*>& z, double* out_dev, Arena& ar, hipStream_t st) {
+    TTSG_CHECK(p != Prec::BF16, TTSG_ERR_ARG, "inner: bf16 not supported");
+    const size_t es = elem_size(p);
+    const size_t mark = ar.mark();
+    const bool op = !D.empty();
+    auto Rk = [&](int b) { return op ? R[b] : 1; };
+    int64_t t1 = 1, t2 = 1, env = 1;
+    for (int mu = 0; mu < d; ++mu) {
+        t1 = std::max<int64_t>(t1, (int64_t)rz[mu] * Rk(mu) * n[mu] * rx_[mu + 1]);
+        t2 = std::max<int64_t>(t2, (int64_t)rz[mu] * n[mu] * Rk(mu + 1) * rx_[mu + 1]);
+        env = std::max<int64_t>(env, (int64_t)rz[mu + 1] * Rk(mu + 1) * rx_[mu + 1]);
+    }
+    void* T1 = ar.get<char>(t1 * es);
+    void* T2 = ar.get<char>(t2 * es);
+    void* Ea = ar.get<char>(env * es);
+    void* Eb = ar.get<char>(env * es);
+    set_one(p, Ea, st);
+    void* E = Ea;
+    void* En = Eb;
+    for (int mu = 0; mu < d; ++mu) {
+        LeftDims s{rx_[mu], n[mu], rx_[mu + 1], Rk(mu), Rk(mu + 1), rz[mu], rz[mu + 1]};
+        left_step(p, s, E, x[mu], op ? D[mu] : nullptr, z[mu], T1, T2, En, st);
+        std::swap(E, En);
+    }
+    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, st, E, p == Prec::F64 ? 1 : 0, out_dev);
+    TTSG_HIP(hipGetLastError());
+    ar.release(mark);
+}
+
+}  // namespace ttsg

@@ -1,0 +1,175 @@
+// Internal declarations shared by the HIP translation units of libttsg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ttsg.h"
+
+namespace ttsg {
+
+// ---------------------------------------------------------------------------
+// Errors: internal code throws ttsg::Error; the C ABI layer converts it to a
+// negative return code and a thread-local message.
+// ---------------------------------------------------------------------------
+struct Error : public std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define TTSG_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            throw ::ttsg::Error(TTSG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define TTSG_CHECK(cond, code, msg)                                                      \
+    do {                                                                                 \
+        if (!(cond)) throw ::ttsg::Error((code), (msg));                                 \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Two-level strided index: x in [0, extent) is split as x0 = x % n0,
+// x1 = x / n0 and addressed as x0 * s0 + x1 * s1.  n0 >= extent means the
+// index is plain-strided (s1 unused).  Every operand of the contraction kernel
+// describes its row, column, reduction and batch index this way, which lets
+// one kernel walk the permuted core layouts of the TT sweeps without copies.
+// ---------------------------------------------------------------------------
+struct Idx2 {
+    int32_t n0;
+    int64_t s0;
+    int64_t s1;
+};
+
+__host__ __device__ inline Idx2 idx1(int64_t s) { return Idx2{0x7fffffff, s, 0}; }
+__host__ __device__ inline Idx2 idx2(int32_t n0, int64_t s0, int64_t s1) { return Idx2{n0, s0, s1}; }
+
+__device__ __forceinline__ int64_t idx_off(const Idx2& ix, int32_t x) {
+    if (x < ix.n0) return (int64_t)x * ix.s0;
+    int32_t x1 = x / ix.n0;
+    int32_t x0 = x - x1 * ix.n0;
+    return (int64_t)x0 * ix.s0 + (int64_t)x1 * ix.s1;
+}
+
+// Largest element offset an index of `extent` values can reach.
+inline int64_t idx_max(const Idx2& ix, int32_t extent) {
+    if (extent <= 0) return 0;
+    const int32_t x = extent - 1;
+    if (extent <= ix.n0) return (int64_t)x * ix.s0;
+    const int64_t inner = (int64_t)(ix.n0 - 1) * ix.s0;
+    return inner + (int64_t)(x / ix.n0) * ix.s1;
+}
+
+// Host-side launch check (enabled by TTSG_CHECK_BOUNDS=1): the byte range
+// [p, p + bytes) must lie inside the device allocation that contains p.
+void check_range(const void* p, size_t bytes, const char* what);
+bool bounds_checking();
+
+// C[b][m][n] = alpha * sum_k A[b][m][k] * B[b][k][n] + beta * C[b][m][n]
+struct ContractDesc {
+    int32_t M, N, K, batch;
+    Idx2 am, ak, bk, bn, cm, cn;
+    Idx2 ab, bb, cb;
+    double alpha, beta;
+};
+
+// Element types of the contraction kernels.
+enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
+
+// Launchers (contract.hip).  A/B are float64 for F64, float32 for F32, and
+// bf16 (uint16_t storage) for BF16; C is float64 for F64 and float32 otherwise.
+void contract(Prec p, const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st);
+
+// Element-wise helpers (misc.hip).
+void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);   // y = a x + b y
+void fill(int64_t n, double v, double* y, hipStream_t st);
+void copy_f64(int64_t n, const double* x, double* y, hipStream_t st);
+void convert_f64_f32(int64_t n, const double* x, float* y, hipStream_t st);
+void convert_f32_f64(int64_t n, const float* x, double* y, hipStream_t st);
+void convert_f64_bf16(int64_t n, const double* x, uint16_t* y, hipStream_t st);
+void scale_f64(int64_t n, double a, double* y, hipStream_t st);
+// y[i] = sum_t coef[t] * x_t[i] for up to 8 sources (coefficients in device memory).
+void lin_comb_dev(int64_t n, int32_t nterms, const double* const* xs, const double* coef_dev,
+                  const double* coef_sign, double* y, hipStream_t st);
+// Sum of squares of x into out[0] (float64, device), via partial sums in part (>= 1024 doubles).
+void sumsq(int64_t n, const double* x, double* part, double* out, hipStream_t st);
+// Copy a row-major rows x cols block with source/destination leading dimensions.
+void copy2d(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst, int64_t ldd,
+            hipStream_t st);
+// dst (cols x rows) = transpose(src (rows x cols)), both row-major with leading dims.
+void transpose2d(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst, int64_t ldd,
+                 hipStream_t st);
+
+// Dense FP64 linear algebra (la.hip).  Matrices are column-major with leading
+// dimension ld unless noted.
+// Householder QR of `batch` m x c matrices (m >= 1, c >= 1), in place: on exit
+// the upper triangle holds R (min(m,c) x c), below it the reflectors; tau
+// receives min(m,c) coefficients per matrix.  One workgroup per matrix.
+void qr_householder(int32_t batch, int32_t m, int32_t c, double* A, int32_t lda, int64_t strideA,
+                    double* tau, int64_t strideTau, hipStream_t st);
+// Form the explicit thin Q (m x k, k = min(m,c)) from the reflectors into Q.
+void qr_form_q(int32_t batch, int32_t m, int32_t c, const double* A, int32_t lda, int64_t strideA,
+               const double* tau, int64_t strideTau, double* Q, int32_t ldq, int64_t strideQ,
+               hipStream_t st);
+// One-sided Jacobi SVD of `batch` m x c matrices (m >= c): on exit A holds U*Sigma
+// (column-major), V (c x c) the right singular vectors, sig the singular values
+// (unsorted; the caller sorts).  One workgroup per matrix.
+void svd_jacobi(int32_t batch, int32_t m, int32_t c, double* A, int32_t lda, int64_t strideA,
+                double* V, int32_t ldv, int64_t strideV, double* sig, int64_t strideSig,
+                hipStream_t st);
+
+// The small host-side helper type for device buffers carved from a workspace.
+class Arena {
+  public:
+    Arena() = default;
+    void reset(char* base, size_t bytes) { base_ = base; cap_ = bytes; off_ = 0; }
+    void measure() { base_ = nullptr; cap_ = (size_t)-1; off_ = 0; }
+    template <typename T> T* get(size_t count) {
+        size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+        size_t o = off_;
+        off_ += bytes;
+        if (base_ != nullptr && off_ > cap_) throw Error(TTSG_ERR_WS, "workspace exhausted");
+        return base_ ? reinterpret_cast<T*>(base_ + o) : reinterpret_cast<T*>(o + 256);
+    }
+    size_t used() const { return off_; }
+    size_t mark() const { return off_; }
+    void release(size_t m) { off_ = m; }
+
+  private:
+    char* base_ = nullptr;
+    size_t cap_ = 0;
+    size_t off_ = 0;
+};
+
+// Scoped workspace: uses the caller's buffer when given and large enough,
+// otherwise allocates with hipMallocAsync on the stream and frees on exit.
+class Workspace {
+  public:
+    Workspace(void* ws, size_t ws_bytes, size_t need, hipStream_t st) : st_(st) {
+        if (ws != nullptr) {
+            TTSG_CHECK(ws_bytes >= need, TTSG_ERR_WS, "workspace too small");
+            ptr_ = ws;
+        } else if (need > 0) {
+            TTSG_HIP(hipMallocAsync(&ptr_, need, st));
+            owned_ = true;
+        }
+        arena.reset(static_cast<char*>(ptr_), need);
+    }
+    ~Workspace() {
+        if (owned_) (void)hipFreeAsync(ptr_, st_);
+    }
+    Arena arena;
+
+  private:
+    void* ptr_ = nullptr;
+    bool owned_ = false;
+    hipStream_t st_;
+};
+
+}  // namespace ttsg

@@ -1,0 +1,284 @@
+"""ctypes binding of libttsg (include/ttsg.h).
+
+Argument marshalling only: every numerical step runs in the HIP library.
+PyTorch provides device memory (float64 CUDA tensors) and the current HIP
+stream.  TT cores are passed as lists of contiguous float64 device tensors of
+shape (r_k, n_k, r_{k+1}); operator cores as (R_k, n_k, n_k, R_{k+1}).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libttsg.so")
+
+PREC_F64 = 0
+PREC_MIXED = 1
+PREC_BF16 = 2
+
+OK = 0
+NOT_CONVERGED = 1
+BREAKDOWN = 2
+
+_lib = None
+
+
+class TTSGError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libttsg.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise TTSGError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        L.ttsg_last_error.restype = ctypes.c_char_p
+        L.ttsg_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+EXPORTED = [
+    "ttsg_last_error", "ttsg_version", "ttsg_matvec", "ttsg_kr_sketch", "ttsg_stta_sketch",
+    "ttsg_round_rand", "ttsg_round_svd", "ttsg_sgmres_solve", "ttsg_true_residual", "ttsg_dot",
+]
+
+
+class SgmresOpts(ctypes.Structure):
+    _fields_ = [
+        ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32), ("q", ctypes.c_int32),
+        ("maxrank", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
+        ("tol", ctypes.c_double), ("round_tol", ctypes.c_double), ("final_tol", ctypes.c_double),
+        ("stop_safety", ctypes.c_double), ("rcond", ctypes.c_double),
+    ]
+
+
+class SgmresInfo(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32), ("cycles", ctypes.c_int32), ("max_rank", ctypes.c_int32),
+        ("status", ctypes.c_int32), ("true_residual", ctypes.c_double),
+        ("sketched_residual", ctypes.c_double),
+        ("sketched_history", ctypes.POINTER(ctypes.c_double)),
+        ("rank_history", ctypes.POINTER(ctypes.c_int32)),
+        ("true_history", ctypes.POINTER(ctypes.c_double)),
+        ("phase_seconds", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+PHASES = ["kr_sketch", "inner_products", "stta_sketch", "stta_recover", "tt_svd", "least_squares",
+          "final_solution", "other"]
+
+
+def _i32(vals) -> ctypes.Array:
+    return (ctypes.c_int32 * len(vals))(*[int(v) for v in vals])
+
+
+def _ptrs(tensors) -> ctypes.Array:
+    for t in tensors:
+        if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+            raise TTSGError("cores must be contiguous float64 CUDA tensors")
+    return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        msg = lib().ttsg_last_error().decode()
+        raise TTSGError(f"{what} failed ({rc}): {msg}")
+    return rc
+
+
+def ranks_of(cores: Sequence[torch.Tensor]) -> List[int]:
+    return [int(c.shape[0]) for c in cores] + [int(cores[-1].shape[2])]
+
+
+def sizes_of(cores: Sequence[torch.Tensor]) -> List[int]:
+    return [int(c.shape[1]) for c in cores]
+
+
+def op_ranks(cores: Sequence[torch.Tensor]) -> List[int]:
+    return [int(c.shape[0]) for c in cores] + [int(cores[-1].shape[3])]
+
+
+def to_device(arrays, device="cuda") -> List[torch.Tensor]:
+    return [torch.as_tensor(a, dtype=torch.float64).contiguous().to(device) for a in arrays]
+
+
+# ----------------------------------------------------------------------------
+# Problem setup: Kronecker-sum operators in TT-matrix form (Sec. 2.2, Sec. 5.1)
+# ----------------------------------------------------------------------------
+
+def kron_sum_operator(terms, device="cuda") -> List[torch.Tensor]:
+    """TT-matrix cores of sum_t sum_k (I x .. x terms[t][k] x .. x I).
+
+    Bond state 0 means "nothing placed yet", state t+1 "the matrix of term t has
+    been placed"; the last core folds all states into one (rank len(terms)+1)."""
+    import numpy as np
+    nterm = len(terms)
+    d = len(terms[0])
+    R = nterm + 1
+    cores = []
+    for k in range(d):
+        n = terms[0][k].shape[0]
+        eye = np.eye(n)
+        left = 1 if k == 0 else R
+        right = 1 if k == d - 1 else R
+        D = np.zeros((left, n, n, right))
+        if d == 1:
+            D[0, :, :, 0] = sum(t[k] for t in terms)
+        elif k == d - 1:
+            D[0, :, :, 0] = sum(t[k] for t in terms)
+            for t in range(nterm):
+                D[t + 1, :, :, 0] = eye
+        else:
+            D[0, :, :, 0] = eye
+            for t in range(nterm):
+                D[0, :, :, t + 1] = terms[t][k]
+                if k > 0:
+                    D[t + 1, :, :, t + 1] = eye
+        cores.append(D)
+    return to_device(cores, device)
+
+
+# ----------------------------------------------------------------------------
+# Entry points
+# ----------------------------------------------------------------------------
+
+def matvec(A: Sequence[torch.Tensor], x: Sequence[torch.Tensor], transpose: bool = False) -> List[torch.Tensor]:
+    d = len(x)
+    n, r, R = sizes_of(x), ranks_of(x), op_ranks(A)
+    y = [torch.empty((r[k] * R[k], n[k], r[k + 1] * R[k + 1]), dtype=torch.float64, device=x[0].device)
+         for k in range(d)]
+    _check(lib().ttsg_matvec(d, _i32(n), _i32(R), _ptrs(A), _i32(r), _ptrs(x), int(transpose), _ptrs(y),
+                             _stream()), "ttsg_matvec")
+    return y
+
+
+def kr_sketch(S: Sequence[torch.Tensor], x: Sequence[torch.Tensor], A: Optional[Sequence[torch.Tensor]] = None,
+              precision: int = PREC_F64) -> torch.Tensor:
+    d = len(x)
+    s = int(S[0].shape[0])
+    w = torch.empty(s, dtype=torch.float64, device=x[0].device)
+    Rp = _i32(op_ranks(A)) if A is not None else None
+    Ap = _ptrs(A) if A is not None else None
+    _check(lib().ttsg_kr_sketch(d, _i32(sizes_of(x)), s, _ptrs(S), Rp, Ap, _i32(ranks_of(x)), _ptrs(x),
+                                ctypes.c_void_p(w.data_ptr()), precision, None, ctypes.c_size_t(0), _stream()),
+           "ttsg_kr_sketch")
+    return w
+
+
+def stta_sketch(x, X, Y, rx, rho, A=None, precision: int = PREC_F64):
+    """Psi (d cores rho_k x n_k x rx_{k+1}) and Omega (d-1 matrices rho_b x rx_b)."""
+    d = len(x)
+    n = sizes_of(x)
+    dev = x[0].device
+    Psi = [torch.empty((rho[k], n[k], rx[k + 1]), dtype=torch.float64, device=dev) for k in range(d)]
+    Om = [torch.empty((rho[b], rx[b]), dtype=torch.float64, device=dev) for b in range(1, d)]
+    Rp = _i32(op_ranks(A)) if A is not None else None
+    Ap = _ptrs(A) if A is not None else None
+    _check(lib().ttsg_stta_sketch(d, _i32(n), _i32(rho), _ptrs(Y), _i32(rx), _ptrs(X), Rp, Ap, _i32(ranks_of(x)),
+                                  _ptrs(x), _ptrs(Psi), _ptrs(Om), precision, None, ctypes.c_size_t(0), _stream()),
+           "ttsg_stta_sketch")
+    return Psi, Om
+
+
+def _trim(cores, r):
+    return [c.reshape(-1)[: r[k] * c.shape[1] * r[k + 1]].reshape(r[k], c.shape[1], r[k + 1]).clone()
+            for k, c in enumerate(cores)]
+
+
+def round_rand(x, X, Y, rx, rho, tol: float, maxrank: int = 0, rcond: float = 1e-12,
+               precision: int = PREC_F64) -> List[torch.Tensor]:
+    d = len(x)
+    n = sizes_of(x)
+    dev = x[0].device
+    out = [torch.empty((rx[k], n[k], rx[k + 1]), dtype=torch.float64, device=dev) for k in range(d)]
+    out_r = (ctypes.c_int32 * (d + 1))()
+    _check(lib().ttsg_round_rand(d, _i32(n), _i32(ranks_of(x)), _ptrs(x), _i32(rho), _ptrs(Y), _i32(rx), _ptrs(X),
+                                 ctypes.c_double(tol), int(maxrank), ctypes.c_double(rcond), _ptrs(out), out_r,
+                                 precision, None, ctypes.c_size_t(0), _stream()), "ttsg_round_rand")
+    return _trim(out, list(out_r))
+
+
+def round_svd(x, tol: float, maxrank: int = 0) -> List[torch.Tensor]:
+    d = len(x)
+    out = [torch.empty_like(c) for c in x]
+    out_r = (ctypes.c_int32 * (d + 1))()
+    _check(lib().ttsg_round_svd(d, _i32(sizes_of(x)), _i32(ranks_of(x)), _ptrs(x), ctypes.c_double(tol),
+                                int(maxrank), _ptrs(out), out_r, None, ctypes.c_size_t(0), _stream()),
+           "ttsg_round_svd")
+    return _trim(out, list(out_r))
+
+
+def dot(x, y) -> float:
+    out = ctypes.c_double(0.0)
+    _check(lib().ttsg_dot(len(x), _i32(sizes_of(x)), _i32(ranks_of(x)), _ptrs(x), _i32(ranks_of(y)), _ptrs(y),
+                          ctypes.byref(out), None, ctypes.c_size_t(0), _stream()), "ttsg_dot")
+    return out.value
+
+
+def true_residual(A, b, x) -> float:
+    out = ctypes.c_double(0.0)
+    _check(lib().ttsg_true_residual(len(x), _i32(sizes_of(x)), _i32(op_ranks(A)), _ptrs(A), _i32(ranks_of(b)),
+                                    _ptrs(b), _i32(ranks_of(x)), _ptrs(x), ctypes.byref(out), None,
+                                    ctypes.c_size_t(0), _stream()), "ttsg_true_residual")
+    return out.value
+
+
+@dataclass
+class SolveResult:
+    x: List[torch.Tensor]
+    status: int
+    iterations: int
+    cycles: int
+    true_residual: float
+    sketched_residual: float
+    max_rank: int
+    sketched_history: List[float] = field(default_factory=list)
+    rank_history: List[int] = field(default_factory=list)
+    true_history: List[float] = field(default_factory=list)
+    phase_seconds: dict = field(default_factory=dict)
+
+
+def sgmres_solve(A, b, S, X, Y, rx, rho, *, maxit: int, tol: float, q: int = 1, round_tol: float = 1e-7,
+                 maxrank: int = 0, restart: int = 0, final_tol: float = 0.0, stop_safety: float = 0.1,
+                 rcond: float = 1e-12, precision: int = PREC_F64, max_cycles: int = 50,
+                 phase_timing: bool = False) -> SolveResult:
+    d = len(b)
+    n = sizes_of(b)
+    dev = b[0].device
+    opts = SgmresOpts(maxit=maxit, restart=restart, q=q, maxrank=maxrank, precision=precision,
+                      max_cycles=max_cycles, tol=tol, round_tol=round_tol, final_tol=final_tol,
+                      stop_safety=stop_safety, rcond=rcond)
+    sh = (ctypes.c_double * maxit)()
+    rh = (ctypes.c_int32 * maxit)()
+    th = (ctypes.c_double * max_cycles)()
+    ph = (ctypes.c_double * 8)()
+    info = SgmresInfo(sketched_history=sh, rank_history=rh, true_history=th,
+                      phase_seconds=ph if phase_timing else None)
+    x = [torch.zeros((rx[k], n[k], rx[k + 1]), dtype=torch.float64, device=dev) for k in range(d)]
+    xr = (ctypes.c_int32 * (d + 1))()
+    rc = lib().ttsg_sgmres_solve(d, _i32(n), _i32(op_ranks(A)), _ptrs(A), _i32(ranks_of(b)), _ptrs(b),
+                                 int(S[0].shape[0]), _ptrs(S), _i32(rho), _ptrs(Y), _i32(rx), _ptrs(X),
+                                 ctypes.byref(opts), _ptrs(x), xr, ctypes.byref(info), None, ctypes.c_size_t(0),
+                                 _stream())
+    _check(rc, "ttsg_sgmres_solve")
+    it = info.iterations
+    return SolveResult(
+        x=_trim(x, list(xr)), status=rc, iterations=it, cycles=info.cycles,
+        true_residual=info.true_residual, sketched_residual=info.sketched_residual, max_rank=info.max_rank,
+        sketched_history=[sh[i] for i in range(min(it, maxit))],
+        rank_history=[rh[i] for i in range(min(it, maxit))],
+        true_history=[th[i] for i in range(min(info.cycles, max_cycles))],
+        phase_seconds={PHASES[i]: ph[i] for i in range(8)} if phase_timing else {},
+    )
