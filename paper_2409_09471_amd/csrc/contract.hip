@@ -14,8 +14,8 @@
 //   FP32: v_mfma_f32_16x16x4_f32      (A, B, C in float32)
 //   BF16: v_mfma_f32_16x16x16_bf16    (A, B in bfloat16, C in float32)
 // Operand layout of the 16x16xK forms: lane l supplies row (l % 16) of A and
-// column (l % 16) of B for the k-group (l / 16); the accumulator holds rows
-// 4*(l/16) + {0..3} of column (l % 16).
+// column (l % 16) of B for the k-group (l / 16); the accumulator of lane l holds
+// column (l % 16), rows given by Traits<T>::acc_row.
 #include <cstdlib>
 
 #include "ttsg_internal.h"
@@ -31,20 +31,26 @@ constexpr int BM = 64;
 constexpr int BN = 64;
 
 template <typename T> struct Traits;
+// Row of accumulator register r held by lane group g (= lane / 16):
+// the f64 form interleaves (row g + 4 r), the f32/bf16 forms keep four
+// consecutive rows per group (row 4 g + r).
 template <> struct Traits<double> {
     using acc4 = d4_t;
     using out_t = double;
     static constexpr int BK = 16;
+    static __device__ __forceinline__ int acc_row(int g, int r) { return g + 4 * r; }
 };
 template <> struct Traits<float> {
     using acc4 = f4_t;
     using out_t = float;
     static constexpr int BK = 16;
+    static __device__ __forceinline__ int acc_row(int g, int r) { return 4 * g + r; }
 };
 template <> struct Traits<uint16_t> {
     using acc4 = f4_t;
     using out_t = float;
     static constexpr int BK = 32;
+    static __device__ __forceinline__ int acc_row(int g, int r) { return 4 * g + r; }
 };
 
 template <typename T>
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const T* 
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                int row = m0 + wm + 16 * i + 4 * lg + r;
+                int row = m0 + wm + 16 * i + Traits<T>::acc_row(lg, r);
                 int col = n0 + wn + 16 * j + lr;
                 if (row < d.M && col < d.N) {
                     int64_t off = idx_off(d.cm, row) + idx_off(d.cn, col);
