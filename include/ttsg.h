@@ -210,6 +210,31 @@ int ttsg_dot(int32_t d, const int32_t* n, const int32_t* rxr, const double* cons
              const int32_t* ryr, const double* const* y, double* out,
              void* ws, size_t ws_bytes, ttsg_stream_t stream);
 
+/* ------------------------------------------------------------------------- */
+/* Measurement: per-kernel-class counters.  While enabled, every contraction */
+/* and factorization launch is bracketed by HIP events recorded on the       */
+/* stream it is launched on; ttsg_stats_read synchronizes those events and    */
+/* returns, per class, the launch count, the algorithmic flops (2*M*N*K*batch */
+/* per contraction; the textbook counts for QR and one Jacobi sweep), the     */
+/* operand bytes (A + B + C, an operand shared across a batch counted once)  */
+/* and the summed kernel durations.  Measurement adds an event pair per      */
+/* launch; it is meant for benchmarking, not for production solves.          */
+/* ------------------------------------------------------------------------- */
+enum { TTSG_ST_CONTRACT_F64 = 0, TTSG_ST_CONTRACT_F32 = 1, TTSG_ST_CONTRACT_BF16 = 2,
+       TTSG_ST_QR = 3, TTSG_ST_SVD = 4, TTSG_ST_CLASSES = 8 };
+
+typedef struct {
+    int64_t launches[TTSG_ST_CLASSES];
+    double flops[TTSG_ST_CLASSES];
+    double bytes[TTSG_ST_CLASSES];
+    double seconds[TTSG_ST_CLASSES];
+} ttsg_stats;
+
+/* on != 0: clear the counters and start recording; on == 0: stop recording. */
+int ttsg_stats_enable(int32_t on);
+/* Resolve the recorded events (synchronizing them) into *out and clear. */
+int ttsg_stats_read(ttsg_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

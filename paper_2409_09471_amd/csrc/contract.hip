@@ -188,6 +188,18 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         check_range(B, eb * sizeof(T), "contract B");
         check_range(C, ec * sizeof(out_t), "contract C");
     }
+    const int cls = sizeof(T) == 8 ? TTSG_ST_CONTRACT_F64 : (sizeof(T) == 4 ? TTSG_ST_CONTRACT_F32 : TTSG_ST_CONTRACT_BF16);
+    double flops = 0.0, bytes = 0.0;
+    if (stats_on()) {
+        using out_t = typename Traits<T>::out_t;
+        const double nb = (double)d.batch;
+        flops = 2.0 * d.M * (double)d.N * d.K * nb;
+        const double ua = (double)d.M * d.K * (d.ab.s0 == 0 ? 1.0 : nb);
+        const double ub = (double)d.K * d.N * (d.bb.s0 == 0 ? 1.0 : nb);
+        const double uc = (double)d.M * d.N * nb * (d.beta != 0.0 ? 2.0 : 1.0);
+        bytes = (ua + ub) * sizeof(T) + uc * sizeof(out_t);
+    }
+    StatScope scope(cls, flops, bytes, st);
     dim3 block(256);
     const int gx = (d.N + BN - 1) / BN;
     const int gy = (d.M + BM - 1) / BM;

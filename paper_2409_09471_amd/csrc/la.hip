@@ -192,6 +192,9 @@ void qr_householder(int32_t batch, int32_t m, int32_t c, double* A, int32_t lda,
         check_range(A, ((int64_t)(batch - 1) * strideA + (int64_t)(c - 1) * lda + m) * 8, "qr A");
         check_range(tau, ((int64_t)(batch - 1) * strideTau + std::min(m, c)) * 8, "qr tau");
     }
+    const double kq = std::min(m, c);
+    StatScope scope(TTSG_ST_QR, batch * (2.0 * m * c * kq - 2.0 / 3.0 * kq * kq * kq),
+                    batch * 16.0 * m * c, st);
     hipLaunchKernelGGL(k_qr, dim3(batch), dim3(LA_THREADS), 0, st, m, c, A, lda, strideA, tau, strideTau);
     TTSG_HIP(hipGetLastError());
 }
@@ -205,6 +208,9 @@ void qr_form_q(int32_t batch, int32_t m, int32_t c, const double* A, int32_t lda
         check_range(A, ((int64_t)(batch - 1) * strideA + (int64_t)(k - 1) * lda + m) * 8, "form_q A");
         check_range(Q, ((int64_t)(batch - 1) * strideQ + (int64_t)(k - 1) * ldq + m) * 8, "form_q Q");
     }
+    const double kq = std::min(m, c);
+    StatScope scope(TTSG_ST_QR, batch * (4.0 * m * kq * kq - 4.0 / 3.0 * kq * kq * kq),
+                    batch * 16.0 * m * kq, st);
     hipLaunchKernelGGL(k_form_q, dim3(batch), dim3(LA_THREADS), 0, st, m, c, A, lda, strideA, tau, strideTau, Q,
                        ldq, strideQ);
     TTSG_HIP(hipGetLastError());
@@ -220,6 +226,9 @@ void svd_jacobi(int32_t batch, int32_t m, int32_t c, double* A, int32_t lda, int
         check_range(V, ((int64_t)(batch - 1) * strideV + (int64_t)(c - 1) * ldv + c) * 8, "jacobi V");
         check_range(sig, ((int64_t)(batch - 1) * strideSig + c) * 8, "jacobi sig");
     }
+    // one sweep of c(c-1)/2 rotations, each three dot products and two
+    // rotated column pairs (m and c long)
+    StatScope scope(TTSG_ST_SVD, batch * 0.5 * c * (c - 1.0) * (12.0 * m + 6.0 * c), batch * 16.0 * m * c, st);
     hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(LA_THREADS), 0, st, m, c, A, lda, strideA, V, ldv, strideV,
                        sig, strideSig, 60, 1e-15);
     TTSG_HIP(hipGetLastError());

@@ -427,14 +427,21 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             Xv[k] = Xp_[k];
         }
     }
+    // Precision map: the Khatri-Rao column w_k, S r0, ||S b|| and the stored
+    // STTA sketches of the basis vectors (which build the final solution) are
+    // FP64; the STTA sketch of A v_k and the coefficients h (which only shape
+    // the next basis vector) run in the working precision p_.
     SketchOperands so_op, so_plain;
-    so_op.p = so_plain.p = p_;
+    so_op.p = p_;
+    so_plain.p = Prec::F64;
     so_op.n = so_plain.n = n;
     so_op.d = so_plain.d = d;
     so_op.rho = so_plain.rho = in_.rho;
     so_op.rx = so_plain.rx = in_.rx;
-    so_op.Y = so_plain.Y = Yv;
-    so_op.X = so_plain.X = Xv;
+    so_op.Y = Yv;
+    so_op.X = Xv;
+    so_plain.Y.assign(in_.Y.begin(), in_.Y.end());
+    so_plain.X.assign(in_.X.begin(), in_.X.end());
     so_op.R = in_.R;
     so_op.D = Dv;
     so_plain.R = R1;
@@ -448,7 +455,8 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     auto sketch_slot = [&](int slot, double* out) {
         std::vector<double*> psi, om;
         sk_ptrs(out, psi, om);
-        stta_sketch(so_plain, slot_r_[slot], slot_ops(slot), psi.data(), om.data(), scratch_, st_);
+        std::vector<const void*> c64(slots_[slot].begin(), slots_[slot].end());
+        stta_sketch(so_plain, slot_r_[slot], c64, psi.data(), om.data(), scratch_, st_);
     };
     auto read = [&](const double* dev) {
         double h = 0.0;
@@ -487,7 +495,8 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         } else {
             for (int mu = 0; mu < d; ++mu) bops[mu] = in_.b[mu];
         }
-        kr_sketch_run(p_, d, n, s, R1, Sv, in_.rb, bops, z_, scratch_, st_);
+        std::vector<const void*> b64(in_.b.begin(), in_.b.end()), S64(in_.S.begin(), in_.S.end());
+        kr_sketch_run(Prec::F64, d, n, s, R1, S64, in_.rb, b64, z_, scratch_, st_);
         sumsq(s, z_, lsres_, scal_, st_);
         scratch_.release(mk);
     }
@@ -565,7 +574,10 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         scale_f64((int64_t)slot_r_[s0][0] * n[0] * slot_r_[s0][1], 1.0 / beta, slots_[s0][0], st_);
         to_lp(s0);
         // S r0 = beta * S v1
-        kr_sketch_run(p_, d, n, s, R1, Sv, slot_r_[s0], slot_ops(s0), z_, scratch_, st_);
+        {
+            std::vector<const void*> S64(in_.S.begin(), in_.S.end()), c64(slots_[s0].begin(), slots_[s0].end());
+            kr_sketch_run(Prec::F64, d, n, s, R1, S64, slot_r_[s0], c64, z_, scratch_, st_);
+        }
         scale_f64(s, beta, z_, st_);
         sketch_slot(s0, sketches_);
         window.push_back(s0);
@@ -577,7 +589,11 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             const int vk = window.back();
             // 1) w_k = S A v_k
             auto t1 = now();
-            kr_sketch_run(p_, d, n, s, in_.R, SAv, slot_r_[vk], slot_ops(vk), W_ + (int64_t)k * s, scratch_, st_);
+            {
+                std::vector<const void*> SA64(SA64_.begin(), SA64_.end());
+                std::vector<const void*> c64(slots_[vk].begin(), slots_[vk].end());
+                kr_sketch_run(Prec::F64, d, n, s, in_.R, SA64, slot_r_[vk], c64, W_ + (int64_t)k * s, scratch_, st_);
+            }
             add_phase(TTSG_PH_KR, t1);
             // 2) h_{i,k} for the window
             t1 = now();
@@ -616,7 +632,8 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
                 std::vector<double*> psi, om;
                 sk_ptrs(skC_, psi, om);
                 std::vector<const double*> cpsi(psi.begin(), psi.end()), com(om.begin(), om.end());
-                stta_recover(d, n, in_.rho, in_.rx, cpsi, com, o.rcond, slots_[fs], slot_r_[fs], scratch_, st_);
+                const double rc = p_ == Prec::F64 ? o.rcond : std::max(o.rcond, 1e-6);
+                stta_recover(d, n, in_.rho, in_.rx, cpsi, com, rc, slots_[fs], slot_r_[fs], scratch_, st_);
             }
             add_phase(TTSG_PH_RECOVER, t1);
             t1 = now();

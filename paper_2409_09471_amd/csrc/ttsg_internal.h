@@ -71,6 +71,19 @@ inline int64_t idx_max(const Idx2& ix, int32_t extent) {
 void check_range(const void* p, size_t bytes, const char* what);
 bool bounds_checking();
 
+// Launch measurement (stats.hip): when enabled, StatScope records a HIP event
+// pair around one launch on `st`, tagged with a class and its work counts.
+bool stats_on();
+struct StatScope {
+    StatScope(int cls, double flops, double bytes, hipStream_t st);
+    ~StatScope();
+    int cls_;
+    double flops_, bytes_;
+    hipStream_t st_;
+    void* a_ = nullptr;
+    void* b_ = nullptr;
+};
+
 // C[b][m][n] = alpha * sum_k A[b][m][k] * B[b][k][n] + beta * C[b][m][n]
 struct ContractDesc {
     int32_t M, N, K, batch;

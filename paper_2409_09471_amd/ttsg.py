@@ -48,7 +48,30 @@ def lib():
 EXPORTED = [
     "ttsg_last_error", "ttsg_version", "ttsg_matvec", "ttsg_kr_sketch", "ttsg_stta_sketch",
     "ttsg_round_rand", "ttsg_round_svd", "ttsg_sgmres_solve", "ttsg_true_residual", "ttsg_dot",
+    "ttsg_stats_enable", "ttsg_stats_read",
 ]
+
+STAT_CLASSES = {0: "contract_f64", 1: "contract_f32", 2: "contract_bf16", 3: "qr", 4: "svd_jacobi"}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 8), ("flops", ctypes.c_double * 8),
+                ("bytes", ctypes.c_double * 8), ("seconds", ctypes.c_double * 8)]
+
+
+def stats_enable(on: bool = True) -> None:
+    _check(lib().ttsg_stats_enable(int(on)), "ttsg_stats_enable")
+
+
+def stats_read() -> dict:
+    st = Stats()
+    _check(lib().ttsg_stats_read(ctypes.byref(st)), "ttsg_stats_read")
+    out = {}
+    for c, name in STAT_CLASSES.items():
+        if st.launches[c]:
+            out[name] = dict(launches=int(st.launches[c]), flops=st.flops[c], bytes=st.bytes[c],
+                             seconds=st.seconds[c])
+    return out
 
 
 class SgmresOpts(ctypes.Structure):
