@@ -30,6 +30,11 @@ __global__ void k_gather_cols(int rows, int k, const double* __restrict__ src, i
     }
 }
 
+__global__ void k_eye(int c, double* __restrict__ I) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < c * c; e += gridDim.x * blockDim.x)
+        I[e] = (e / c == e % c) ? 1.0 : 0.0;
+}
+
 inline int nb(int64_t total) {
     int64_t b = (total + 255) / 256;
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, 65536));
@@ -38,6 +43,20 @@ inline int nb(int64_t total) {
 void extract_r(int k, int c, const double* A, int lda, double* R, int ldr, hipStream_t st) {
     hipLaunchKernelGGL(k_extract_r, dim3(nb((int64_t)k * c)), dim3(256), 0, st, k, c, A, lda, R, ldr);
     TTSG_HIP(hipGetLastError());
+}
+
+void eye(int c, double* I, hipStream_t st) {
+    hipLaunchKernelGGL(k_eye, dim3(nb((int64_t)c * c)), dim3(256), 0, st, c, I);
+    TTSG_HIP(hipGetLastError());
+}
+
+// SVD of a c x c column-major matrix in place (LDS kernel when it fits).
+void svd_small(int c, double* A, double* V, double* sig, hipStream_t st) {
+    if (jacobi_lds_fits(c, c)) {
+        svd_jacobi_batched({JacobiJob{c, c, c, A, V, sig}}, st);
+    } else {
+        svd_jacobi(1, c, c, A, c, 0, V, c, 0, sig, 0, st);
+    }
 }
 
 void gather_cols(int rows, int k, const double* src, int lds, double* dst, int ldd, const int* perm,
@@ -151,11 +170,23 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
     // 1) right-to-left QR orthogonalization
     for (int mu = d - 1; mu >= 1; --mu) {
         const int rl = r[mu], rr = r[mu + 1], m = n[mu] * rr, c = rl;
-        copy_f64((int64_t)m * c, w[mu], A, st);            // column-major m x c == row-major core
-        qr_householder(1, m, c, A, m, 0, tau, 0, st);
         const int k = std::min(m, c);
-        qr_form_q(1, m, c, A, m, 0, tau, 0, w[mu], m, 0, st);  // Q^T as the new row-major core
-        extract_r(k, c, A, m, Rm, k, st);
+        if (tsqr_fits(m, c)) {
+            // the row-major core is the column-major m x c matrix C^T
+            const size_t mk = ar.mark();
+            TsqrPlan plan;
+            plan.factor(m, c, w[mu], m, ar, st);
+            double* I = ar.get<double>((int64_t)c * c);
+            eye(c, I, st);
+            copy_f64((int64_t)c * c, plan.R, Rm, st);          // R: c x c, ld c (k == c)
+            plan.apply(c, I, c, w[mu], m, false, ar, st);      // Q^T as the new row-major core
+            ar.release(mk);
+        } else {
+            copy_f64((int64_t)m * c, w[mu], A, st);            // column-major m x c == row-major core
+            qr_householder(1, m, c, A, m, 0, tau, 0, st);
+            qr_form_q(1, m, c, A, m, 0, tau, 0, w[mu], m, 0, st);  // Q^T as the new row-major core
+            extract_r(k, c, A, m, Rm, k, st);
+        }
         const int rll = r[mu - 1], nl = n[mu - 1];
         // T (rll*nl x k) = W_{mu-1} (rll*nl x rl) * R^T
         // B[l][kk] = R[kk][l] = Rm[l*k + kk]: the column-major R read row-major
@@ -183,11 +214,19 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
         int k;
         std::vector<int> perm;
         if (m >= c) {
+            const bool tsqr = tsqr_fits(m, c);
+            TsqrPlan plan;
+            const size_t mk = ar.mark();
             transpose2d(m, c, w[mu], c, A, m, st);           // column-major m x c
-            qr_householder(1, m, c, A, m, 0, tau, 0, st);
-            qr_form_q(1, m, c, A, m, 0, tau, 0, Q, m, 0, st);
-            extract_r(c, c, A, m, Rm, c, st);
-            svd_jacobi(1, c, c, Rm, c, 0, V, c, 0, sig, 0, st);
+            if (tsqr) {
+                plan.factor(m, c, A, m, ar, st);
+                copy_f64((int64_t)c * c, plan.R, Rm, st);
+            } else {
+                qr_householder(1, m, c, A, m, 0, tau, 0, st);
+                qr_form_q(1, m, c, A, m, 0, tau, 0, Q, m, 0, st);
+                extract_r(c, c, A, m, Rm, c, st);
+            }
+            svd_small(c, Rm, V, sig, st);
             hsig.assign(c, 0.0);
             TTSG_HIP(hipMemcpyAsync(hsig.data(), sig, c * sizeof(double), hipMemcpyDeviceToHost, st));
             TTSG_HIP(hipStreamSynchronize(st));
@@ -209,8 +248,13 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             hold_d.push_back(sv);
             upload_perm(hold_i.back(), hold_d[hold_d.size() - 2], perm_dev, fac_dev, st);
             gather_cols(c, k, Rm, c, T, c, perm_dev, fac_dev, st);
-            // new core (row-major m x k) = Q (column-major m x c) * Uk
-            gemm_cm_cm(m, k, c, Q, m, T, c, w[mu], k, st);
+            // new core (row-major m x k) = Q (m x c) * Uk
+            if (tsqr) {
+                plan.apply(k, T, c, w[mu], k, true, ar, st);
+            } else {
+                gemm_cm_cm(m, k, c, Q, m, T, c, w[mu], k, st);
+            }
+            ar.release(mk);
             // SVt (row-major k x c) = column-major c x k of V[:, perm] * sigma
             TTSG_HIP(hipMemcpyAsync(fac_dev, hold_d.back().data(), k * sizeof(double), hipMemcpyHostToDevice, st));
             gather_cols(c, k, V, c, QV, c, perm_dev, fac_dev, st);
@@ -222,7 +266,7 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             extract_r(m, m, A, c, Rm, m, st);                    // R2: m x m (column-major)
             // R2^T column-major = transpose of R2
             transpose2d(m, m, Rm, m, T, m, st);                  // T = R2 row-major == R2^T column-major
-            svd_jacobi(1, m, m, T, m, 0, V, m, 0, sig, 0, st);   // R2^T = U2 S V2^T
+            svd_small(m, T, V, sig, st);                         // R2^T = U2 S V2^T
             hsig.assign(m, 0.0);
             TTSG_HIP(hipMemcpyAsync(hsig.data(), sig, m * sizeof(double), hipMemcpyDeviceToHost, st));
             TTSG_HIP(hipStreamSynchronize(st));
@@ -296,7 +340,16 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         permb[b] = ar.get<int>(c);
         facb[b] = ar.get<double>(2 * (int64_t)c);
         transpose2d(m, c, Omega[b - 1], c, Ab[b], m, st);
-        svd_jacobi(1, m, c, Ab[b], m, 0, Vb[b], c, 0, Sb[b], 0, st);
+    }
+    {
+        std::vector<JacobiJob> jobs;
+        for (int b = 1; b <= d - 1; ++b) {
+            if (jacobi_lds_fits(rho[b], rx[b]))
+                jobs.push_back(JacobiJob{rho[b], rx[b], rho[b], Ab[b], Vb[b], Sb[b]});
+            else
+                svd_jacobi(1, rho[b], rx[b], Ab[b], rho[b], 0, Vb[b], rx[b], 0, Sb[b], 0, st);
+        }
+        if (!jobs.empty()) svd_jacobi_batched(jobs, st);
     }
     for (int mu = 0; mu < d; ++mu) maxT = std::max<int64_t>(maxT, (int64_t)rx[mu] * n[mu] * rx[mu + 1]);
     double* T = ar.get<double>(maxT);

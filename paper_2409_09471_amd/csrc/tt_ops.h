@@ -91,6 +91,38 @@ void inner_run(Prec p, int d, const int* n, const std::vector<int>& R, const std
                const std::vector<const void*>& z, double* out_dev, Arena& ar, hipStream_t st);
 
 // ---------------------------------------------------------------------------
+// LDS-resident factorizations (la_lds.hip)
+// ---------------------------------------------------------------------------
+struct JacobiJob {
+    int m, c, lda;        // column-major m x c (m >= c), leading dimension lda
+    double* A;            // in: matrix; out: U * Sigma
+    double* V;            // out: c x c right singular vectors (column-major, ld c)
+    double* sig;          // out: c singular values (unsorted)
+};
+bool jacobi_lds_fits(int m, int c);
+// One launch for up to 32 matrices (more are split into several launches).
+void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st);
+
+bool tsqr_fits(int m, int c);
+// Tall-skinny QR of a column-major m x c matrix (m >= c, c <= 64) by a tree of
+// LDS Householder leaves.  factor() leaves R (c x c, column-major, ld c, zero
+// below the diagonal) in `R`; apply() writes Q * B (m x k) for a c x k matrix B.
+struct TsqrPlan {
+    struct Level {
+        int rows, nleaves;
+        double* refl;
+        double* tau;
+        double* stack;
+    };
+    int m = 0, c = 0;
+    std::vector<Level> levels;
+    double* R = nullptr;
+    void factor(int m, int c, const double* A, int lda, Arena& ar, hipStream_t st);
+    void apply(int k, const double* B, int ldb, double* Out, int ldo, bool out_rowmajor, Arena& ar,
+               hipStream_t st) const;
+};
+
+// ---------------------------------------------------------------------------
 // Rounding pipeline (rounding.hip), all FP64.
 // ---------------------------------------------------------------------------
 // TT-SVD rounding in place: cores `w` (capacity per core given by cap_elems)

@@ -177,3 +177,45 @@ def test_c1_fp64_solution_against_dst():
     assert osol.true_residual(A, w.b, x) <= 1e-6
     assert abs(res.true_residual - osol.true_residual(A, w.b, x)) < 1e-8
     assert np.linalg.norm(ott.full(x) - xe) <= 1e-5 * np.linalg.norm(xe)
+
+
+def _decaying_tt(rng, ns, terms, rate, rank_each=1):
+    acc = None
+    for j in range(terms):
+        t = ott.scale(syn.gaussian_tt(rng, ns, [1] + [rank_each] * (len(ns) - 1) + [1]), rate ** j)
+        acc = t if acc is None else ott.add(acc, t)
+    return acc
+
+
+@pytest.mark.parametrize("n,terms,rank_each,tol,maxrank", [
+    (64, 16, 4, 1e-7, 0),        # unfoldings 4096 x 64: three TSQR levels
+    (64, 20, 3, 1e-3, 32),       # rank cap active
+    (40, 9, 5, 0.0, 0),          # ragged leaves (m = 40 * 45)
+])
+def test_round_svd_large(n, terms, rank_each, tol, maxrank):
+    d = 4
+    rng = np.random.default_rng(11)
+    x = _decaying_tt(rng, [n] * d, terms, 0.5, rank_each)
+    y = ttsg.round_svd(ttsg.to_device(x, DEV), tol, maxrank)
+    ref = ott.round_svd(x, tol, maxrank if maxrank else None)
+    assert ttsg.ranks_of(y) == ott.ranks(ref)
+    assert tt_rel(host(y), ref) < 1e-9 + 1e-3 * tol
+    if maxrank == 0:
+        assert tt_rel(host(y), x) <= max(tol, 1e-13) * (1 + 1e-6)
+
+
+def test_round_rand_workload_shapes():
+    """STTA rounding of a rank-192 A v to target rank 64 (rho = 84) at n = 64, d = 5."""
+    n, d = 64, 5
+    rng = np.random.default_rng(12)
+    terms = _op("convdiff", n, d)
+    A = oops.tt_kron_sum(terms)
+    v = syn.gaussian_tt(rng, [n] * d, [1, 64, 64, 64, 64, 1])
+    av = ott.matvec(A, v)
+    rx, rho = syn.stta_ranks([n] * d, 64, 20)
+    X = syn.tt_drm(rng, [n] * d, rx, 1, d)
+    Y = syn.tt_drm(rng, [n] * d, rho, 0, d - 1)
+    y = ttsg.round_rand(ttsg.to_device(av, DEV), ttsg.to_device(X, DEV), ttsg.to_device(Y, DEV), rx, rho, 1e-7, 64)
+    ref = osk.round_rand(av, X, Y, 1e-7, 64)
+    assert ttsg.ranks_of(y) == ott.ranks(ref)
+    assert tt_rel(host(y), ref) < 1e-8
