@@ -55,6 +55,9 @@ template <typename T> std::vector<const void*> vp(const T* const* p, int cnt) {
 
 hipStream_t S(ttsg_stream_t s) { return static_cast<hipStream_t>(s); }
 
+// Split-K partial sums of one contraction take at most 4M output elements.
+constexpr size_t kSplitSlack = (size_t)40 << 20;
+
 }  // namespace
 
 extern "C" {
@@ -105,7 +108,7 @@ int ttsg_kr_sketch(int32_t d, const int32_t* n, int32_t s, const double* const* 
             need += 2 * ((size_t)s * RR[mu + 1] * r[mu + 1] * 8 + 256);             // P buffers
         }
         need += (size_t)s * 8 * 4 + 4096;
-        ttsg::Workspace W(ws, ws_bytes, need * 2, S(stream));
+        ttsg::Workspace W(ws, ws_bytes, (need * 2) + kSplitSlack, S(stream));
         ttsg::Arena& ar = W.arena;
         std::vector<const void*> SA(d), xs(d);
         for (int mu = 0; mu < d; ++mu) {
@@ -201,7 +204,7 @@ int ttsg_stta_sketch(int32_t d, const int32_t* n, const int32_t* rho, const doub
             check_shape(d, n, R, "stta A");
             check_ptrs(d, (const void* const*)A, "stta A");
         }
-        ttsg::Workspace W(ws, ws_bytes, stta_ws(d, n, rho, rx, A ? R : nullptr, r), S(stream));
+        ttsg::Workspace W(ws, ws_bytes, (stta_ws(d, n, rho, rx, A ? R : nullptr, r)) + kSplitSlack, S(stream));
         stta_common(d, n, rho, Y, rx, X, A ? R : nullptr, A, r, x, Psi, Omega, precision, W.arena, S(stream));
         TTSG_HIP(hipStreamSynchronize(S(stream)));
         return 0;
@@ -233,7 +236,7 @@ int ttsg_round_rand(int32_t d, const int32_t* n, const int32_t* r, const double*
         }
         const size_t need = stta_ws(d, n, rho, rx, nullptr, r) + sk * 8 + (8 * core + 12 * rmax * rmax) * 8 +
                             (size_t)d * 16 * rmax * rmax * 8 + (4 << 20);
-        ttsg::Workspace W(ws, ws_bytes, need, S(stream));
+        ttsg::Workspace W(ws, ws_bytes, (need) + kSplitSlack, S(stream));
         ttsg::Arena& ar = W.arena;
         std::vector<double*> psi(d), om(d - 1);
         for (int mu = 0; mu < d; ++mu) psi[mu] = ar.get<double>((int64_t)rho[mu] * n[mu] * rx[mu + 1]);
@@ -265,7 +268,7 @@ int ttsg_round_svd(int32_t d, const int32_t* n, const int32_t* r, const double* 
             core = std::max(core, (size_t)r[mu] * n[mu] * r[mu + 1]);
             rmax = std::max(rmax, (size_t)r[mu]);
         }
-        ttsg::Workspace W(ws, ws_bytes, (6 * core + 4 * rmax * rmax + 8 * rmax) * 8 + (1 << 20), S(stream));
+        ttsg::Workspace W(ws, ws_bytes, ((6 * core + 4 * rmax * rmax + 8 * rmax) * 8 + (1 << 20)) + kSplitSlack, S(stream));
         std::vector<double*> o(out, out + d);
         for (int mu = 0; mu < d; ++mu) ttsg::copy_f64((int64_t)r[mu] * n[mu] * r[mu + 1], x[mu], o[mu], S(stream));
         std::vector<int> rr = vec(r, d + 1);
@@ -288,7 +291,7 @@ int ttsg_dot(int32_t d, const int32_t* n, const int32_t* rxr, const double* cons
         size_t big = 0;
         for (int mu = 0; mu < d; ++mu)
             big = std::max(big, (size_t)ryr[mu] * n[mu] * rxr[mu + 1] + (size_t)ryr[mu + 1] * rxr[mu + 1]);
-        ttsg::Workspace W(ws, ws_bytes, 6 * big * 8 + (1 << 16), S(stream));
+        ttsg::Workspace W(ws, ws_bytes, (6 * big * 8 + (1 << 16)) + kSplitSlack, S(stream));
         double* dev = W.arena.get<double>(1);
         std::vector<int> R1(d + 1, 1);
         ttsg::inner_run(ttsg::Prec::F64, d, n, R1, {}, vec(rxr, d + 1), vp(x, d), vec(ryr, d + 1), vp(y, d), dev,

@@ -16,6 +16,7 @@
 // Operand layout of the 16x16xK forms: lane l supplies row (l % 16) of A and
 // column (l % 16) of B for the k-group (l / 16); the accumulator of lane l holds
 // column (l % 16), rows given by Traits<T>::acc_row.
+#include <algorithm>
 #include <cstdlib>
 
 #include "ttsg_internal.h"
@@ -84,18 +85,26 @@ __device__ __forceinline__ f4_t mfma(float a, float b, f4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// With splits > 1 every workgroup reduces one K-chunk of kchunk values and
+// writes its unscaled partial tile to part[split][batch][M][N]; a second
+// kernel sums the partials in a fixed order (deterministic) into C.
 template <typename T>
 __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const T* __restrict__ A,
                                                        const T* __restrict__ B,
                                                        typename Traits<T>::out_t* __restrict__ C,
-                                                       int batch0) {
+                                                       int batch0, int splits, int kchunk,
+                                                       typename Traits<T>::out_t* __restrict__ part) {
     using acc4 = typename Traits<T>::acc4;
     using out_t = typename Traits<T>::out_t;
     constexpr int BK = Traits<T>::BK;
     __shared__ T As[BK][BM + 1];
     __shared__ T Bs[BK][BN + 1];
 
-    const int bidx = batch0 + blockIdx.z;
+    const int zz = batch0 + blockIdx.z;
+    const int bidx = zz / splits;
+    const int split = zz - bidx * splits;
+    const int kbeg = split * kchunk;
+    const int kend = min(d.K, kbeg + kchunk);
     const int m0 = blockIdx.y * BM;
     const int n0 = blockIdx.x * BN;
     const T* Ab = A + idx_off(d.ab, bidx);
@@ -118,9 +127,9 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const T* 
     const bool a_kfast = (d.ak.s0 == 1);
     const bool b_kfast = (d.bk.s0 == 1);
 
-    for (int k0 = 0; k0 < d.K; k0 += BK) {
-        load_tile<T>(As, Ab, d.am, d.ak, m0, k0, d.M, d.K, a_kfast);
-        load_tile<T>(Bs, Bb, d.bn, d.bk, n0, k0, d.N, d.K, b_kfast);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        load_tile<T>(As, Ab, d.am, d.ak, m0, k0, d.M, kend, a_kfast);
+        load_tile<T>(Bs, Bb, d.bn, d.bk, n0, k0, d.N, kend, b_kfast);
         __syncthreads();
         if constexpr (sizeof(T) == 2) {
 #pragma unroll
@@ -168,16 +177,38 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const T* 
                 int row = m0 + wm + 16 * i + Traits<T>::acc_row(lg, r);
                 int col = n0 + wn + 16 * j + lr;
                 if (row < d.M && col < d.N) {
-                    int64_t off = idx_off(d.cm, row) + idx_off(d.cn, col);
-                    out_t v = alpha * (out_t)acc[i][j][r];
-                    if (beta != out_t(0)) v += beta * Cb[off];
-                    Cb[off] = v;
+                    if (part != nullptr) {
+                        part[(((int64_t)split * d.batch + bidx) * d.M + row) * d.N + col] = (out_t)acc[i][j][r];
+                    } else {
+                        int64_t off = idx_off(d.cm, row) + idx_off(d.cn, col);
+                        out_t v = alpha * (out_t)acc[i][j][r];
+                        if (beta != out_t(0)) v += beta * Cb[off];
+                        Cb[off] = v;
+                    }
                 }
             }
 }
 
+template <typename O>
+__global__ void reduce_splits(ContractDesc d, int splits, const O* __restrict__ part, O* __restrict__ C) {
+    const int64_t per = (int64_t)d.M * d.N;
+    const int64_t total = per * d.batch;
+    const O alpha = (O)d.alpha, beta = (O)d.beta;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(e / per);
+        const int64_t mn = e - (int64_t)b * per;
+        const int m = (int)(mn / d.N), n = (int)(mn - (int64_t)m * d.N);
+        O acc = 0;
+        for (int s = 0; s < splits; ++s) acc += part[(int64_t)s * total + e];
+        const int64_t off = idx_off(d.cb, b) + idx_off(d.cm, m) + idx_off(d.cn, n);
+        O v = alpha * acc;
+        if (beta != O(0)) v += beta * C[off];
+        C[off] = v;
+    }
+}
+
 template <typename T>
-void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st) {
+void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st, Arena* ar) {
     if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
     if (bounds_checking()) {
         using out_t = typename Traits<T>::out_t;
@@ -200,15 +231,41 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         bytes = (ua + ub) * sizeof(T) + uc * sizeof(out_t);
     }
     StatScope scope(cls, flops, bytes, st);
+    using out_t = typename Traits<T>::out_t;
     dim3 block(256);
     const int gx = (d.N + BN - 1) / BN;
     const int gy = (d.M + BM - 1) / BM;
     TTSG_CHECK(gy < 65536, TTSG_ERR_ARG, "contraction: M too large");
-    for (int b0 = 0; b0 < d.batch; b0 += 65535) {
-        int nb = d.batch - b0 < 65535 ? d.batch - b0 : 65535;
-        dim3 grid(gx, gy, nb);
-        hipLaunchKernelGGL(contract_kernel<T>, grid, block, 0, st, d, static_cast<const T*>(A),
-                           static_cast<const T*>(B), static_cast<typename Traits<T>::out_t*>(C), b0);
+    // split-K when the output tiles alone cannot fill the chip
+    constexpr int BK = Traits<T>::BK;
+    const int64_t wgs = (int64_t)gx * gy * d.batch;
+    int splits = 1, kchunk = d.K;
+    if (ar != nullptr && wgs < 512 && d.K >= 4 * BK) {
+        int want = (int)std::min<int64_t>((1024 + wgs - 1) / wgs, d.K / (2 * BK));
+        want = std::min<int64_t>(want, 65535 / std::max(d.batch, 1));
+        if (want >= 2) {
+            kchunk = ((d.K + want - 1) / want + BK - 1) / BK * BK;
+            splits = (d.K + kchunk - 1) / kchunk;
+        }
+    }
+    if (splits > 1) {
+        const size_t mark = ar->mark();
+        out_t* part = ar->get<out_t>((size_t)splits * d.batch * d.M * d.N);
+        const int zt = d.batch * splits;
+        hipLaunchKernelGGL(contract_kernel<T>, dim3(gx, gy, zt), block, 0, st, d, static_cast<const T*>(A),
+                           static_cast<const T*>(B), static_cast<out_t*>(C), 0, splits, kchunk, part);
+        const int64_t total = (int64_t)d.batch * d.M * d.N;
+        const int rb = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 8192));
+        hipLaunchKernelGGL(reduce_splits<out_t>, dim3(rb), dim3(256), 0, st, d, splits, part, static_cast<out_t*>(C));
+        ar->release(mark);
+    } else {
+        for (int b0 = 0; b0 < d.batch; b0 += 65535) {
+            int nb = d.batch - b0 < 65535 ? d.batch - b0 : 65535;
+            dim3 grid(gx, gy, nb);
+            hipLaunchKernelGGL(contract_kernel<T>, grid, block, 0, st, d, static_cast<const T*>(A),
+                               static_cast<const T*>(B), static_cast<out_t*>(C), b0, 1, d.K,
+                               static_cast<out_t*>(nullptr));
+        }
     }
     TTSG_HIP(hipGetLastError());
 }
@@ -234,15 +291,15 @@ void check_range(const void* p, size_t bytes, const char* what) {
                std::string(what) + ": access range exceeds its allocation");
 }
 
-void contract(Prec p, const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st) {
+void contract(Prec p, const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st, Arena* ar) {
     if (d.K <= 0) {
         // empty reduction: C = beta * C handled by callers never passing K = 0
         TTSG_CHECK(false, TTSG_ERR_ARG, "contraction with empty reduction");
     }
     switch (p) {
-        case Prec::F64: launch<double>(d, A, B, C, st); break;
-        case Prec::F32: launch<float>(d, A, B, C, st); break;
-        case Prec::BF16: launch<uint16_t>(d, A, B, C, st); break;
+        case Prec::F64: launch<double>(d, A, B, C, st, ar); break;
+        case Prec::F32: launch<float>(d, A, B, C, st, ar); break;
+        case Prec::BF16: launch<uint16_t>(d, A, B, C, st, ar); break;
     }
 }
 

@@ -230,7 +230,7 @@ void svd_jacobi(int32_t batch, int32_t m, int32_t c, double* A, int32_t lda, int
     // rotated column pairs (m and c long)
     StatScope scope(TTSG_ST_SVD, batch * 0.5 * c * (c - 1.0) * (12.0 * m + 6.0 * c), batch * 16.0 * m * c, st);
     hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(LA_THREADS), 0, st, m, c, A, lda, strideA, V, ldv, strideV,
-                       sig, strideSig, 60, 1e-15);
+                       sig, strideSig, 40, m * 2.220446049250313e-16);
     TTSG_HIP(hipGetLastError());
 }
 

@@ -20,7 +20,7 @@ namespace ttsg {
 namespace {
 
 constexpr int JT = 1024;   // threads of the Jacobi workgroup
-constexpr int QT = 512;    // threads of the QR leaf workgroups
+constexpr int QT = 1024;   // threads of the QR leaf workgroups
 constexpr int LEAF = 256;  // maximum rows of a TSQR leaf
 
 __device__ __forceinline__ double wsum(double v) {
@@ -36,17 +36,39 @@ struct JacobiBatch {
     double* sig[32];
 };
 
+// Wave leaders add their partial into an LDS scalar (thread 0 first zeroes it
+// through the initial value of its own contribution order: the caller runs
+// this after a barrier, so a plain atomic add is enough).
+__device__ __forceinline__ void tab_partial_add(double* dst, double v, bool first) {
+    (void)first;
+    atomicAdd(dst, v);
+}
+
+// Sum over the G lanes of a lane group (G a power of two dividing 64).
+template <int G> __device__ __forceinline__ double gsum(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+
+// One-sided Jacobi with one lane group of JG lanes per column pair: the group
+// forms the pair's three dot products over its strided rows, reduces them in
+// registers, and rotates the same rows, so a round of the circle method costs
+// a single barrier.  The pairs of every round come from a table built once.
+constexpr int JG = 32;
 __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps, double tol) {
     extern __shared__ double lds[];
+    __shared__ short tab[2 * 32 * 63];      // (p, q) of pair k in round r, c <= 64
+    __shared__ int s_rot;
     const int bi = blockIdx.x;
     const int m = jb.m[bi], c = jb.c[bi], lda = jb.lda[bi];
     double* Ag = jb.A[bi];
     double* Vg = jb.V[bi];
-    const int ldm = m | 1;          // odd leading dimensions spread the LDS banks
+    const int ldm = m | 1;
     const int ldv = c | 1;
     double* A = lds;
     double* V = lds + (size_t)ldm * c;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int tid = threadIdx.x;
     for (int e = tid; e < m * c; e += blockDim.x) {
         int j = e / m, i = e - j * m;
         A[j * ldm + i] = Ag[(int64_t)j * lda + i];
@@ -55,59 +77,87 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
         int j = e / c, i = e - j * c;
         V[j * ldv + i] = (i == j) ? 1.0 : 0.0;
     }
-    __shared__ int s_rot;
     const int cp = c + (c & 1);
+    const int npair = cp / 2;
+    const int nround = cp - 1;
+    for (int e = tid; e < nround * npair; e += blockDim.x) {
+        const int r = e / npair, k = e - r * npair;
+        int p, q;
+        if (k == 0) {
+            p = cp - 1;
+            q = r;
+        } else {
+            p = (r + k) % (cp - 1);
+            q = (r - k + cp - 1) % (cp - 1);
+        }
+        tab[2 * e] = (short)p;
+        tab[2 * e + 1] = (short)q;
+    }
+    const int grp = tid / JG, lt = tid - grp * JG;
+    const int ngrp = JT / JG;
+    __shared__ double s_fro;
+    if (tid == 0) {
+        s_rot = 0;
+        s_fro = 0.0;
+    }
     __syncthreads();
+    {
+        // squared Frobenius norm: columns below eps ||A||_F are rounding noise
+        double f = 0.0;
+        for (int e = tid; e < m * c; e += blockDim.x) {
+            int j = e / m, i = e - j * m;
+            f += A[j * ldm + i] * A[j * ldm + i];
+        }
+        f = wsum(f);
+        if ((tid & 63) == 0) tab_partial_add(&s_fro, f, tid == 0);
+    }
+    __syncthreads();
+    const double tiny = 4.930380657631324e-32 * s_fro;   // (eps ||A||_F)^2
     for (int sweep = 0; sweep < maxsweeps && cp > 1; ++sweep) {
-        if (tid == 0) s_rot = 0;
-        __syncthreads();
-        for (int r = 0; r < cp - 1; ++r) {
-            for (int pk = wave; pk < cp / 2; pk += nw) {
-                int p, q;
-                if (pk == 0) {
-                    p = cp - 1;
-                    q = r;
-                } else {
-                    p = (r + pk) % (cp - 1);
-                    q = (r - pk + cp - 1) % (cp - 1);
-                }
+        int rotated = 0;
+        for (int r = 0; r < nround; ++r) {
+            for (int k = grp; k < npair; k += ngrp) {
+                const int p = tab[2 * (r * npair + k)], q = tab[2 * (r * npair + k) + 1];
                 if (p >= c || q >= c) continue;
                 double* ap = A + p * ldm;
                 double* aq = A + q * ldm;
                 double al = 0.0, be = 0.0, ga = 0.0;
-                for (int i = lane; i < m; i += 64) {
-                    double x = ap[i], y = aq[i];
+                for (int i = lt; i < m; i += JG) {
+                    const double x = ap[i], y = aq[i];
                     al += x * x;
                     be += y * y;
                     ga += x * y;
                 }
-                al = wsum(al);
-                be = wsum(be);
-                ga = wsum(ga);
-                if (al == 0.0 || be == 0.0) continue;
-                if (fabs(ga) <= tol * sqrt(al) * sqrt(be)) continue;
-                double zeta = (be - al) / (2.0 * ga);
-                double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
-                double cs = 1.0 / sqrt(1.0 + t * t);
-                double sn = cs * t;
-                for (int i = lane; i < m; i += 64) {
-                    double x = ap[i], y = aq[i];
+                al = gsum<JG>(al);
+                be = gsum<JG>(be);
+                ga = gsum<JG>(ga);
+                if (al <= tiny || be <= tiny || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
+                const double cs = 1.0 / sqrt(1.0 + t * t);
+                const double sn = cs * t;
+                for (int i = lt; i < m; i += JG) {
+                    const double x = ap[i], y = aq[i];
                     ap[i] = cs * x - sn * y;
                     aq[i] = sn * x + cs * y;
                 }
                 double* vp = V + p * ldv;
                 double* vq = V + q * ldv;
-                for (int i = lane; i < c; i += 64) {
-                    double x = vp[i], y = vq[i];
+                for (int i = lt; i < c; i += JG) {
+                    const double x = vp[i], y = vq[i];
                     vp[i] = cs * x - sn * y;
                     vq[i] = sn * x + cs * y;
                 }
-                if (lane == 0) s_rot = 1;
+                rotated = 1;
             }
             __syncthreads();
         }
-        if (s_rot == 0) break;
+        if (rotated && lt == 0) s_rot = 1;
         __syncthreads();
+        const int any = s_rot;      // every thread reads the flag ...
+        __syncthreads();            // ... before thread 0 clears it for the next sweep
+        if (tid == 0) s_rot = 0;
+        if (any == 0) break;
     }
     __syncthreads();
     for (int e = tid; e < m * c; e += blockDim.x) {
@@ -118,12 +168,12 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
         int j = e / c, i = e - j * c;
         Vg[(int64_t)j * c + i] = V[j * ldv + i];
     }
-    for (int l = wave; l < c; l += nw) {
+    for (int l = grp; l < c; l += ngrp) {
         const double* al = A + l * ldm;
-        double s = 0.0;
-        for (int i = lane; i < m; i += 64) s += al[i] * al[i];
-        s = wsum(s);
-        if (lane == 0) jb.sig[bi][l] = sqrt(s);
+        double s2 = 0.0;
+        for (int i = lt; i < m; i += JG) s2 += al[i] * al[i];
+        s2 = gsum<JG>(s2);
+        if (lt == 0) jb.sig[bi][l] = sqrt(s2);
     }
 }
 
@@ -133,56 +183,61 @@ __device__ __forceinline__ void leaf_rows(int m, int nleaves, int i, int& r0, in
     r1 = (int)(((int64_t)(i + 1) * m) / nleaves);
 }
 
+// Householder QR of one leaf in LDS.  Step j: one wavefront forms the
+// reflector of column j; then every trailing column is owned by a lane group
+// of QG lanes that reduces v^T a_l in registers and updates its own rows.
+constexpr int QG = 16;
 __global__ __launch_bounds__(QT) void k_qr_leaf(int m, int c, const double* __restrict__ A, int lda,
                                                  int nleaves, double* __restrict__ refl, int ldr,
                                                  double* __restrict__ tau, double* __restrict__ Rs, int ldrs) {
     extern __shared__ double T[];
+    __shared__ double s_tau, s_scale;
     const int i = blockIdx.x;
     int r0, r1;
     leaf_rows(m, nleaves, i, r0, r1);
     const int rows = r1 - r0;
     const int ldt = rows | 1;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int grp = tid / QG, lt = tid - grp * QG, ngrp = QT / QG;
     for (int e = tid; e < rows * c; e += blockDim.x) {
         int j = e / rows, r = e - j * rows;
         T[j * ldt + r] = A[(int64_t)j * lda + r0 + r];
     }
-    __shared__ double s_tau, s_scale;
     __syncthreads();
     const int kk = rows < c ? rows : c;
     for (int j = 0; j < kk; ++j) {
         double* col = T + j * ldt;
         if (wave == 0) {
-            double s = 0.0;
-            for (int r = j + 1 + lane; r < rows; r += 64) s += col[r] * col[r];
-            s = wsum(s);
+            double sacc = 0.0;
+            for (int r = j + 1 + lane; r < rows; r += 64) sacc += col[r] * col[r];
+            sacc = wsum(sacc);
+            const double alpha = col[j];
+            double tt = 0.0, sc = 0.0, beta = alpha;
+            if (sacc != 0.0) {
+                beta = -copysign(sqrt(alpha * alpha + sacc), alpha);
+                tt = (beta - alpha) / beta;
+                sc = 1.0 / (alpha - beta);
+            }
+            for (int r = j + 1 + lane; r < rows; r += 64) col[r] *= sc == 0.0 ? 1.0 : sc;
             if (lane == 0) {
-                double alpha = col[j];
-                if (s == 0.0) {
-                    s_tau = 0.0;
-                    s_scale = 0.0;
-                } else {
-                    double beta = -copysign(sqrt(alpha * alpha + s), alpha);
-                    s_tau = (beta - alpha) / beta;
-                    s_scale = 1.0 / (alpha - beta);
-                    col[j] = beta;
-                }
-                tau[(int64_t)i * c + j] = s_tau;
+                col[j] = beta;
+                s_tau = tt;
+                s_scale = sc;
+                tau[(int64_t)i * c + j] = tt;
             }
         }
         __syncthreads();
-        const double t = s_tau, sc = s_scale;
+        const double t = s_tau;
         if (t != 0.0) {
-            for (int r = j + 1 + tid; r < rows; r += blockDim.x) col[r] *= sc;
-            __syncthreads();
-            for (int l = j + 1 + wave; l < c; l += nw) {
+            for (int l = j + 1 + grp; l < c; l += ngrp) {
                 double* cl = T + l * ldt;
                 double w = 0.0;
-                for (int r = j + 1 + lane; r < rows; r += 64) w += col[r] * cl[r];
-                w = wsum(w);
+                for (int r = j + 1 + lt; r < rows; r += QG) w += col[r] * cl[r];
+                w = gsum<QG>(w);
                 w = t * (w + cl[j]);
-                if (lane == 0) cl[j] -= w;
-                for (int r = j + 1 + lane; r < rows; r += 64) cl[r] -= w * col[r];
+                if (lt == 0) cl[j] -= w;
+                for (int r = j + 1 + lt; r < rows; r += QG) cl[r] -= w * col[r];
             }
         }
         __syncthreads();
@@ -212,7 +267,8 @@ __global__ __launch_bounds__(QT) void k_qr_apply_leaf(int m, int c, int k, const
     const int rows = r1 - r0;
     const int ldx = rows | 1;
     double* v = X + (size_t)ldx * k;   // the current reflector
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int tid = threadIdx.x;
+    const int grp = tid / QG, lt = tid - grp * QG, ngrp = QT / QG;
     for (int e = tid; e < rows * k; e += blockDim.x) {
         int t = e / rows, r = e - t * rows;
         X[t * ldx + r] = (r < c) ? Bin[(int64_t)t * ldb + (int64_t)i * c + r] : 0.0;
@@ -224,14 +280,14 @@ __global__ __launch_bounds__(QT) void k_qr_apply_leaf(int m, int c, int k, const
         if (tj == 0.0) continue;
         for (int r = j + 1 + tid; r < rows; r += blockDim.x) v[r] = refl[(int64_t)j * ldr + r0 + r];
         __syncthreads();
-        for (int t = wave; t < k; t += nw) {
+        for (int t = grp; t < k; t += ngrp) {
             double* xt = X + t * ldx;
             double w = 0.0;
-            for (int r = j + 1 + lane; r < rows; r += 64) w += v[r] * xt[r];
-            w = wsum(w);
+            for (int r = j + 1 + lt; r < rows; r += QG) w += v[r] * xt[r];
+            w = gsum<QG>(w);
             w = tj * (w + xt[j]);
-            if (lane == 0) xt[j] -= w;
-            for (int r = j + 1 + lane; r < rows; r += 64) xt[r] -= w * v[r];
+            if (lt == 0) xt[j] -= w;
+            for (int r = j + 1 + lt; r < rows; r += QG) xt[r] -= w * v[r];
         }
     }
     __syncthreads();
@@ -244,13 +300,14 @@ __global__ __launch_bounds__(QT) void k_qr_apply_leaf(int m, int c, int k, const
     }
 }
 
-// Dynamic LDS above the default limit must be requested once per kernel.
-void allow_lds(const void* fn, bool& done) {
-    if (done) return;
-    TTSG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
-    done = true;
+// Dynamic LDS above the default limit must be requested per kernel; the
+// request (dynamic bytes) plus the kernel's static LDS must fit in 160 KB.
+void allow_lds(const void* fn, size_t bytes, size_t& granted) {
+    if (bytes <= granted) return;
+    TTSG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    granted = bytes;
 }
-bool g_lds_jacobi = false, g_lds_leaf = false, g_lds_apply = false;
+size_t g_lds_jacobi = 0, g_lds_leaf = 0, g_lds_apply = 0;
 
 int choose_leaves(int m, int c) {
     int nl = (m + LEAF - 1) / LEAF;
@@ -262,7 +319,8 @@ int choose_leaves(int m, int c) {
 
 size_t jacobi_lds_bytes(int m, int c) { return ((size_t)(m | 1) * c + (size_t)(c | 1) * c) * 8; }
 
-bool jacobi_lds_fits(int m, int c) { return m >= c && jacobi_lds_bytes(m, c) <= 150 * 1024; }
+// dynamic LDS (matrix + rotations) plus ~26 KB of static scratch must fit in 160 KB
+bool jacobi_lds_fits(int m, int c) { return m >= c && c <= 64 && jacobi_lds_bytes(m, c) <= 128 * 1024; }
 
 void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st) {
     size_t i = 0;
@@ -290,8 +348,12 @@ void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st) {
         }
         jb.count = cnt;
         StatScope scope(TTSG_ST_SVD, flops, 0.0, st);
-        allow_lds(reinterpret_cast<const void*>(&k_jacobi_lds), g_lds_jacobi);
-        hipLaunchKernelGGL(k_jacobi_lds, dim3(cnt), dim3(JT), lds, st, jb, 60, 1e-15);
+        allow_lds(reinterpret_cast<const void*>(&k_jacobi_lds), lds, g_lds_jacobi);
+        // a pair counts as orthogonal once |a_p.a_q| <= m eps ||a_p|| ||a_q||: below
+        // that the computed dot product is rounding noise and sweeps never end
+        int mmax = 1;
+        for (int t = 0; t < cnt; ++t) mmax = std::max(mmax, jb.m[t]);
+        hipLaunchKernelGGL(k_jacobi_lds, dim3(cnt), dim3(JT), lds, st, jb, 30, 4.0 * mmax * 2.220446049250313e-16);
         TTSG_HIP(hipGetLastError());
     }
 }
@@ -324,7 +386,7 @@ void TsqrPlan::factor(int m_, int c_, const double* A, int lda, Arena& ar, hipSt
         {
             const double kq = std::min(maxrows, c);
             StatScope scope(TTSG_ST_QR, L.nleaves * (2.0 * maxrows * c * kq - 2.0 / 3.0 * kq * kq * kq), 0.0, st);
-            allow_lds(reinterpret_cast<const void*>(&k_qr_leaf), g_lds_leaf);
+            allow_lds(reinterpret_cast<const void*>(&k_qr_leaf), lds, g_lds_leaf);
             hipLaunchKernelGGL(k_qr_leaf, dim3(L.nleaves), dim3(QT), lds, st, rows, c, in, ld_in, L.nleaves, L.refl,
                                rows, L.tau, L.stack, ldstack);
             TTSG_HIP(hipGetLastError());
@@ -360,7 +422,7 @@ void TsqrPlan::apply(int k, const double* B, int ldb, double* Out, int ldo, bool
         TTSG_CHECK(lds <= 150 * 1024, TTSG_ERR_ARG, "tsqr apply exceeds LDS");
         {
             StatScope scope(TTSG_ST_QR, L.nleaves * 4.0 * maxrows * c * (double)k, 0.0, st);
-            allow_lds(reinterpret_cast<const void*>(&k_qr_apply_leaf), g_lds_apply);
+            allow_lds(reinterpret_cast<const void*>(&k_qr_apply_leaf), lds, g_lds_apply);
             hipLaunchKernelGGL(k_qr_apply_leaf, dim3(L.nleaves), dim3(QT), lds, st, L.rows, c, k, L.refl, L.rows,
                                L.tau, L.nleaves, in, ld_in, out, ld_out, (last && out_rowmajor) ? 1 : 0);
             TTSG_HIP(hipGetLastError());

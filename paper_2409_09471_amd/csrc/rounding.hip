@@ -69,7 +69,7 @@ void gather_cols(int rows, int k, const double* src, int lds, double* dst, int l
 
 // Row-major C (M x N) = A (row-major M x K) * B (column-major K x N, ld = ldb)
 void gemm_rm_cm(int M, int N, int K, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
-                hipStream_t st) {
+                hipStream_t st, Arena* ar = nullptr) {
     ContractDesc d = cdesc(M, N, K);
     d.am = idx1(lda);
     d.ak = idx1(1);
@@ -77,12 +77,12 @@ void gemm_rm_cm(int M, int N, int K, const double* A, int lda, const double* B, 
     d.bn = idx1(ldb);
     d.cm = idx1(ldc);
     d.cn = idx1(1);
-    contract(Prec::F64, d, A, B, C, st);
+    contract(Prec::F64, d, A, B, C, st, ar);
 }
 
 // Row-major C (M x N) = A (row-major M x K) * B (row-major K x N)
 void gemm_rm_rm(int M, int N, int K, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
-                hipStream_t st) {
+                hipStream_t st, Arena* ar = nullptr) {
     ContractDesc d = cdesc(M, N, K);
     d.am = idx1(lda);
     d.ak = idx1(1);
@@ -90,12 +90,12 @@ void gemm_rm_rm(int M, int N, int K, const double* A, int lda, const double* B, 
     d.bn = idx1(1);
     d.cm = idx1(ldc);
     d.cn = idx1(1);
-    contract(Prec::F64, d, A, B, C, st);
+    contract(Prec::F64, d, A, B, C, st, ar);
 }
 
 // Row-major C (M x N) = A (column-major M x K, ld lda) * B (column-major K x N, ld ldb)
 void gemm_cm_cm(int M, int N, int K, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
-                hipStream_t st) {
+                hipStream_t st, Arena* ar = nullptr) {
     ContractDesc d = cdesc(M, N, K);
     d.am = idx1(1);
     d.ak = idx1(lda);
@@ -103,7 +103,7 @@ void gemm_cm_cm(int M, int N, int K, const double* A, int lda, const double* B, 
     d.bn = idx1(ldb);
     d.cm = idx1(ldc);
     d.cn = idx1(1);
-    contract(Prec::F64, d, A, B, C, st);
+    contract(Prec::F64, d, A, B, C, st, ar);
 }
 
 // Smallest k whose discarded tail is <= delta; at least 1; capped at maxrank.
@@ -190,7 +190,7 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
         const int rll = r[mu - 1], nl = n[mu - 1];
         // T (rll*nl x k) = W_{mu-1} (rll*nl x rl) * R^T
         // B[l][kk] = R[kk][l] = Rm[l*k + kk]: the column-major R read row-major
-        gemm_rm_rm(rll * nl, k, rl, w[mu - 1], rl, Rm, k, T, k, st);
+        gemm_rm_rm(rll * nl, k, rl, w[mu - 1], rl, Rm, k, T, k, st, &ar);
         copy_f64((int64_t)rll * nl * k, T, w[mu - 1], st);
         r[mu] = k;
     }
@@ -252,7 +252,7 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             if (tsqr) {
                 plan.apply(k, T, c, w[mu], k, true, ar, st);
             } else {
-                gemm_cm_cm(m, k, c, Q, m, T, c, w[mu], k, st);
+                gemm_cm_cm(m, k, c, Q, m, T, c, w[mu], k, st, &ar);
             }
             ar.release(mk);
             // SVt (row-major k x c) = column-major c x k of V[:, perm] * sigma
@@ -285,7 +285,7 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             gather_cols(m, k, T, m, A, m, perm_dev, fac_dev, st);  // A: column-major m x k
             transpose2d(k, m, A, m, w[mu], k, st);                 // row-major m x k
             // (Q2 V2) column-major c x m, then SVt (row-major k x c) = S * (Q2 V2)[:, perm]^T
-            gemm_cm_cm(c, m, m, Q, c, V, m, QV, m, st);            // row-major c x m == QV^T column-major
+            gemm_cm_cm(c, m, m, Q, c, V, m, QV, m, st, &ar);            // row-major c x m == QV^T column-major
             // QV row-major c x m: column j of (Q2 V2) is strided by m -> transpose to column-major
             transpose2d(c, m, QV, m, A, c, st);                    // A column-major c x m
             std::vector<double> sv(k);
@@ -303,7 +303,7 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             dd.bn = idx1(1);
             dd.cm = idx1((int64_t)n2 * r2);
             dd.cn = idx1(1);
-            contract(Prec::F64, dd, QV, w[mu + 1], T, st);
+            contract(Prec::F64, dd, QV, w[mu + 1], T, st, &ar);
             copy_f64((int64_t)k * n2 * r2, T, w[mu + 1], st);
         }
         r[mu + 1] = k;
@@ -390,12 +390,12 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         double* mid = T;
         if (mu >= 1) {
             // T (kl x nn*qr) = G_mu (kl x rho_mu) * Psi_mu (rho_mu x nn*qr)
-            gemm_rm_rm(kl, nn * qr, rho[mu], Gb[mu], rho[mu], Psi[mu], nn * qr, T, nn * qr, st);
+            gemm_rm_rm(kl, nn * qr, rho[mu], Gb[mu], rho[mu], Psi[mu], nn * qr, T, nn * qr, st, &ar);
             src = T;
         }
         if (mu <= d - 2) {
             // out (kl*nn x kr) = src (kl*nn x qr) * V'_{mu+1} (column-major qr x kr)
-            gemm_rm_cm(kl * nn, kr, qr, src, qr, Vk[mu + 1], qr, out[mu], kr, st);
+            gemm_rm_cm(kl * nn, kr, qr, src, qr, Vk[mu + 1], qr, out[mu], kr, st, &ar);
         } else {
             copy_f64((int64_t)kl * nn, src, out[mu], st);
         }
@@ -436,7 +436,7 @@ double tt_norm_orth(int d, const int* n, std::vector<int>& r, const std::vector<
         dd.bn = idx1(1);
         dd.cm = idx1((int64_t)n2 * r2);
         dd.cn = idx1(1);
-        contract(Prec::F64, dd, Rm, w[mu + 1], T, st);
+        contract(Prec::F64, dd, Rm, w[mu + 1], T, st, &ar);
         copy_f64((int64_t)k * n2 * r2, T, w[mu + 1], st);
         r[mu + 1] = k;
     }

@@ -21,18 +21,19 @@ void matvec_core(int rl, int n, int rr, int Rl, int Rr, const double* D, const d
 // pl*n*Rr*rr elements; with D == nullptr T2 is not used (T1 plays its role).
 // Z == nullptr stops after T1/T2 (what the core sketch Psi needs).
 void left_step(Prec p, const LeftDims& s, const void* E, const void* C, const void* D, const void* Z, void* T1,
-               void* T2, void* Eout, hipStream_t st);
+               void* T2, void* Eout, hipStream_t st, Arena* ar = nullptr);
 // F (rr x Rr x pr) -> Fout (rl x Rl x pl).  U1: rl*n*Rr*pr, U2: rl*Rl*n*pr.
 void right_step(Prec p, const LeftDims& s, const void* F, const void* C, const void* D, const void* Z, void* U1,
-                void* U2, void* Fout, hipStream_t st);
+                void* U2, void* Fout, hipStream_t st, Arena* ar = nullptr);
 void psi_step(Prec p, int pl, int n, int Rr, int rr, int qr, const void* T2, const void* F, void* Psi,
-              hipStream_t st);
-void omega_step(Prec p, int pl, int Rr, int rr, int qr, const void* E, const void* F, void* Om, hipStream_t st);
+              hipStream_t st, Arena* ar = nullptr);
+void omega_step(Prec p, int pl, int Rr, int rr, int qr, const void* E, const void* F, void* Om, hipStream_t st,
+                Arena* ar = nullptr);
 
 void kr_precompute(Prec p, int s, int n, int Rl, int Rr, const void* S, const void* D, void* SA, hipStream_t st);
 // P (s x Rl x rl) -> Pout (s x Rr x rr); Xbuf holds s*Rr*rl*n elements.
 void kr_step(Prec p, int s, int rl, int n, int rr, int Rl, int Rr, const void* P, const void* SA, const void* C,
-             void* Xbuf, void* Pout, hipStream_t st);
+             void* Xbuf, void* Pout, hipStream_t st, Arena* ar = nullptr);
 
 // ---------------------------------------------------------------------------
 // Views with host-known ranks.

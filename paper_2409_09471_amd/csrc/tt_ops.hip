@@ -57,7 +57,7 @@ void matvec_core(int rl, int n, int rr, int Rl, int Rr, const double* D, const d
 static inline int64_t eoff(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
 void left_step(Prec p, const LeftDims& s, const void* E, const void* C, const void* D, const void* Z, void* T1,
-               void* T2, void* Eout, hipStream_t st) {
+               void* T2, void* Eout, hipStream_t st, Arena* ar) {
     const int rl = s.rl, n = s.n, rr = s.rr, Rl = s.Rl, Rr = s.Rr, pl = s.pl, pr = s.pr;
     // L1: T1[p'][al][j][b] = sum_a E[p'][al][a] C[a][j][b]
     {
@@ -68,7 +68,7 @@ void left_step(Prec p, const LeftDims& s, const void* E, const void* C, const vo
         d.bn = idx1(1);
         d.cm = idx1((int64_t)n * rr);
         d.cn = idx1(1);
-        contract(p, d, E, C, T1, st);
+        contract(p, d, E, C, T1, st, ar);
     }
     const void* T2in = T1;
     if (D != nullptr) {
@@ -83,7 +83,7 @@ void left_step(Prec p, const LeftDims& s, const void* E, const void* C, const vo
         d.cb = idx1((int64_t)n * Rr * rr);
         d.cm = idx1(rr);
         d.cn = idx1(1);
-        contract(p, d, D, T1, T2, st);
+        contract(p, d, D, T1, T2, st, ar);
         T2in = T2;
     }
     if (Z != nullptr && Eout != nullptr) {
@@ -95,12 +95,12 @@ void left_step(Prec p, const LeftDims& s, const void* E, const void* C, const vo
         d.bn = idx1(1);
         d.cm = idx1((int64_t)Rr * rr);
         d.cn = idx1(1);
-        contract(p, d, Z, T2in, Eout, st);
+        contract(p, d, Z, T2in, Eout, st, ar);
     }
 }
 
 void right_step(Prec p, const LeftDims& s, const void* F, const void* C, const void* D, const void* Z, void* U1,
-                void* U2, void* Fout, hipStream_t st) {
+                void* U2, void* Fout, hipStream_t st, Arena* ar) {
     // here pl/pr are the probe ranks (rho_l x n x rho_r) of Z; F is r_r x R_r x pr
     const int rl = s.rl, n = s.n, rr = s.rr, Rl = s.Rl, Rr = s.Rr, pl = s.pl, pr = s.pr;
     // R1: U1[a][j][be][q] = sum_b C[a][j][b] F[b][be][q]
@@ -112,7 +112,7 @@ void right_step(Prec p, const LeftDims& s, const void* F, const void* C, const v
         d.bn = idx1(1);
         d.cm = idx1((int64_t)Rr * pr);
         d.cn = idx1(1);
-        contract(p, d, C, F, U1, st);
+        contract(p, d, C, F, U1, st, ar);
     }
     const void* U2in = U1;
     if (D != nullptr) {
@@ -127,7 +127,7 @@ void right_step(Prec p, const LeftDims& s, const void* F, const void* C, const v
         d.cb = idx1((int64_t)Rl * n * pr);
         d.cm = idx1(pr);
         d.cn = idx1(1);
-        contract(p, d, D, U1, U2, st);
+        contract(p, d, D, U1, U2, st, ar);
         U2in = U2;
     }
     // R3: F'[a][al][p'] = sum_{(i,q)} U2[a][al][i][q] Z[p'][i][q]
@@ -139,12 +139,12 @@ void right_step(Prec p, const LeftDims& s, const void* F, const void* C, const v
         d.bn = idx1((int64_t)n * pr);
         d.cm = idx1(pl);
         d.cn = idx1(1);
-        contract(p, d, U2in, Z, Fout, st);
+        contract(p, d, U2in, Z, Fout, st, ar);
     }
 }
 
 void psi_step(Prec p, int pl, int n, int Rr, int rr, int qr, const void* T2, const void* F, void* Psi,
-              hipStream_t st) {
+              hipStream_t st, Arena* ar) {
     // Psi[p'][i][q] = sum_{(be,b)} T2[p'][i][be][b] F[b][be][q]
     ContractDesc d = cdesc(pl * n, qr, Rr * rr);
     d.am = idx1((int64_t)Rr * rr);
@@ -153,10 +153,11 @@ void psi_step(Prec p, int pl, int n, int Rr, int rr, int qr, const void* T2, con
     d.bn = idx1(1);
     d.cm = idx1(qr);
     d.cn = idx1(1);
-    contract(p, d, T2, F, Psi, st);
+    contract(p, d, T2, F, Psi, st, ar);
 }
 
-void omega_step(Prec p, int pl, int Rr, int rr, int qr, const void* E, const void* F, void* Om, hipStream_t st) {
+void omega_step(Prec p, int pl, int Rr, int rr, int qr, const void* E, const void* F, void* Om, hipStream_t st,
+                Arena* ar) {
     // Om[p][q] = sum_{(be,b)} E[p][be][b] F[b][be][q]
     ContractDesc d = cdesc(pl, qr, Rr * rr);
     d.am = idx1((int64_t)Rr * rr);
@@ -165,7 +166,7 @@ void omega_step(Prec p, int pl, int Rr, int rr, int qr, const void* E, const voi
     d.bn = idx1(1);
     d.cm = idx1(qr);
     d.cn = idx1(1);
-    contract(p, d, E, F, Om, st);
+    contract(p, d, E, F, Om, st, ar);
 }
 
 // ---------------------------------------------------------------------------
@@ -185,7 +186,7 @@ void kr_precompute(Prec p, int s, int n, int Rl, int Rr, const void* S, const vo
 }
 
 void kr_step(Prec p, int s, int rl, int n, int rr, int Rl, int Rr, const void* P, const void* SA, const void* C,
-             void* Xbuf, void* Pout, hipStream_t st) {
+             void* Xbuf, void* Pout, hipStream_t st, Arena* ar) {
     // KR1: X[j][be][a][i'] = sum_al P[j][al][a] SA[j][al][i'][be]
     {
         ContractDesc d = cdesc(rl, Rr * n, Rl, s);
@@ -198,7 +199,7 @@ void kr_step(Prec p, int s, int rl, int n, int rr, int Rl, int Rr, const void* P
         d.cb = idx1((int64_t)Rr * rl * n);
         d.cm = idx1(n);
         d.cn = idx2(n, 1, (int64_t)rl * n);
-        contract(p, d, P, SA, Xbuf, st);
+        contract(p, d, P, SA, Xbuf, st, ar);
     }
     // KR2: P'[(j,be)][b] = sum_{(a,i')} X[(j,be)][(a,i')] C[(a,i')][b]
     {
@@ -209,7 +210,7 @@ void kr_step(Prec p, int s, int rl, int n, int rr, int Rl, int Rr, const void* P
         d.bn = idx1(1);
         d.cm = idx1(rr);
         d.cn = idx1(1);
-        contract(p, d, Xbuf, C, Pout, st);
+        contract(p, d, Xbuf, C, Pout, st, ar);
     }
 }
 
@@ -292,7 +293,7 @@ void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::
     set_one(p, F[d], st);
     for (int mu = d - 1; mu >= 1; --mu) {
         LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rx[mu], o.rx[mu + 1]};
-        right_step(p, s, F[mu + 1], x[mu], op ? o.D[mu] : nullptr, o.X[mu - 1], U1, U2, F[mu], st);
+        right_step(p, s, F[mu + 1], x[mu], op ? o.D[mu] : nullptr, o.X[mu - 1], U1, U2, F[mu], st, &ar);
     }
     // left sweep with Psi and Omega
     set_one(p, Ea, st);
@@ -301,13 +302,13 @@ void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::
     for (int mu = 0; mu < d; ++mu) {
         LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rho[mu], mu + 1 < d ? o.rho[mu + 1] : 1};
         const bool last = (mu == d - 1);
-        left_step(p, s, E, x[mu], op ? o.D[mu] : nullptr, nullptr, T1, T2, nullptr, st);
+        left_step(p, s, E, x[mu], op ? o.D[mu] : nullptr, nullptr, T1, T2, nullptr, st, &ar);
         const void* T2r = op ? T2 : T1;
         const int64_t npsi = (int64_t)o.rho[mu] * n[mu] * o.rx[mu + 1];
         if (p == Prec::F64) {
-            psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2r, F[mu + 1], Psi[mu], st);
+            psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2r, F[mu + 1], Psi[mu], st, &ar);
         } else {
-            psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2r, F[mu + 1], tmp_out, st);
+            psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2r, F[mu + 1], tmp_out, st, &ar);
             to_f64(p, npsi, tmp_out, Psi[mu], st);
         }
         if (!last) {
@@ -319,12 +320,12 @@ void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::
             dd.bn = idx1(1);
             dd.cm = idx1((int64_t)Rk(mu + 1) * r[mu + 1]);
             dd.cn = idx1(1);
-            contract(p, dd, o.Y[mu], T2r, En, st);
+            contract(p, dd, o.Y[mu], T2r, En, st, &ar);
             const int b = mu + 1;
             if (p == Prec::F64) {
-                omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], En, F[b], Omega[b - 1], st);
+                omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], En, F[b], Omega[b - 1], st, &ar);
             } else {
-                omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], En, F[b], tmp_out, st);
+                omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], En, F[b], tmp_out, st, &ar);
                 to_f64(p, (int64_t)o.rho[b] * o.rx[b], tmp_out, Omega[b - 1], st);
             }
             std::swap(E, En);
@@ -360,7 +361,7 @@ void kr_sketch_run(Prec p, int d, const int* n, int s, const std::vector<int>& R
     void* P = Pa;
     void* Pn = Pb;
     for (int mu = 0; mu < d; ++mu) {
-        kr_step(p, s, r[mu], n[mu], r[mu + 1], R[mu], R[mu + 1], P, SA[mu], x[mu], Xb, Pn, st);
+        kr_step(p, s, r[mu], n[mu], r[mu + 1], R[mu], R[mu + 1], P, SA[mu], x[mu], Xb, Pn, st, &ar);
         std::swap(P, Pn);
     }
     to_f64(p, s, P, w, st);
@@ -390,7 +391,7 @@ void inner_run(Prec p, int d, const int* n, const std::vector<int>& R, const std
     void* En = Eb;
     for (int mu = 0; mu < d; ++mu) {
         LeftDims s{rx_[mu], n[mu], rx_[mu + 1], Rk(mu), Rk(mu + 1), rz[mu], rz[mu + 1]};
-        left_step(p, s, E, x[mu], op ? D[mu] : nullptr, z[mu], T1, T2, En, st);
+        left_step(p, s, E, x[mu], op ? D[mu] : nullptr, z[mu], T1, T2, En, st, &ar);
         std::swap(E, En);
     }
     hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, st, E, p == Prec::F64 ? 1 : 0, out_dev);

@@ -95,9 +95,13 @@ struct ContractDesc {
 // Element types of the contraction kernels.
 enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
 
+class Arena;
 // Launchers (contract.hip).  A/B are float64 for F64, float32 for F32, and
 // bf16 (uint16_t storage) for BF16; C is float64 for F64 and float32 otherwise.
-void contract(Prec p, const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st);
+// With an arena, reductions too long for the output tiles to fill the chip are
+// split over several workgroups (partials in the arena, summed in fixed order).
+void contract(Prec p, const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st,
+              Arena* ar = nullptr);
 
 // Element-wise helpers (misc.hip).
 void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);   // y = a x + b y
