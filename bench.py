@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="wall-clock budget of the oracle sample")
     ap.add_argument("--no-fp64-leg", action="store_true", help="skip timing the FP64 path beside the mixed one")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy a 256 MiB buffer with a plain device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -152,6 +154,13 @@ def main():
     from paper_2409_09471_amd import ttsg
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("# calibration copy: 268435456 bytes read, 268435456 bytes written", file=sys.stderr, flush=True)
+        del src, dst
     w, t = build_inputs("cuda:0")
     prec = ttsg.PREC_MIXED if args.precision == "mixed" else ttsg.PREC_F64
     el, results, stats = timed_solves(w, t, prec, args.steps, args.warmup)

@@ -93,13 +93,15 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const T* 
                                                        const T* __restrict__ B,
                                                        typename Traits<T>::out_t* __restrict__ C,
                                                        int batch0, int splits, int kchunk,
-                                                       typename Traits<T>::out_t* __restrict__ part) {
+                                                       typename Traits<T>::out_t* __restrict__ part,
+                                                       DevSlot* slot) {
     using acc4 = typename Traits<T>::acc4;
     using out_t = typename Traits<T>::out_t;
     constexpr int BK = Traits<T>::BK;
     __shared__ T As[BK][BM + 1];
     __shared__ T Bs[BK][BN + 1];
 
+    slot_begin(slot);
     const int zz = batch0 + blockIdx.z;
     const int bidx = zz / splits;
     const int split = zz - bidx * splits;
@@ -187,6 +189,7 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const T* 
                     }
                 }
             }
+    slot_end(slot);
 }
 
 template <typename O>
@@ -253,7 +256,8 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         out_t* part = ar->get<out_t>((size_t)splits * d.batch * d.M * d.N);
         const int zt = d.batch * splits;
         hipLaunchKernelGGL(contract_kernel<T>, dim3(gx, gy, zt), block, 0, st, d, static_cast<const T*>(A),
-                           static_cast<const T*>(B), static_cast<out_t*>(C), 0, splits, kchunk, part);
+                           static_cast<const T*>(B), static_cast<out_t*>(C), 0, splits, kchunk, part,
+                           scope.slot());
         const int64_t total = (int64_t)d.batch * d.M * d.N;
         const int rb = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 8192));
         hipLaunchKernelGGL(reduce_splits<out_t>, dim3(rb), dim3(256), 0, st, d, splits, part, static_cast<out_t*>(C));
@@ -264,7 +268,7 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
             dim3 grid(gx, gy, nb);
             hipLaunchKernelGGL(contract_kernel<T>, grid, block, 0, st, d, static_cast<const T*>(A),
                                static_cast<const T*>(B), static_cast<out_t*>(C), b0, 1, d.K,
-                               static_cast<out_t*>(nullptr));
+                               static_cast<out_t*>(nullptr), scope.slot());
         }
     }
     TTSG_HIP(hipGetLastError());

@@ -27,7 +27,8 @@ __device__ __forceinline__ double wsum(double v) {
 }
 
 __global__ __launch_bounds__(LA_THREADS) void k_qr(int m, int c, double* __restrict__ A, int lda, int64_t sA,
-                                                    double* __restrict__ tau, int64_t sT) {
+                                                    double* __restrict__ tau, int64_t sT, DevSlot* slot) {
+    slot_begin(slot);
     A += blockIdx.x * sA;
     tau += blockIdx.x * sT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
@@ -73,11 +74,13 @@ __global__ __launch_bounds__(LA_THREADS) void k_qr(int m, int c, double* __restr
         }
         __syncthreads();
     }
+    slot_end(slot);
 }
 
 __global__ __launch_bounds__(LA_THREADS) void k_form_q(int m, int c, const double* __restrict__ A, int lda,
                                                         int64_t sA, const double* __restrict__ tau, int64_t sT,
-                                                        double* __restrict__ Q, int ldq, int64_t sQ) {
+                                                        double* __restrict__ Q, int ldq, int64_t sQ, DevSlot* slot) {
+    slot_begin(slot);
     A += blockIdx.x * sA;
     tau += blockIdx.x * sT;
     Q += blockIdx.x * sQ;
@@ -102,6 +105,7 @@ __global__ __launch_bounds__(LA_THREADS) void k_form_q(int m, int c, const doubl
         }
         __syncthreads();
     }
+    slot_end(slot);
 }
 
 __device__ __forceinline__ void circle_pair(int r, int k, int cp, int& p, int& q) {
@@ -117,7 +121,8 @@ __device__ __forceinline__ void circle_pair(int r, int k, int cp, int& p, int& q
 __global__ __launch_bounds__(LA_THREADS) void k_jacobi(int m, int c, double* __restrict__ A, int lda, int64_t sA,
                                                         double* __restrict__ V, int ldv, int64_t sV,
                                                         double* __restrict__ sig, int64_t sS, int maxsweeps,
-                                                        double tol) {
+                                                        double tol, DevSlot* slot) {
+    slot_begin(slot);
     A += blockIdx.x * sA;
     V += blockIdx.x * sV;
     sig += blockIdx.x * sS;
@@ -180,6 +185,7 @@ __global__ __launch_bounds__(LA_THREADS) void k_jacobi(int m, int c, double* __r
         s = wsum(s);
         if (lane == 0) sig[l] = sqrt(s);
     }
+    slot_end(slot);
 }
 
 }  // namespace
@@ -195,7 +201,8 @@ void qr_householder(int32_t batch, int32_t m, int32_t c, double* A, int32_t lda,
     const double kq = std::min(m, c);
     StatScope scope(TTSG_ST_QR, batch * (2.0 * m * c * kq - 2.0 / 3.0 * kq * kq * kq),
                     batch * 16.0 * m * c, st);
-    hipLaunchKernelGGL(k_qr, dim3(batch), dim3(LA_THREADS), 0, st, m, c, A, lda, strideA, tau, strideTau);
+    hipLaunchKernelGGL(k_qr, dim3(batch), dim3(LA_THREADS), 0, st, m, c, A, lda, strideA, tau, strideTau,
+                       scope.slot());
     TTSG_HIP(hipGetLastError());
 }
 
@@ -212,7 +219,7 @@ void qr_form_q(int32_t batch, int32_t m, int32_t c, const double* A, int32_t lda
     StatScope scope(TTSG_ST_QR, batch * (4.0 * m * kq * kq - 4.0 / 3.0 * kq * kq * kq),
                     batch * 16.0 * m * kq, st);
     hipLaunchKernelGGL(k_form_q, dim3(batch), dim3(LA_THREADS), 0, st, m, c, A, lda, strideA, tau, strideTau, Q,
-                       ldq, strideQ);
+                       ldq, strideQ, scope.slot());
     TTSG_HIP(hipGetLastError());
 }
 
@@ -230,7 +237,7 @@ void svd_jacobi(int32_t batch, int32_t m, int32_t c, double* A, int32_t lda, int
     // rotated column pairs (m and c long)
     StatScope scope(TTSG_ST_SVD, batch * 0.5 * c * (c - 1.0) * (12.0 * m + 6.0 * c), batch * 16.0 * m * c, st);
     hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(LA_THREADS), 0, st, m, c, A, lda, strideA, V, ldv, strideV,
-                       sig, strideSig, 40, m * 2.220446049250313e-16);
+                       sig, strideSig, 40, m * 2.220446049250313e-16, scope.slot());
     TTSG_HIP(hipGetLastError());
 }
 

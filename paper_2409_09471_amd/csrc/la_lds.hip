@@ -31,6 +31,7 @@ __device__ __forceinline__ double wsum(double v) {
 struct JacobiBatch {
     int count;
     int m[32], c[32], lda[32];
+    double tol[32];
     double* A[32];
     double* V[32];
     double* sig[32];
@@ -56,12 +57,15 @@ template <int G> __device__ __forceinline__ double gsum(double v) {
 // registers, and rotates the same rows, so a round of the circle method costs
 // a single barrier.  The pairs of every round come from a table built once.
 constexpr int JG = 32;
-__global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps, double tol) {
+__global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps, DevSlot* slot) {
     extern __shared__ double lds[];
+    slot_begin(slot);
+    int sweeps_done = 0;
     __shared__ short tab[2 * 32 * 63];      // (p, q) of pair k in round r, c <= 64
     __shared__ int s_rot;
     const int bi = blockIdx.x;
     const int m = jb.m[bi], c = jb.c[bi], lda = jb.lda[bi];
+    const double tol = jb.tol[bi];
     double* Ag = jb.A[bi];
     double* Vg = jb.V[bi];
     const int ldm = m | 1;
@@ -115,6 +119,7 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
     const double tiny = 4.930380657631324e-32 * s_fro;   // (eps ||A||_F)^2
     for (int sweep = 0; sweep < maxsweeps && cp > 1; ++sweep) {
         int rotated = 0;
+        sweeps_done = sweep + 1;
         for (int r = 0; r < nround; ++r) {
             for (int k = grp; k < npair; k += ngrp) {
                 const int p = tab[2 * (r * npair + k)], q = tab[2 * (r * npair + k) + 1];
@@ -175,6 +180,7 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
         s2 = gsum<JG>(s2);
         if (lt == 0) jb.sig[bi][l] = sqrt(s2);
     }
+    slot_end(slot, (unsigned long long)sweeps_done);
 }
 
 // Leaf i of a TSQR level: rows [r0, r1) of the column-major m x c matrix A.
@@ -189,8 +195,10 @@ __device__ __forceinline__ void leaf_rows(int m, int nleaves, int i, int& r0, in
 constexpr int QG = 16;
 __global__ __launch_bounds__(QT) void k_qr_leaf(int m, int c, const double* __restrict__ A, int lda,
                                                  int nleaves, double* __restrict__ refl, int ldr,
-                                                 double* __restrict__ tau, double* __restrict__ Rs, int ldrs) {
+                                                 double* __restrict__ tau, double* __restrict__ Rs, int ldrs,
+                                                 DevSlot* slot) {
     extern __shared__ double T[];
+    slot_begin(slot);
     __shared__ double s_tau, s_scale;
     const int i = blockIdx.x;
     int r0, r1;
@@ -253,14 +261,17 @@ __global__ __launch_bounds__(QT) void k_qr_leaf(int m, int c, const double* __re
         int j = e / c, r = e - j * c;
         Rs[(int64_t)j * ldrs + (int64_t)i * c + r] = (r <= j && r < kk) ? T[j * ldt + r] : 0.0;
     }
+    slot_end(slot);
 }
 
 // Out (rows of this level x k) = blockdiag(Q_i) [B_i; 0], B_i = rows i*c.. of Bin.
 __global__ __launch_bounds__(QT) void k_qr_apply_leaf(int m, int c, int k, const double* __restrict__ refl, int ldr,
                                                        const double* __restrict__ tau, int nleaves,
                                                        const double* __restrict__ Bin, int ldb,
-                                                       double* __restrict__ Out, int ldo, int out_rowmajor) {
+                                                       double* __restrict__ Out, int ldo, int out_rowmajor,
+                                                       DevSlot* slot) {
     extern __shared__ double X[];
+    slot_begin(slot);
     const int i = blockIdx.x;
     int r0, r1;
     leaf_rows(m, nleaves, i, r0, r1);
@@ -298,6 +309,7 @@ __global__ __launch_bounds__(QT) void k_qr_apply_leaf(int m, int c, int k, const
         else
             Out[(int64_t)t * ldo + r0 + r] = X[t * ldx + r];
     }
+    slot_end(slot);
 }
 
 // Dynamic LDS above the default limit must be requested per kernel; the
@@ -338,6 +350,8 @@ void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st) {
             jb.A[cnt] = j.A;
             jb.V[cnt] = j.V;
             jb.sig[cnt] = j.sig;
+            // below m eps a computed dot product is rounding noise
+            jb.tol[cnt] = j.tol > 0.0 ? j.tol : 4.0 * j.m * 2.220446049250313e-16;
             lds = std::max(lds, jacobi_lds_bytes(j.m, j.c));
             flops += 0.5 * j.c * (j.c - 1.0) * (12.0 * j.m + 6.0 * j.c);
             if (bounds_checking()) {
@@ -349,11 +363,7 @@ void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st) {
         jb.count = cnt;
         StatScope scope(TTSG_ST_SVD, flops, 0.0, st);
         allow_lds(reinterpret_cast<const void*>(&k_jacobi_lds), lds, g_lds_jacobi);
-        // a pair counts as orthogonal once |a_p.a_q| <= m eps ||a_p|| ||a_q||: below
-        // that the computed dot product is rounding noise and sweeps never end
-        int mmax = 1;
-        for (int t = 0; t < cnt; ++t) mmax = std::max(mmax, jb.m[t]);
-        hipLaunchKernelGGL(k_jacobi_lds, dim3(cnt), dim3(JT), lds, st, jb, 30, 4.0 * mmax * 2.220446049250313e-16);
+        hipLaunchKernelGGL(k_jacobi_lds, dim3(cnt), dim3(JT), lds, st, jb, 30, scope.slot());
         TTSG_HIP(hipGetLastError());
     }
 }
@@ -388,7 +398,7 @@ void TsqrPlan::factor(int m_, int c_, const double* A, int lda, Arena& ar, hipSt
             StatScope scope(TTSG_ST_QR, L.nleaves * (2.0 * maxrows * c * kq - 2.0 / 3.0 * kq * kq * kq), 0.0, st);
             allow_lds(reinterpret_cast<const void*>(&k_qr_leaf), lds, g_lds_leaf);
             hipLaunchKernelGGL(k_qr_leaf, dim3(L.nleaves), dim3(QT), lds, st, rows, c, in, ld_in, L.nleaves, L.refl,
-                               rows, L.tau, L.stack, ldstack);
+                               rows, L.tau, L.stack, ldstack, scope.slot());
             TTSG_HIP(hipGetLastError());
         }
         levels.push_back(L);
@@ -424,7 +434,8 @@ void TsqrPlan::apply(int k, const double* B, int ldb, double* Out, int ldo, bool
             StatScope scope(TTSG_ST_QR, L.nleaves * 4.0 * maxrows * c * (double)k, 0.0, st);
             allow_lds(reinterpret_cast<const void*>(&k_qr_apply_leaf), lds, g_lds_apply);
             hipLaunchKernelGGL(k_qr_apply_leaf, dim3(L.nleaves), dim3(QT), lds, st, L.rows, c, k, L.refl, L.rows,
-                               L.tau, L.nleaves, in, ld_in, out, ld_out, (last && out_rowmajor) ? 1 : 0);
+                               L.tau, L.nleaves, in, ld_in, out, ld_out, (last && out_rowmajor) ? 1 : 0,
+                               scope.slot());
             TTSG_HIP(hipGetLastError());
         }
         in = out;

@@ -51,9 +51,9 @@ void eye(int c, double* I, hipStream_t st) {
 }
 
 // SVD of a c x c column-major matrix in place (LDS kernel when it fits).
-void svd_small(int c, double* A, double* V, double* sig, hipStream_t st) {
+void svd_small(int c, double* A, double* V, double* sig, hipStream_t st, double tol = 0.0) {
     if (jacobi_lds_fits(c, c)) {
-        svd_jacobi_batched({JacobiJob{c, c, c, A, V, sig}}, st);
+        svd_jacobi_batched({JacobiJob{c, c, c, A, V, sig, tol}}, st);
     } else {
         svd_jacobi(1, c, c, A, c, 0, V, c, 0, sig, 0, st);
     }
@@ -226,7 +226,12 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
                 qr_form_q(1, m, c, A, m, 0, tau, 0, Q, m, 0, st);
                 extract_r(c, c, A, m, Rm, c, st);
             }
-            svd_small(c, Rm, V, sig, st);
+            // SVD of R through one-sided Jacobi on R^T (rows of a QR factor of a
+            // graded unfolding converge in few sweeps): R^T V' = U' S gives
+            // R = V' S U'^T, i.e. U_R = V' and S V_R^T = (U' S)^T.  Relative
+            // orthogonality 1e-11 is far below every rounding tolerance used.
+            transpose2d(c, c, Rm, c, QV, c, st);              // QV = R^T (column-major)
+            svd_small(c, QV, V, sig, st, 1e-11);
             hsig.assign(c, 0.0);
             TTSG_HIP(hipMemcpyAsync(hsig.data(), sig, c * sizeof(double), hipMemcpyDeviceToHost, st));
             TTSG_HIP(hipStreamSynchronize(st));
@@ -235,19 +240,12 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             for (int t = 0; t < c; ++t) sd[t] = hsig[perm[t]];
             k = trunc_rank(sd, delta, maxrank);
             k = std::min(k, c);
-            // Uk (c x k, column-major) = (U Sigma)[:, perm] / sigma
             std::vector<int> pk(perm.begin(), perm.begin() + k);
-            std::vector<double> inv(k), sv(k);
-            for (int t = 0; t < k; ++t) {
-                double s = hsig[pk[t]];
-                inv[t] = s > 0.0 ? 1.0 / s : 0.0;
-                sv[t] = s;
-            }
             hold_i.push_back(pk);
-            hold_d.push_back(inv);
-            hold_d.push_back(sv);
-            upload_perm(hold_i.back(), hold_d[hold_d.size() - 2], perm_dev, fac_dev, st);
-            gather_cols(c, k, Rm, c, T, c, perm_dev, fac_dev, st);
+            hold_d.push_back(std::vector<double>(k, 1.0));
+            upload_perm(hold_i.back(), hold_d.back(), perm_dev, fac_dev, st);
+            // Uk (c x k, column-major) = V'[:, perm]
+            gather_cols(c, k, V, c, T, c, perm_dev, fac_dev, st);
             // new core (row-major m x k) = Q (m x c) * Uk
             if (tsqr) {
                 plan.apply(k, T, c, w[mu], k, true, ar, st);
@@ -255,9 +253,9 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
                 gemm_cm_cm(m, k, c, Q, m, T, c, w[mu], k, st, &ar);
             }
             ar.release(mk);
-            // SVt (row-major k x c) = column-major c x k of V[:, perm] * sigma
-            TTSG_HIP(hipMemcpyAsync(fac_dev, hold_d.back().data(), k * sizeof(double), hipMemcpyHostToDevice, st));
-            gather_cols(c, k, V, c, QV, c, perm_dev, fac_dev, st);
+            // S V_R^T (row-major k x c == column-major c x k) = (U' S)[:, perm]
+            gather_cols(c, k, QV, c, Rm, c, perm_dev, fac_dev, st);
+            copy_f64((int64_t)c * k, Rm, QV, st);
         } else {
             // wide unfolding: M^T (c x m) is the row-major core read column-major
             copy_f64((int64_t)m * c, w[mu], A, st);

@@ -1,4 +1,10 @@
 // Launch measurement behind ttsg_stats_enable / ttsg_stats_read.
+//
+// Every measured launch gets one DevSlot in a device array; its workgroups
+// record the earliest start and latest end of the GPU wall clock.  The
+// duration of a launch is therefore the time its kernel actually ran, not the
+// gap between host-side events (which would include submission latency
+// whenever the stream had drained).
 #include <mutex>
 
 #include "ttsg_internal.h"
@@ -7,37 +13,33 @@ namespace ttsg {
 namespace {
 
 struct Rec {
-    hipEvent_t a, b;
     int cls;
     double flops, bytes;
+    int64_t slot;
 };
 
+constexpr int64_t kSlots = 1 << 20;
 std::mutex g_mu;
 std::vector<Rec> g_recs;
 bool g_on = false;
+DevSlot* g_slots = nullptr;
+int64_t g_next = 0;
 
 }  // namespace
 
 bool stats_on() { return g_on; }
 
-StatScope::StatScope(int cls, double flops, double bytes, hipStream_t st)
-    : cls_(cls), flops_(flops), bytes_(bytes), st_(st) {
+StatScope::StatScope(int cls, double flops, double bytes, hipStream_t st) {
+    (void)st;
     if (!g_on) return;
-    hipEvent_t a, b;
-    TTSG_HIP(hipEventCreate(&a));
-    TTSG_HIP(hipEventCreate(&b));
-    TTSG_HIP(hipEventRecord(a, st));
-    a_ = a;
-    b_ = b;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_next >= kSlots) return;           // beyond the slot budget: not measured
+    const int64_t id = g_next++;
+    slot_ = g_slots + id;
+    g_recs.push_back(Rec{cls, flops, bytes, id});
 }
 
-StatScope::~StatScope() {
-    if (a_ == nullptr) return;
-    hipEvent_t a = static_cast<hipEvent_t>(a_), b = static_cast<hipEvent_t>(b_);
-    if (hipEventRecord(b, st_) != hipSuccess) return;
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_recs.push_back(Rec{a, b, cls_, flops_, bytes_});
-}
+StatScope::~StatScope() = default;
 
 }  // namespace ttsg
 
@@ -45,12 +47,15 @@ extern "C" {
 
 int ttsg_stats_enable(int32_t on) {
     std::lock_guard<std::mutex> lk(ttsg::g_mu);
-    for (auto& r : ttsg::g_recs) {
-        (void)hipEventSynchronize(r.b);
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
-    }
     ttsg::g_recs.clear();
+    ttsg::g_next = 0;
+    if (on) {
+        if (ttsg::g_slots == nullptr) {
+            if (hipMalloc(&ttsg::g_slots, ttsg::kSlots * sizeof(ttsg::DevSlot)) != hipSuccess) return -TTSG_ERR_HIP;
+        }
+        if (hipMemset(ttsg::g_slots, 0, ttsg::kSlots * sizeof(ttsg::DevSlot)) != hipSuccess) return -TTSG_ERR_HIP;
+        if (hipDeviceSynchronize() != hipSuccess) return -TTSG_ERR_HIP;
+    }
     ttsg::g_on = on != 0;
     return 0;
 }
@@ -62,20 +67,32 @@ int ttsg_stats_read(ttsg_stats* out) {
         out->launches[c] = 0;
         out->flops[c] = out->bytes[c] = out->seconds[c] = 0.0;
     }
-    int rc = 0;
-    for (auto& r : ttsg::g_recs) {
-        float ms = 0.0f;
-        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) rc = -TTSG_ERR_HIP;
+    if (hipDeviceSynchronize() != hipSuccess) return -TTSG_ERR_HIP;
+    int rate_khz = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
+        return -TTSG_ERR_HIP;
+    std::vector<ttsg::DevSlot> h(ttsg::g_next);
+    if (ttsg::g_next > 0 &&
+        hipMemcpy(h.data(), ttsg::g_slots, ttsg::g_next * sizeof(ttsg::DevSlot), hipMemcpyDeviceToHost) != hipSuccess)
+        return -TTSG_ERR_HIP;
+    for (const auto& r : ttsg::g_recs) {
+        const ttsg::DevSlot& s = h[r.slot];
+        if (s.end == 0 || s.start_inv == 0) continue;      // launch without workgroups
+        const unsigned long long t0 = ~s.start_inv;
+        const double sec = s.end > t0 ? (double)(s.end - t0) / (1e3 * rate_khz) : 0.0;
         const int c = r.cls;
         out->launches[c] += 1;
         out->flops[c] += r.flops;
         out->bytes[c] += r.bytes;
-        out->seconds[c] += 1e-3 * (double)ms;
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
+        out->seconds[c] += sec;
+        if (c == TTSG_ST_SVD && s.aux > (unsigned long long)out->flops[7]) out->flops[7] = (double)s.aux;
     }
     ttsg::g_recs.clear();
-    return rc;
+    ttsg::g_next = 0;
+    if (hipMemset(ttsg::g_slots, 0, ttsg::kSlots * sizeof(ttsg::DevSlot)) != hipSuccess) return -TTSG_ERR_HIP;
+    return 0;
 }
 
 }  // extern "C"

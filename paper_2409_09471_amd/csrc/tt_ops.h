@@ -99,6 +99,7 @@ struct JacobiJob {
     double* A;            // in: matrix; out: U * Sigma
     double* V;            // out: c x c right singular vectors (column-major, ld c)
     double* sig;          // out: c singular values (unsorted)
+    double tol = 0.0;     // stop when every |a_p.a_q| <= tol ||a_p|| ||a_q|| (0: 4 m eps)
 };
 bool jacobi_lds_fits(int m, int c);
 // One launch for up to 32 matrices (more are split into several launches).

@@ -71,18 +71,37 @@ inline int64_t idx_max(const Idx2& ix, int32_t extent) {
 void check_range(const void* p, size_t bytes, const char* what);
 bool bounds_checking();
 
-// Launch measurement (stats.hip): when enabled, StatScope records a HIP event
-// pair around one launch on `st`, tagged with a class and its work counts.
+// Launch measurement (stats.hip): when enabled, StatScope hands the launch a
+// device slot in which its workgroups record the earliest start and latest end
+// of the wall clock (so host gaps between launches are not counted), plus an
+// auxiliary maximum (e.g. Jacobi sweeps).  Kernels take the slot pointer
+// (nullptr when measurement is off) and call slot_begin / slot_end.
+struct DevSlot {
+    unsigned long long start_inv;   // max over workgroups of ~t_start
+    unsigned long long end;         // max over workgroups of t_end
+    unsigned long long aux;
+    unsigned long long pad;
+};
 bool stats_on();
 struct StatScope {
     StatScope(int cls, double flops, double bytes, hipStream_t st);
     ~StatScope();
-    int cls_;
-    double flops_, bytes_;
-    hipStream_t st_;
-    void* a_ = nullptr;
-    void* b_ = nullptr;
+    DevSlot* slot() const { return slot_; }
+    DevSlot* slot_ = nullptr;
 };
+
+__device__ __forceinline__ void slot_begin(DevSlot* s) {
+    if (s != nullptr && threadIdx.x == 0) atomicMax(&s->start_inv, ~(unsigned long long)wall_clock64());
+}
+// Call from all threads of the workgroup (contains a barrier when s != nullptr).
+__device__ __forceinline__ void slot_end(DevSlot* s, unsigned long long aux = 0) {
+    if (s == nullptr) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicMax(&s->end, (unsigned long long)wall_clock64());
+        if (aux) atomicMax(&s->aux, aux);
+    }
+}
 
 // C[b][m][n] = alpha * sum_k A[b][m][k] * B[b][k][n] + beta * C[b][m][n]
 struct ContractDesc {
