@@ -118,74 +118,115 @@ __device__ __forceinline__ void circle_pair(int r, int k, int cp, int& p, int& q
     }
 }
 
-__global__ __launch_bounds__(LA_THREADS) void k_jacobi(int m, int c, double* __restrict__ A, int lda, int64_t sA,
-                                                        double* __restrict__ V, int ldv, int64_t sV,
-                                                        double* __restrict__ sig, int64_t sS, int maxsweeps,
-                                                        double tol, DevSlot* slot) {
+// One-sided Jacobi for matrices too large for LDS (they stay L2-resident).
+// Same structure as the LDS kernel: a lane group of 32 lanes owns a column
+// pair for a round, reduces the three dot products in registers and rotates
+// the rows it owns; one barrier per round.
+template <int G> __device__ __forceinline__ double gsum_g(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+
+__global__ __launch_bounds__(1024) void k_jacobi(int m, int c, double* __restrict__ A, int lda, int64_t sA,
+                                                  double* __restrict__ V, int ldv, int64_t sV,
+                                                  double* __restrict__ sig, int64_t sS, int maxsweeps,
+                                                  double tol, DevSlot* slot) {
     slot_begin(slot);
+    constexpr int G = 32;
     A += blockIdx.x * sA;
     V += blockIdx.x * sV;
     sig += blockIdx.x * sS;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int tid = threadIdx.x;
+    const int grp = tid / G, lt = tid - grp * G, ngrp = blockDim.x / G;
     for (int l = 0; l < c; ++l)
         for (int i = tid; i < c; i += blockDim.x) V[(int64_t)l * ldv + i] = (i == l) ? 1.0 : 0.0;
     __shared__ int s_rot;
-    const int cp = c + (c & 1);
+    __shared__ double s_fro;
+    if (tid == 0) {
+        s_rot = 0;
+        s_fro = 0.0;
+    }
     __syncthreads();
+    {
+        double f = 0.0;
+        for (int l = grp; l < c; l += ngrp)
+            for (int i = lt; i < m; i += G) f += A[(int64_t)l * lda + i] * A[(int64_t)l * lda + i];
+        f = gsum_g<G>(f);
+        if (lt == 0) atomicAdd(&s_fro, f);
+    }
+    __syncthreads();
+    // columns below 2 m eps ||A||_F carry only rounding noise (null space of a
+    // rank-deficient matrix); their mutual dot products never look orthogonal,
+    // so they are treated as converged
+    const double nz = 2.0 * m * 2.220446049250313e-16;
+    const double tiny = nz * nz * s_fro;
+    const int cp = c + (c & 1);
+    const int npair = cp / 2;
+    int sweeps_done = 0;
     for (int sweep = 0; sweep < maxsweeps && cp > 1; ++sweep) {
-        if (tid == 0) s_rot = 0;
-        __syncthreads();
+        int rotated = 0;
+        sweeps_done = sweep + 1;
         for (int r = 0; r < cp - 1; ++r) {
-            for (int pk = wave; pk < cp / 2; pk += nw) {
+            for (int k = grp; k < npair; k += ngrp) {
                 int p, q;
-                circle_pair(r, pk, cp, p, q);
+                if (k == 0) {
+                    p = cp - 1;
+                    q = r;
+                } else {
+                    p = (r + k) % (cp - 1);
+                    q = (r - k + cp - 1) % (cp - 1);
+                }
                 if (p >= c || q >= c) continue;
                 double* ap = A + (int64_t)p * lda;
                 double* aq = A + (int64_t)q * lda;
                 double al = 0.0, be = 0.0, ga = 0.0;
-                for (int i = lane; i < m; i += 64) {
-                    double x = ap[i], y = aq[i];
+                for (int i = lt; i < m; i += G) {
+                    const double x = ap[i], y = aq[i];
                     al += x * x;
                     be += y * y;
                     ga += x * y;
                 }
-                al = wsum(al);
-                be = wsum(be);
-                ga = wsum(ga);
-                if (al == 0.0 || be == 0.0) continue;
-                if (fabs(ga) <= tol * sqrt(al) * sqrt(be)) continue;
-                double zeta = (be - al) / (2.0 * ga);
-                double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
-                double cs = 1.0 / sqrt(1.0 + t * t);
-                double sn = cs * t;
-                for (int i = lane; i < m; i += 64) {
-                    double x = ap[i], y = aq[i];
+                al = gsum_g<G>(al);
+                be = gsum_g<G>(be);
+                ga = gsum_g<G>(ga);
+                if (al <= tiny || be <= tiny || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
+                const double cs = 1.0 / sqrt(1.0 + t * t);
+                const double sn = cs * t;
+                for (int i = lt; i < m; i += G) {
+                    const double x = ap[i], y = aq[i];
                     ap[i] = cs * x - sn * y;
                     aq[i] = sn * x + cs * y;
                 }
                 double* vp = V + (int64_t)p * ldv;
                 double* vq = V + (int64_t)q * ldv;
-                for (int i = lane; i < c; i += 64) {
-                    double x = vp[i], y = vq[i];
+                for (int i = lt; i < c; i += G) {
+                    const double x = vp[i], y = vq[i];
                     vp[i] = cs * x - sn * y;
                     vq[i] = sn * x + cs * y;
                 }
-                if (lane == 0) s_rot = 1;
+                rotated = 1;
             }
             __syncthreads();
         }
-        if (s_rot == 0) break;
+        if (rotated && lt == 0) s_rot = 1;
         __syncthreads();
+        const int any = s_rot;
+        __syncthreads();
+        if (tid == 0) s_rot = 0;
+        if (any == 0) break;
     }
     __syncthreads();
-    for (int l = wave; l < c; l += nw) {
+    for (int l = grp; l < c; l += ngrp) {
         const double* al = A + (int64_t)l * lda;
-        double s = 0.0;
-        for (int i = lane; i < m; i += 64) s += al[i] * al[i];
-        s = wsum(s);
-        if (lane == 0) sig[l] = sqrt(s);
+        double s2 = 0.0;
+        for (int i = lt; i < m; i += G) s2 += al[i] * al[i];
+        s2 = gsum_g<G>(s2);
+        if (lt == 0) sig[l] = sqrt(s2);
     }
-    slot_end(slot);
+    slot_end(slot, (unsigned long long)sweeps_done);
 }
 
 }  // namespace
@@ -236,8 +277,8 @@ void svd_jacobi(int32_t batch, int32_t m, int32_t c, double* A, int32_t lda, int
     // one sweep of c(c-1)/2 rotations, each three dot products and two
     // rotated column pairs (m and c long)
     StatScope scope(TTSG_ST_SVD, batch * 0.5 * c * (c - 1.0) * (12.0 * m + 6.0 * c), batch * 16.0 * m * c, st);
-    hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(LA_THREADS), 0, st, m, c, A, lda, strideA, V, ldv, strideV,
-                       sig, strideSig, 40, m * 2.220446049250313e-16, scope.slot());
+    hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(1024), 0, st, m, c, A, lda, strideA, V, ldv, strideV,
+                       sig, strideSig, 30, 4.0 * m * 2.220446049250313e-16, scope.slot());
     TTSG_HIP(hipGetLastError());
 }
 

@@ -322,34 +322,55 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         copy_f64(n[0], Psi[0], out[0], st);
         return;
     }
-    // SVD of every Omega_b (rho_b x rx_b, rho_b >= rx_b)
-    std::vector<double*> Ab(d), Vb(d), Sb(d), Gb(d), Vk(d);
+    // SVD of every Omega_b (rho_b x rx_b, rho_b >= rx_b) as Omega = Q R followed
+    // by one-sided Jacobi on R^T (graded matrices converge in a third of the
+    // sweeps that Jacobi on Omega itself needs): R^T W = U_B S gives
+    // Omega = (Q W) S U_B^T, so Omega^+ = U_B S^-1 (Q W)^T.
+    std::vector<double*> Ab(d), Rt(d), Wb(d), Sb(d), Gb(d), Vk(d), Wk(d), Qb(d);
     std::vector<int*> permb(d);
     std::vector<double*> facb(d);
+    std::vector<TsqrPlan> plans(d);
+    std::vector<bool> use_tsqr(d, false);
     int64_t maxT = 1;
     for (int b = 1; b <= d - 1; ++b) {
         const int m = rho[b], c = rx[b];
         TTSG_CHECK(m >= c, TTSG_ERR_ARG, "STTA needs rho_b >= rx_b");
         Ab[b] = ar.get<double>((int64_t)m * c);
-        Vb[b] = ar.get<double>((int64_t)c * c);
+        Rt[b] = ar.get<double>((int64_t)c * c);
+        Wb[b] = ar.get<double>((int64_t)c * c);
         Sb[b] = ar.get<double>(c);
         Gb[b] = ar.get<double>((int64_t)m * c);
         Vk[b] = ar.get<double>((int64_t)c * c);
+        Wk[b] = ar.get<double>((int64_t)c * c);
         permb[b] = ar.get<int>(c);
         facb[b] = ar.get<double>(2 * (int64_t)c);
-        transpose2d(m, c, Omega[b - 1], c, Ab[b], m, st);
+        transpose2d(m, c, Omega[b - 1], c, Ab[b], m, st);        // column-major m x c
+        use_tsqr[b] = tsqr_fits(m, c);
+        if (use_tsqr[b]) {
+            plans[b].factor(m, c, Ab[b], m, ar, st);
+            transpose2d(c, c, plans[b].R, c, Rt[b], c, st);       // R (column-major) -> R^T
+        } else {
+            double* tau = ar.get<double>(c);
+            double* Rm = ar.get<double>((int64_t)c * c);
+            Qb[b] = ar.get<double>((int64_t)m * c);
+            qr_householder(1, m, c, Ab[b], m, 0, tau, 0, st);
+            qr_form_q(1, m, c, Ab[b], m, 0, tau, 0, Qb[b], m, 0, st);
+            extract_r(c, c, Ab[b], m, Rm, c, st);
+            transpose2d(c, c, Rm, c, Rt[b], c, st);
+        }
     }
     {
         std::vector<JacobiJob> jobs;
         for (int b = 1; b <= d - 1; ++b) {
-            if (jacobi_lds_fits(rho[b], rx[b]))
-                jobs.push_back(JacobiJob{rho[b], rx[b], rho[b], Ab[b], Vb[b], Sb[b]});
+            if (jacobi_lds_fits(rx[b], rx[b]))
+                jobs.push_back(JacobiJob{rx[b], rx[b], rx[b], Rt[b], Wb[b], Sb[b]});
             else
-                svd_jacobi(1, rho[b], rx[b], Ab[b], rho[b], 0, Vb[b], rx[b], 0, Sb[b], 0, st);
+                svd_jacobi(1, rx[b], rx[b], Rt[b], rx[b], 0, Wb[b], rx[b], 0, Sb[b], 0, st);
         }
         if (!jobs.empty()) svd_jacobi_batched(jobs, st);
     }
     for (int mu = 0; mu < d; ++mu) maxT = std::max<int64_t>(maxT, (int64_t)rx[mu] * n[mu] * rx[mu + 1]);
+    for (int b = 1; b <= d - 1; ++b) maxT = std::max<int64_t>(maxT, (int64_t)rho[b] * rx[b]);
     double* T = ar.get<double>(maxT);
     std::vector<std::vector<double>> hs(d);
     for (int b = 1; b <= d - 1; ++b) {
@@ -366,19 +387,25 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         while (k < (int)p.size() && hs[b][p[k]] > rcond * smax && hs[b][p[k]] > 0.0) ++k;
         k = std::max(k, 1);
         keep[b].assign(p.begin(), p.begin() + k);
-        facs[b].resize(2 * k);
+        facs[b].resize(k);
         for (int t = 0; t < k; ++t) {
-            double s = hs[b][keep[b][t]];
-            facs[b][t] = s > 0.0 ? 1.0 / (s * s) : 0.0;
-            facs[b][k + t] = 1.0;
+            double sv = hs[b][keep[b][t]];
+            facs[b][t] = sv > 0.0 ? 1.0 / sv : 0.0;
         }
         r_out[b] = k;
         TTSG_HIP(hipMemcpyAsync(permb[b], keep[b].data(), k * sizeof(int), hipMemcpyHostToDevice, st));
-        TTSG_HIP(hipMemcpyAsync(facb[b], facs[b].data(), 2 * k * sizeof(double), hipMemcpyHostToDevice, st));
-        // G_b (row-major k x rho == column-major rho x k) = (U S)[:, keep] / s^2
-        gather_cols(rho[b], k, Ab[b], rho[b], Gb[b], rho[b], permb[b], facb[b], st);
-        // V'_b (column-major rx x k) = V[:, keep]
-        gather_cols(rx[b], k, Vb[b], rx[b], Vk[b], rx[b], permb[b], facb[b] + k, st);
+        TTSG_HIP(hipMemcpyAsync(facb[b], facs[b].data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+        const int m = rho[b], c = rx[b];
+        // V'_b (column-major rx x k) = U_B[:, keep] = (U_B S)[:, keep] / s
+        gather_cols(c, k, Rt[b], c, Vk[b], c, permb[b], facb[b], st);
+        // G_b (row-major k x rho == column-major rho x k) = Q W[:, keep] / s
+        gather_cols(c, k, Wb[b], c, Wk[b], c, permb[b], facb[b], st);
+        if (use_tsqr[b]) {
+            plans[b].apply(k, Wk[b], c, Gb[b], m, false, ar, st);
+        } else {
+            gemm_cm_cm(m, k, c, Qb[b], m, Wk[b], c, T, k, st, &ar);   // row-major m x k
+            transpose2d(m, k, T, k, Gb[b], m, st);                    // column-major m x k
+        }
     }
     for (int mu = 0; mu < d; ++mu) {
         const int nn = n[mu];

@@ -166,8 +166,8 @@ def test_sgmres_small_matches_oracle_iterates():
     assert tt_rel(host(res.x), xo) < 1e-5
 
 
-@pytest.mark.slow
 def test_c1_fp64_solution_against_dst():
+    """d=5, n=16 FP64 workload: restart 20, s=40, q=2, full STTA ranks; closed-form check."""
     w = syn.config_c1()
     res = _solve(w)
     x = host(res.x)
