@@ -211,14 +211,37 @@ int ttsg_dot(int32_t d, const int32_t* n, const int32_t* rxr, const double* cons
              void* ws, size_t ws_bytes, ttsg_stream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* Differentiation of a Kronecker-sum solve                                   */
+/* ------------------------------------------------------------------------- */
+/* For A(theta) = sum_k theta_k (I x .. x L_k x .. x I) and the adjoint state
+ * lambda = A^-T dLoss/dx, dLoss/dtheta_k = -<lambda, L_k x>.  All d values come
+ * from one left and one right environment sweep of <lambda, x> plus one local
+ * contraction per mode: g_k = E_k . (lambda_k, L_k x_k) . F_{k+1}.
+ * L: d DEVICE pointers to n[k] x n[k] row-major matrices (the unscaled L_k);
+ * out: HOST double[d] receives -<lambda, L_k x>.  Synchronizes `stream`. */
+int ttsg_grad_kron_sum(int32_t d, const int32_t* n, const double* const* L,
+                       const int32_t* rl, const double* const* lam,
+                       const int32_t* rx, const double* const* x,
+                       double* out, void* ws, size_t ws_bytes, ttsg_stream_t stream);
+
+/* z = alpha x + beta y as a TT with block cores (ranks add; Sec. 2.2).
+ * z cores have shape (rx[k]+ry[k]) x n[k] x (rx[k+1]+ry[k+1]) for 0 < k < d-1,
+ * 1 x n x (rx[1]+ry[1]) first and (rx[d-1]+ry[d-1]) x n x 1 last (d = 1: n).
+ * Does not synchronize. */
+int ttsg_tt_axpby(int32_t d, const int32_t* n, double alpha, const int32_t* rx, const double* const* x,
+                  double beta, const int32_t* ry, const double* const* y, double* const* z,
+                  ttsg_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
 /* Measurement: per-kernel-class counters.  While enabled, every contraction */
-/* and factorization launch is bracketed by HIP events recorded on the       */
-/* stream it is launched on; ttsg_stats_read synchronizes those events and    */
-/* returns, per class, the launch count, the algorithmic flops (2*M*N*K*batch */
-/* per contraction; the textbook counts for QR and one Jacobi sweep), the     */
-/* operand bytes (A + B + C, an operand shared across a batch counted once)  */
-/* and the summed kernel durations.  Measurement adds an event pair per      */
-/* launch; it is meant for benchmarking, not for production solves.          */
+/* and factorization launch records on the GPU the wall-clock time at which  */
+/* its first workgroup started and its last one ended (one small device slot */
+/* per launch); ttsg_stats_read synchronizes the device and returns, per     */
+/* class, the launch count, the algorithmic flops (2*M*N*K*batch per         */
+/* contraction; the textbook counts for QR and one Jacobi sweep), the operand */
+/* bytes (A + B + C, an operand shared across a batch counted once) and the  */
+/* summed kernel durations.  It is meant for benchmarking: each launch pays  */
+/* two extra atomics per workgroup.                                           */
 /* ------------------------------------------------------------------------- */
 enum { TTSG_ST_CONTRACT_F64 = 0, TTSG_ST_CONTRACT_F32 = 1, TTSG_ST_CONTRACT_BF16 = 2,
        TTSG_ST_QR = 3, TTSG_ST_SVD = 4, TTSG_ST_CLASSES = 8 };
@@ -232,7 +255,7 @@ typedef struct {
 
 /* on != 0: clear the counters and start recording; on == 0: stop recording. */
 int ttsg_stats_enable(int32_t on);
-/* Resolve the recorded events (synchronizing them) into *out and clear. */
+/* Synchronize the device, resolve the recorded slots into *out and clear. */
 int ttsg_stats_read(ttsg_stats* out);
 
 #ifdef __cplusplus

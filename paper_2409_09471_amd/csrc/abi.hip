@@ -354,6 +354,48 @@ int ttsg_true_residual(int32_t d, const int32_t* n, const int32_t* R, const doub
     });
 }
 
+int ttsg_grad_kron_sum(int32_t d, const int32_t* n, const double* const* L, const int32_t* rl,
+                       const double* const* lam, const int32_t* rx, const double* const* x, double* out, void* ws,
+                       size_t ws_bytes, ttsg_stream_t stream) {
+    return guarded([&]() {
+        check_shape(d, n, rl, "grad lambda");
+        check_shape(d, n, rx, "grad x");
+        check_ptrs(d, (const void* const*)L, "grad L");
+        check_ptrs(d, (const void* const*)lam, "grad lambda");
+        check_ptrs(d, (const void* const*)x, "grad x");
+        TTSG_CHECK(out != nullptr, TTSG_ERR_ARG, "grad: null output");
+        size_t tot = 0, big = 0;
+        for (int k = 0; k <= d; ++k) tot += 2 * (size_t)rl[k] * rx[k] + 64;
+        for (int k = 0; k < d; ++k)
+            big = std::max(big, (size_t)std::max(rl[k], rx[k]) * n[k] * std::max(rl[k + 1], rx[k + 1]));
+        ttsg::Workspace W(ws, ws_bytes, (tot + 4 * big + (size_t)d + 64) * 8 + kSplitSlack, S(stream));
+        double* dev = W.arena.get<double>(d);
+        std::vector<const double*> Lv(L, L + d), lv(lam, lam + d), xv(x, x + d);
+        ttsg::grad_kron_sum(d, n, Lv, vec(rl, d + 1), lv, vec(rx, d + 1), xv, dev, W.arena, S(stream));
+        TTSG_HIP(hipMemcpyAsync(out, dev, d * sizeof(double), hipMemcpyDeviceToHost, S(stream)));
+        TTSG_HIP(hipStreamSynchronize(S(stream)));
+        return 0;
+    });
+}
+
+int ttsg_tt_axpby(int32_t d, const int32_t* n, double alpha, const int32_t* rx, const double* const* x, double beta,
+                  const int32_t* ry, const double* const* y, double* const* z, ttsg_stream_t stream) {
+    return guarded([&]() {
+        check_shape(d, n, rx, "axpby x");
+        check_shape(d, n, ry, "axpby y");
+        check_ptrs(d, (const void* const*)x, "axpby x");
+        check_ptrs(d, (const void* const*)y, "axpby y");
+        check_ptrs(d, (const void* const*)z, "axpby z");
+        std::vector<double*> xv(d);
+        for (int k = 0; k < d; ++k) xv[k] = const_cast<double*>(x[k]);
+        std::vector<const double*> yv(y, y + d);
+        std::vector<double*> zv(z, z + d);
+        std::vector<int> rz;
+        ttsg::tt_add_block(d, n, vec(rx, d + 1), xv, vec(ry, d + 1), yv, beta, zv, rz, S(stream), alpha);
+        return 0;
+    });
+}
+
 int ttsg_sgmres_solve(int32_t d, const int32_t* n, const int32_t* R, const double* const* A, const int32_t* rb,
                       const double* const* b, int32_t s, const double* const* Sf, const int32_t* rho,
                       const double* const* Y, const int32_t* rx, const double* const* X,

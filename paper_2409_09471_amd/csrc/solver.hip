@@ -137,7 +137,7 @@ int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n 
 //   first core [A B], last core [A; B], middle cores diag(A, B).
 __global__ void k_block_core(int rl1, int rr1, int rl2, int rr2, int n, int first, int last,
                              const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ out,
-                             double bscale) {
+                             double bscale, double ascale) {
     const int rl = first ? 1 : rl1 + rl2;
     const int rr = last ? 1 : rr1 + rr2;
     const int64_t total = (int64_t)rl * n * rr;
@@ -151,9 +151,9 @@ __global__ void k_block_core(int rl1, int rr1, int rl2, int rr2, int n, int firs
         int aa = a, bb = b;
         bool inA = (first || aa < rl1) && (last || bb < rr1);
         if (first && last) {
-            v = A[i] + bscale * B[i];
+            v = ascale * A[i] + bscale * B[i];
         } else if (inA) {
-            v = A[((int64_t)aa * n + i) * rr1 + bb];
+            v = (first ? ascale : 1.0) * A[((int64_t)aa * n + i) * rr1 + bb];
         } else {
             int a2 = first ? 0 : aa - rl1;
             int b2 = last ? 0 : bb - rr1;
@@ -169,14 +169,14 @@ __global__ void k_block_core(int rl1, int rr1, int rl2, int rr2, int n, int firs
 // Sum a + bscale * b of two TTs into block cores `out` (ranks ra + rb).
 void tt_add_block(int d, const int* n, const std::vector<int>& ra, const std::vector<double*>& a,
                   const std::vector<int>& rb, const std::vector<const double*>& b, double bscale,
-                  const std::vector<double*>& out, std::vector<int>& rout, hipStream_t st) {
+                  const std::vector<double*>& out, std::vector<int>& rout, hipStream_t st, double ascale) {
     rout.assign(d + 1, 1);
     for (int k = 1; k < d; ++k) rout[k] = ra[k] + rb[k];
     for (int mu = 0; mu < d; ++mu) {
         const int first = (mu == 0), last = (mu == d - 1);
         int64_t total = (int64_t)rout[mu] * n[mu] * rout[mu + 1];
         hipLaunchKernelGGL(k_block_core, dim3(grid_for(total)), dim3(256), 0, st, ra[mu], ra[mu + 1], rb[mu],
-                           rb[mu + 1], n[mu], first, last, a[mu], b[mu], out[mu], bscale);
+                           rb[mu + 1], n[mu], first, last, a[mu], b[mu], out[mu], bscale, ascale);
     }
     TTSG_HIP(hipGetLastError());
 }

@@ -169,6 +169,12 @@ int sgmres_solve(const SolverInputs& in, double* const* x, int32_t* x_r, ttsg_sg
 // a + bscale * b as block cores (ranks add); first/last cores concatenated.
 void tt_add_block(int d, const int* n, const std::vector<int>& ra, const std::vector<double*>& a,
                   const std::vector<int>& rb, const std::vector<const double*>& b, double bscale,
-                  const std::vector<double*>& out, std::vector<int>& rout, hipStream_t st);
+                  const std::vector<double*>& out, std::vector<int>& rout, hipStream_t st,
+                  double ascale = 1.0);
+
+// -<lambda, L_k x> for every mode k (grad.hip); result in out_dev[0..d-1].
+void grad_kron_sum(int d, const int* n, const std::vector<const double*>& L, const std::vector<int>& rl,
+                   const std::vector<const double*>& lam, const std::vector<int>& rx,
+                   const std::vector<const double*>& x, double* out_dev, Arena& ar, hipStream_t st);
 
 }  // namespace ttsg

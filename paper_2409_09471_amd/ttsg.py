@@ -48,7 +48,7 @@ def lib():
 EXPORTED = [
     "ttsg_last_error", "ttsg_version", "ttsg_matvec", "ttsg_kr_sketch", "ttsg_stta_sketch",
     "ttsg_round_rand", "ttsg_round_svd", "ttsg_sgmres_solve", "ttsg_true_residual", "ttsg_dot",
-    "ttsg_stats_enable", "ttsg_stats_read",
+    "ttsg_grad_kron_sum", "ttsg_tt_axpby", "ttsg_stats_enable", "ttsg_stats_read",
 ]
 
 STAT_CLASSES = {0: "contract_f64", 1: "contract_f32", 2: "contract_bf16", 3: "qr", 4: "svd_jacobi"}
@@ -248,6 +248,32 @@ def dot(x, y) -> float:
     _check(lib().ttsg_dot(len(x), _i32(sizes_of(x)), _i32(ranks_of(x)), _ptrs(x), _i32(ranks_of(y)), _ptrs(y),
                           ctypes.byref(out), None, ctypes.c_size_t(0), _stream()), "ttsg_dot")
     return out.value
+
+
+def grad_kron_sum(Ls, lam, x):
+    """[-<lam, L_k x>]_k for mode operators L_k (n_k x n_k CUDA float64 tensors)."""
+    import numpy as np
+    d = len(x)
+    for k, L in enumerate(Ls):
+        if tuple(L.shape) != (x[k].shape[1], x[k].shape[1]):
+            raise TTSGError(f"grad_kron_sum: L[{k}] has shape {tuple(L.shape)}")
+    out = (ctypes.c_double * d)()
+    _check(lib().ttsg_grad_kron_sum(d, _i32(sizes_of(x)), _ptrs(Ls), _i32(ranks_of(lam)), _ptrs(lam),
+                                    _i32(ranks_of(x)), _ptrs(x), out, None, ctypes.c_size_t(0), _stream()),
+           "ttsg_grad_kron_sum")
+    return np.array([out[k] for k in range(d)])
+
+
+def tt_axpby(alpha: float, x, beta: float, y) -> List[torch.Tensor]:
+    """alpha x + beta y as a block TT (ranks add on the inner bonds)."""
+    d = len(x)
+    n = sizes_of(x)
+    rx, ry = ranks_of(x), ranks_of(y)
+    rz = [1] + [rx[k] + ry[k] for k in range(1, d)] + [1] if d > 1 else [1, 1]
+    z = [torch.empty((rz[k], n[k], rz[k + 1]), dtype=torch.float64, device=x[0].device) for k in range(d)]
+    _check(lib().ttsg_tt_axpby(d, _i32(n), ctypes.c_double(alpha), _i32(rx), _ptrs(x), ctypes.c_double(beta),
+                               _i32(ry), _ptrs(y), _ptrs(z), _stream()), "ttsg_tt_axpby")
+    return z
 
 
 def true_residual(A, b, x) -> float:
