@@ -196,6 +196,39 @@ int ttsg_sgmres_solve(int32_t d, const int32_t* n,
                       ttsg_sgmres_info* info,
                       void* ws, size_t ws_bytes, ttsg_stream_t stream);
 
+/* Many independent systems (Alg. 4 on each), solved concurrently on one GPU.
+ * Each entry carries exactly the arguments of ttsg_sgmres_solve (same meaning,
+ * layout and ownership); `status` receives that system's return value.
+ * Systems are taken longest-first by `concurrency` host workers (<= 0: 8),
+ * each driving its own non-blocking stream of default priority, so the
+ * kernels of different systems overlap on the GPU while each system's host
+ * rank decisions proceed independently.  All worker streams first wait for
+ * the work queued on `stream`.  Returns 0 when every system returned >= 0,
+ * else the first negative code (ttsg_last_error names the system).  Returns
+ * after every system has finished. */
+typedef struct {
+    int32_t d;
+    const int32_t* n;
+    const int32_t* R;
+    const double* const* A;
+    const int32_t* rb;
+    const double* const* b;
+    int32_t s;
+    const double* const* S;
+    const int32_t* rho;
+    const double* const* Y;
+    const int32_t* rx;
+    const double* const* X;
+    const ttsg_sgmres_opts* opts;
+    double* const* x;
+    int32_t* x_r;
+    ttsg_sgmres_info* info;
+    int32_t status;
+} ttsg_system;
+
+int ttsg_sgmres_solve_batched(int32_t count, ttsg_system* systems, int32_t concurrency,
+                              ttsg_stream_t stream);
+
 /* FP64 true residual ||b - A x|| / ||b|| through TT arithmetic on the GPU
  * (b - A x formed as a TT, its norm taken after QR orthogonalization).
  * Synchronizes `stream`; result in *res. */
@@ -243,8 +276,10 @@ int ttsg_tt_axpby(int32_t d, const int32_t* n, double alpha, const int32_t* rx, 
 /* summed kernel durations.  It is meant for benchmarking: each launch pays  */
 /* two extra atomics per workgroup.                                           */
 /* ------------------------------------------------------------------------- */
+/* TTSG_ST_QR_REDO counts (in `launches` only) Cholesky-QR factorizations of */
+/* the TT-SVD that were rejected as inaccurate and redone by Householder QR. */
 enum { TTSG_ST_CONTRACT_F64 = 0, TTSG_ST_CONTRACT_F32 = 1, TTSG_ST_CONTRACT_BF16 = 2,
-       TTSG_ST_QR = 3, TTSG_ST_SVD = 4, TTSG_ST_CLASSES = 8 };
+       TTSG_ST_QR = 3, TTSG_ST_SVD = 4, TTSG_ST_QR_REDO = 5, TTSG_ST_CLASSES = 8 };
 
 typedef struct {
     int64_t launches[TTSG_ST_CLASSES];
@@ -255,7 +290,10 @@ typedef struct {
 
 /* on != 0: clear the counters and start recording; on == 0: stop recording. */
 int ttsg_stats_enable(int32_t on);
-/* Synchronize the device, resolve the recorded slots into *out and clear. */
+/* Synchronize the device, resolve the recorded slots into *out and clear.
+ * When the environment variable TTSG_SHAPE_LOG names a file, one line per
+ * measured launch is appended to it: class, M, N, K, batch, split count (0s
+ * for non-contractions), seconds, flops. */
 int ttsg_stats_read(ttsg_stats* out);
 
 #ifdef __cplusplus

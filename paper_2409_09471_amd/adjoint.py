@@ -36,11 +36,12 @@ class KronSumProblem:
     rx: List[int]
     rho: List[int]
     maxit: int = 500
-    tol: float = 1e-8
-    q: int = 2
-    round_tol: float = 1e-10
+    tol: float = 1e-6
+    q: int = 1
+    round_tol: float = 1e-8
+    final_tol: float = 1e-10
     maxrank: int = 64
-    stop_safety: float = 0.1
+    stop_safety: float = 0.3
     restart: int = 0
     precision: int = ttsg.PREC_F64
     adjoint_rhs_tol: float = 1e-13
@@ -55,7 +56,7 @@ def _operator(Ls: Sequence[np.ndarray], theta: np.ndarray, transpose: bool, devi
 def _solve(P: KronSumProblem, A, rhs) -> ttsg.SolveResult:
     r = ttsg.sgmres_solve(A, rhs, P.S, P.X, P.Y, P.rx, P.rho, maxit=P.maxit, tol=P.tol, q=P.q,
                           round_tol=P.round_tol, maxrank=P.maxrank, stop_safety=P.stop_safety,
-                          restart=P.restart, precision=P.precision)
+                          restart=P.restart, final_tol=P.final_tol, precision=P.precision)
     if r.status != ttsg.OK:
         raise ttsg.TTSGError(f"parametric solve did not converge (status {r.status}, true residual "
                              f"{r.true_residual:.3e} after {r.iterations} iterations)")

@@ -1,8 +1,12 @@
 // extern "C" entry points of libttsg: argument validation, workspace
 // handling and conversion of internal errors into return codes.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <numeric>
+#include <thread>
 
 #include "tt_ops.h"
 
@@ -55,6 +59,13 @@ template <typename T> std::vector<const void*> vp(const T* const* p, int cnt) {
 
 hipStream_t S(ttsg_stream_t s) { return static_cast<hipStream_t>(s); }
 
+ttsg::Prec prec_of(int32_t precision) {
+    TTSG_CHECK(precision == TTSG_PREC_F64 || precision == TTSG_PREC_MIXED || precision == TTSG_PREC_BF16,
+               TTSG_ERR_ARG, "unknown precision");
+    return precision == TTSG_PREC_F64 ? ttsg::Prec::F64
+                                      : (precision == TTSG_PREC_MIXED ? ttsg::Prec::F32 : ttsg::Prec::BF16);
+}
+
 // Split-K partial sums of one contraction take at most 4M output elements.
 constexpr size_t kSplitSlack = (size_t)40 << 20;
 
@@ -97,7 +108,7 @@ int ttsg_kr_sketch(int32_t d, const int32_t* n, int32_t s, const double* const* 
             check_shape(d, n, R, "kr_sketch A");
             check_ptrs(d, (const void* const*)A, "kr_sketch A");
         }
-        const ttsg::Prec p = precision == TTSG_PREC_F64 ? ttsg::Prec::F64 : ttsg::Prec::F32;
+        const ttsg::Prec p = prec_of(precision);
         std::vector<int> RR(d + 1, 1);
         if (op) RR = vec(R, d + 1);
         size_t need = 0;
@@ -120,7 +131,7 @@ int ttsg_kr_sketch(int32_t d, const int32_t* n, int32_t s, const double* const* 
             } else {
                 SA[mu] = Sf[mu];
             }
-            if (p == ttsg::Prec::F32) {
+            if (p != ttsg::Prec::F64) {
                 float* f = ar.get<float>(sz);
                 ttsg::convert_f64_f32(sz, (const double*)SA[mu], f, S(stream));
                 SA[mu] = f;
@@ -142,7 +153,7 @@ static void stta_common(int32_t d, const int32_t* n, const int32_t* rho, const d
                         const double* const* X, const int32_t* R, const double* const* A, const int32_t* r,
                         const double* const* x, double* const* Psi, double* const* Omega, int32_t precision,
                         ttsg::Arena& ar, hipStream_t st) {
-    const ttsg::Prec p = precision == TTSG_PREC_F64 ? ttsg::Prec::F64 : ttsg::Prec::F32;
+    const ttsg::Prec p = prec_of(precision);
     ttsg::SketchOperands o;
     o.p = p;
     o.n = n;
@@ -235,7 +246,7 @@ int ttsg_round_rand(int32_t d, const int32_t* n, const int32_t* r, const double*
             rmax = std::max(rmax, (size_t)std::max(rho[mu], rx[mu]));
         }
         const size_t need = stta_ws(d, n, rho, rx, nullptr, r) + sk * 8 + (8 * core + 12 * rmax * rmax) * 8 +
-                            (size_t)d * 16 * rmax * rmax * 8 + (4 << 20);
+                            (size_t)d * 16 * rmax * rmax * 8 + (4 << 20) + ttsg::tt_svd_extra_bytes(d, n, rx);
         ttsg::Workspace W(ws, ws_bytes, (need) + kSplitSlack, S(stream));
         ttsg::Arena& ar = W.arena;
         std::vector<double*> psi(d), om(d - 1);
@@ -268,7 +279,10 @@ int ttsg_round_svd(int32_t d, const int32_t* n, const int32_t* r, const double* 
             core = std::max(core, (size_t)r[mu] * n[mu] * r[mu + 1]);
             rmax = std::max(rmax, (size_t)r[mu]);
         }
-        ttsg::Workspace W(ws, ws_bytes, ((6 * core + 4 * rmax * rmax + 8 * rmax) * 8 + (1 << 20)) + kSplitSlack, S(stream));
+        ttsg::Workspace W(ws, ws_bytes,
+                          ((6 * core + 4 * rmax * rmax + 8 * rmax) * 8 + (1 << 20)) + ttsg::tt_svd_extra_bytes(d, n, r) +
+                              kSplitSlack,
+                          S(stream));
         std::vector<double*> o(out, out + d);
         for (int mu = 0; mu < d; ++mu) ttsg::copy_f64((int64_t)r[mu] * n[mu] * r[mu + 1], x[mu], o[mu], S(stream));
         std::vector<int> rr = vec(r, d + 1);
@@ -411,12 +425,9 @@ int ttsg_sgmres_solve(int32_t d, const int32_t* n, const int32_t* R, const doubl
         TTSG_CHECK(opts->maxit >= 1, TTSG_ERR_ARG, "sgmres: maxit < 1");
         TTSG_CHECK(opts->tol > 0.0 && opts->round_tol >= 0.0, TTSG_ERR_ARG, "sgmres: bad tolerance");
         TTSG_CHECK(opts->q >= 1 && opts->q <= 7, TTSG_ERR_ARG, "sgmres: q must be in 1..7");
-        TTSG_CHECK(opts->precision == TTSG_PREC_F64 || opts->precision == TTSG_PREC_MIXED, TTSG_ERR_ARG,
-                   "sgmres: precision must be F64 or MIXED");
+        (void)prec_of(opts->precision);
         TTSG_CHECK(s >= 1, TTSG_ERR_ARG, "sgmres: s < 1");
         for (int b2 = 1; b2 < d; ++b2) TTSG_CHECK(rho[b2] >= rx[b2], TTSG_ERR_ARG, "sgmres: rho_b < rx_b");
-        for (int b2 = 0; b2 <= d; ++b2)
-            TTSG_CHECK(rb[b2] <= std::max(rx[b2], 1) || true, TTSG_ERR_CAPACITY, "");
         check_ptrs(d, (const void* const*)A, "sgmres A");
         check_ptrs(d, (const void* const*)b, "sgmres b");
         check_ptrs(d, (const void* const*)Sf, "sgmres S");
@@ -443,6 +454,73 @@ int ttsg_sgmres_solve(int32_t d, const int32_t* n, const int32_t* R, const doubl
         if (in.o.rcond <= 0.0) in.o.rcond = 1e-12;
         if (in.o.stop_safety <= 0.0) in.o.stop_safety = 1.0;
         return ttsg::sgmres_solve(in, x, x_r, info, ws, ws_bytes, S(stream));
+    });
+}
+
+int ttsg_sgmres_solve_batched(int32_t count, ttsg_system* sys, int32_t concurrency, ttsg_stream_t stream) {
+    return guarded([&]() {
+        TTSG_CHECK(count >= 0, TTSG_ERR_ARG, "batched: count < 0");
+        TTSG_CHECK(count == 0 || sys != nullptr, TTSG_ERR_ARG, "batched: null system array");
+        if (count == 0) return 0;
+        int dev = 0;
+        TTSG_HIP(hipGetDevice(&dev));
+        // Longest-first order: a system's cost grows with sum_k n_k * (R rx)^2 * rho.
+        std::vector<double> cost(count, 0.0);
+        for (int i = 0; i < count; ++i) {
+            const ttsg_system& q = sys[i];
+            check_shape(q.d, q.n, q.rx, "batched rx");
+            check_shape(q.d, q.n, q.R, "batched A");
+            check_shape(q.d, q.n, q.rho, "batched rho");
+            for (int k = 0; k < q.d; ++k)
+                cost[i] += (double)q.n[k] * q.R[k] * q.rx[k] * q.R[k + 1] * q.rx[k + 1] * (q.rho[k] + q.rho[k + 1]);
+            sys[i].status = 0;
+        }
+        std::vector<int> order(count);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        const int workers = std::max(1, std::min<int>(concurrency > 0 ? concurrency : 8, count));
+        // Every worker stream first waits for the work already queued on `stream`.
+        hipEvent_t ready;
+        TTSG_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        TTSG_HIP(hipEventRecord(ready, S(stream)));
+        std::atomic<int> next{0};
+        std::mutex mu;
+        std::string first_err;
+        int first_rc = 0;
+        auto work = [&]() {
+            hipStream_t st = nullptr;
+            if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+                hipStreamWaitEvent(st, ready, 0) != hipSuccess) {
+                std::lock_guard<std::mutex> lk(mu);
+                if (first_rc == 0) {
+                    first_rc = -TTSG_ERR_HIP;
+                    first_err = "batched: could not set up a worker stream";
+                }
+                if (st) (void)hipStreamDestroy(st);
+                return;
+            }
+            for (int j = next++; j < count; j = next++) {
+                ttsg_system& q = sys[order[j]];
+                const int rc = ttsg_sgmres_solve(q.d, q.n, q.R, q.A, q.rb, q.b, q.s, q.S, q.rho, q.Y, q.rx, q.X, q.opts,
+                                                 q.x, q.x_r, q.info, nullptr, 0, st);
+                q.status = rc;
+                if (rc < 0) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    if (first_rc == 0) {
+                        first_rc = rc;
+                        first_err = "batched: system " + std::to_string(order[j]) + ": " + ttsg_last_error();
+                    }
+                }
+            }
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        };
+        std::vector<std::thread> pool;
+        for (int w = 0; w < workers; ++w) pool.emplace_back(work);
+        for (auto& t : pool) t.join();
+        TTSG_HIP(hipEventDestroy(ready));
+        if (first_rc < 0) throw Error(-first_rc, first_err);
+        return 0;
     });
 }
 

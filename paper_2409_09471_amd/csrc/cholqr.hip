@@ -1,0 +1,162 @@
+// Cholesky QR in two passes (CholQR2) for the tall-skinny unfoldings of the
+// TT-SVD: X = Q R through G = X^T X = R^T R and Q = X R^-1, repeated once on
+// Q to restore orthogonality to working precision.  The Gram products and the
+// multiplications by R^-1 are matrix-core contractions over the whole chip;
+// only the c x c Cholesky factorization and the triangular inverse are
+// sequential, inside one workgroup's LDS.
+//
+// CholQR2 is accurate while the column-equilibrated X is well conditioned.
+// Each factorization raises a device flag when a pivot of the first pass falls
+// below 1e-10 of its column's squared norm, when a pivot is not finite, or when
+// the second-pass factor differs from the identity by more than 0.1 (the first
+// Q was not nearly orthonormal); callers read the flag at their next
+// synchronization and redo the factorization with Householder QR.
+#include <cmath>
+
+#include "tt_ops.h"
+
+namespace ttsg {
+namespace {
+
+constexpr int CQ_T = 256;
+constexpr int CQ_MAX = 64;
+
+// Cholesky of the c x c symmetric G (column-major) into upper R (G = R^T R),
+// then R^-1; both written column-major with leading dimension c.
+__global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restrict__ G, double* __restrict__ R,
+                                                    double* __restrict__ Ri, int* __restrict__ flag,
+                                                    int second_pass, DevSlot* slot) {
+    __shared__ double A[CQ_MAX][CQ_MAX + 1];
+    __shared__ double d0[CQ_MAX], rd[CQ_MAX];
+    __shared__ int s_bad;
+    slot_begin(slot);
+    const int tid = threadIdx.x;
+    for (int e = tid; e < c * c; e += CQ_T) {
+        const int l = e / c, i = e - l * c;
+        A[i][l] = G[i + (int64_t)l * c];
+    }
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    for (int j = tid; j < c; j += CQ_T) d0[j] = A[j][j];
+    __syncthreads();
+    // Right-looking Cholesky on the upper triangle.  Step j reads row j and
+    // writes the scaled row as R^T into the (unused) lower triangle and the
+    // rank-1 update into rows > j, so one barrier per step suffices.
+    for (int j = 0; j < c; ++j) {
+        double p = A[j][j];
+        const double dj = d0[j];
+        const bool ok = p > 1e-10 * dj && p <= 4.0 * dj && dj < INFINITY;
+        if (!ok) p = (dj > 0.0 && dj < INFINITY) ? dj : 1.0;   // keep going; the flag discards the result
+        const double rjj = sqrt(p);
+        const double inv_p = 1.0 / p;
+        if (tid == 0) {
+            rd[j] = rjj;
+            if (!ok) s_bad = 1;
+        }
+        const int w = c - j - 1;
+        for (int l = j + 1 + tid; l < c; l += CQ_T) A[l][j] = A[j][l] / rjj;
+        for (int e = tid; e < w * w; e += CQ_T) {
+            const int i = j + 1 + e / w, l = j + 1 + e % w;
+            if (i <= l) A[i][l] -= A[j][i] * A[j][l] * inv_p;
+        }
+        __syncthreads();
+    }
+    // R (upper): R[j][l] = A[l][j] for l > j, rd[j] on the diagonal
+    for (int e = tid; e < c * c; e += CQ_T) {
+        const int l = e / c, j = e - l * c;
+        const double v = l > j ? A[l][j] : (l == j ? rd[j] : 0.0);
+        R[j + (int64_t)l * c] = v;
+        if (second_pass && fabs(v - (l == j ? 1.0 : 0.0)) > 0.1) s_bad = 1;
+    }
+    __syncthreads();
+    // R^-1 (upper) into the upper triangle, bottom row first:
+    // Ri[i][l] = -(sum_{t=i+1..l} R[i][t] Ri[t][l]) / R[i][i].  Four lanes share
+    // a column and split the sum.
+    const int col = tid >> 2, part = tid & 3;
+    for (int i = c - 1; i >= 0; --i) {
+        double s = 0.0;
+        if (col < c && col > i)
+            for (int t = i + 1 + part; t <= col; t += 4) s += A[t][i] * A[t][col];
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (col < c && part == 0 && col >= i) A[i][col] = col == i ? 1.0 / rd[i] : -s / rd[i];
+        __syncthreads();
+    }
+    for (int e = tid; e < c * c; e += CQ_T) {
+        const int l = e / c, i = e - l * c;
+        Ri[i + (int64_t)l * c] = l >= i ? A[i][l] : 0.0;
+    }
+    if (tid == 0 && s_bad) flag[0] = 1;
+    slot_end(slot);
+}
+
+__global__ void k_zero_flags(int n, int* __restrict__ f) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) f[i] = 0;
+}
+
+}  // namespace
+
+void zero_flags(int n, int* f, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero_flags, dim3((n + 255) / 256), dim3(256), 0, st, n, f);
+    TTSG_HIP(hipGetLastError());
+}
+
+bool cholqr_fits(int m, int c) { return c >= 1 && c <= CQ_MAX && m >= c; }
+
+void cholqr2(int m, int c, const double* X, int64_t xr, int64_t xc, double* Q, int64_t qr, int64_t qc, double* R,
+             int* flag, Arena& ar, hipStream_t st) {
+    TTSG_CHECK(cholqr_fits(m, c), TTSG_ERR_ARG, "cholqr2: needs m >= c and c <= 64");
+    const size_t mark = ar.mark();
+    double* G = ar.get<double>((int64_t)c * c);
+    double* R1 = ar.get<double>((int64_t)c * c);
+    double* R1i = ar.get<double>((int64_t)c * c);
+    double* R2 = ar.get<double>((int64_t)c * c);
+    double* R2i = ar.get<double>((int64_t)c * c);
+    double* Q1 = ar.get<double>((int64_t)m * c);
+    auto gram = [&](const double* Y, int64_t yr, int64_t yc) {
+        ContractDesc d = cdesc(c, c, m);
+        d.am = idx1(yc);
+        d.ak = idx1(yr);
+        d.bk = idx1(yr);
+        d.bn = idx1(yc);
+        d.cm = idx1(1);
+        d.cn = idx1(c);
+        contract(Prec::F64, d, Y, Y, G, st, &ar);
+    };
+    auto times_inv = [&](const double* Y, int64_t yr, int64_t yc, const double* Ri, double* Z, int64_t zr,
+                         int64_t zc) {
+        ContractDesc d = cdesc(m, c, c);
+        d.am = idx1(yr);
+        d.ak = idx1(yc);
+        d.bk = idx1(1);
+        d.bn = idx1(c);
+        d.cm = idx1(zr);
+        d.cn = idx1(zc);
+        contract(Prec::F64, d, Y, Ri, Z, st, &ar);
+    };
+    auto chol = [&](double* Rf, double* Rfi, int second) {
+        StatScope sc(TTSG_ST_QR, (double)c * c * c / 3.0 + (double)c * c * c / 3.0, 0.0, st);
+        hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(CQ_T), 0, st, c, G, Rf, Rfi, flag, second, sc.slot());
+        TTSG_HIP(hipGetLastError());
+    };
+    gram(X, xr, xc);
+    chol(R1, R1i, 0);
+    times_inv(X, xr, xc, R1i, Q1, c, 1);
+    gram(Q1, c, 1);
+    chol(R2, R2i, 1);
+    times_inv(Q1, c, 1, R2i, Q, qr, qc);
+    // R = R2 R1 (upper triangular, column-major)
+    ContractDesc d = cdesc(c, c, c);
+    d.am = idx1(1);
+    d.ak = idx1(c);
+    d.bk = idx1(1);
+    d.bn = idx1(c);
+    d.cm = idx1(1);
+    d.cn = idx1(c);
+    contract(Prec::F64, d, R2, R1, R, st, &ar);
+    ar.release(mark);
+}
+
+}  // namespace ttsg

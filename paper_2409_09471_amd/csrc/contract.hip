@@ -7,12 +7,14 @@
 // (rank, mode) indices, operator ranks split from vector ranks -- are read in
 // place.  A 256-thread workgroup computes a 64 x 64 tile of C: the four
 // wavefronts each own a 32 x 32 block made of 2 x 2 MFMA 16x16 tiles; A and B
-// are staged through LDS in k-slabs (16 for FP64/FP32, 32 for BF16).
+// are staged through LDS in k-slabs (16 for FP64/FP32, 32 for BF16), the next
+// slab's global loads in flight while the matrix cores work on the current one.
 //
 // Matrix-core forms used (gfx950):
 //   FP64: v_mfma_f64_16x16x4_f64      (A, B, C in float64)
 //   FP32: v_mfma_f32_16x16x4_f32      (A, B, C in float32)
-//   BF16: v_mfma_f32_16x16x16_bf16    (A, B in bfloat16, C in float32)
+//   BF16: v_mfma_f32_16x16x16_bf16    (A, B stored as float32 and rounded to
+//         bfloat16, nearest-even, while they are staged into LDS; C in float32)
 // Operand layout of the 16x16xK forms: lane l supplies row (l % 16) of A and
 // column (l % 16) of B for the k-group (l / 16); the accumulator of lane l holds
 // column (l % 16), rows given by Traits<T>::acc_row.
@@ -31,52 +33,118 @@ typedef short s4_t __attribute__((ext_vector_type(4)));
 constexpr int BM = 64;
 constexpr int BN = 64;
 
+// float32 -> bfloat16 bits, round to nearest even (NaN stays a quiet NaN).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+struct Bf16 {};  // tag: float32 operands, bfloat16 matrix-core inputs
+
 template <typename T> struct Traits;
+// in_t: operand type in memory; lds_t: type staged in LDS; out_t: C.
 // Row of accumulator register r held by lane group g (= lane / 16):
 // the f64 form interleaves (row g + 4 r), the f32/bf16 forms keep four
 // consecutive rows per group (row 4 g + r).
 template <> struct Traits<double> {
     using acc4 = d4_t;
+    using in_t = double;
+    using lds_t = double;
     using out_t = double;
     static constexpr int BK = 16;
     static __device__ __forceinline__ int acc_row(int g, int r) { return g + 4 * r; }
+    static __device__ __forceinline__ lds_t stage(in_t v) { return v; }
 };
 template <> struct Traits<float> {
     using acc4 = f4_t;
+    using in_t = float;
+    using lds_t = float;
     using out_t = float;
     static constexpr int BK = 16;
     static __device__ __forceinline__ int acc_row(int g, int r) { return 4 * g + r; }
+    static __device__ __forceinline__ lds_t stage(in_t v) { return v; }
 };
-template <> struct Traits<uint16_t> {
+template <> struct Traits<Bf16> {
     using acc4 = f4_t;
+    using in_t = float;
+    using lds_t = uint16_t;
     using out_t = float;
     static constexpr int BK = 32;
     static __device__ __forceinline__ int acc_row(int g, int r) { return 4 * g + r; }
+    static __device__ __forceinline__ lds_t stage(in_t v) { return bf16_rne(v); }
 };
 
+// Global -> register -> LDS staging of one operand's k-slab.  The thread to
+// element map follows whichever index has unit stride (k or the row), so
+// consecutive lanes read consecutive addresses; each thread's row offsets are
+// computed once per tile, so a slab costs one (k-fast) or PER (row-fast) index
+// evaluations.  fetch() issues the global loads of the next slab before the
+// matrix-core work on the current one, commit() writes them to LDS after it.
 template <typename T>
-__device__ __forceinline__ void load_tile(T (*S)[BM + 1], const T* __restrict__ G, const Idx2& rowix,
-                                          const Idx2& kix, int row0, int k0, int nrows, int nk,
-                                          bool k_fast) {
-    constexpr int BK = Traits<T>::BK;
-    const int tid = threadIdx.x;
-    // Thread-to-element order follows whichever index has unit stride, so
-    // consecutive lanes touch consecutive addresses.
-    for (int e = tid; e < BM * BK; e += 256) {
-        int rr, kk;
-        if (k_fast) {
-            rr = e / BK;
-            kk = e - rr * BK;
+struct SlabLoader {
+    using in_t = typename Traits<T>::in_t;
+    using lds_t = typename Traits<T>::lds_t;
+    static constexpr int BK = Traits<T>::BK;
+    static constexpr int PER = BM * BK / 256;
+    const in_t* G;
+    Idx2 kix;
+    int kend;
+    bool k_fast;
+    int fixed;            // kk (k-fast) or the row within the tile (row-fast)
+    int64_t ro[PER];      // row offsets (k-fast: per element; row-fast: ro[0]); -1 = outside
+    in_t buf[PER];
+
+    __device__ __forceinline__ void init(const in_t* G_, const Idx2& rowix, const Idx2& kix_, int row0, int nrows,
+                                         int kend_, bool kf) {
+        G = G_;
+        kix = kix_;
+        kend = kend_;
+        k_fast = kf;
+        const int tid = threadIdx.x;
+        if (kf) {
+            fixed = tid % BK;
+#pragma unroll
+            for (int t = 0; t < PER; ++t) {
+                const int gr = row0 + tid / BK + (256 / BK) * t;
+                ro[t] = gr < nrows ? idx_off(rowix, gr) : -1;
+            }
         } else {
-            kk = e / BM;
-            rr = e - kk * BM;
+            fixed = tid % BM;
+            const int gr = row0 + fixed;
+            ro[0] = gr < nrows ? idx_off(rowix, gr) : -1;
+#pragma unroll
+            for (int t = 1; t < PER; ++t) ro[t] = ro[0];
         }
-        int gr = row0 + rr, gk = k0 + kk;
-        T v = T(0);
-        if (gr < nrows && gk < nk) v = G[idx_off(rowix, gr) + idx_off(kix, gk)];
-        S[kk][rr] = v;
     }
-}
+    __device__ __forceinline__ void fetch(int k0) {
+        const int tid = threadIdx.x;
+        if (k_fast) {
+            const int gk = k0 + fixed;
+            const bool kin = gk < kend;
+            const int64_t ko = kin ? idx_off(kix, gk) : 0;
+#pragma unroll
+            for (int t = 0; t < PER; ++t) buf[t] = (kin && ro[t] >= 0) ? G[ro[t] + ko] : in_t(0);
+        } else {
+#pragma unroll
+            for (int t = 0; t < PER; ++t) {
+                const int gk = k0 + tid / BM + (256 / BM) * t;
+                buf[t] = (gk < kend && ro[t] >= 0) ? G[ro[t] + idx_off(kix, gk)] : in_t(0);
+            }
+        }
+    }
+    __device__ __forceinline__ void commit(lds_t (*S)[BM + 1]) const {
+        const int tid = threadIdx.x;
+        if (k_fast) {
+#pragma unroll
+            for (int t = 0; t < PER; ++t) S[fixed][tid / BK + (256 / BK) * t] = Traits<T>::stage(buf[t]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < PER; ++t) S[tid / BM + (256 / BM) * t][fixed] = Traits<T>::stage(buf[t]);
+        }
+    }
+};
 
 __device__ __forceinline__ d4_t mfma(double a, double b, d4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -89,17 +157,19 @@ __device__ __forceinline__ f4_t mfma(float a, float b, f4_t c) {
 // writes its unscaled partial tile to part[split][batch][M][N]; a second
 // kernel sums the partials in a fixed order (deterministic) into C.
 template <typename T>
-__global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const T* __restrict__ A,
-                                                       const T* __restrict__ B,
+__global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typename Traits<T>::in_t* __restrict__ A,
+                                                       const typename Traits<T>::in_t* __restrict__ B,
                                                        typename Traits<T>::out_t* __restrict__ C,
                                                        int batch0, int splits, int kchunk,
                                                        typename Traits<T>::out_t* __restrict__ part,
                                                        DevSlot* slot) {
     using acc4 = typename Traits<T>::acc4;
+    using in_t = typename Traits<T>::in_t;
+    using lds_t = typename Traits<T>::lds_t;
     using out_t = typename Traits<T>::out_t;
     constexpr int BK = Traits<T>::BK;
-    __shared__ T As[BK][BM + 1];
-    __shared__ T Bs[BK][BN + 1];
+    __shared__ lds_t As[BK][BM + 1];
+    __shared__ lds_t Bs[BK][BN + 1];
 
     slot_begin(slot);
     const int zz = batch0 + blockIdx.z;
@@ -109,8 +179,8 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const T* 
     const int kend = min(d.K, kbeg + kchunk);
     const int m0 = blockIdx.y * BM;
     const int n0 = blockIdx.x * BN;
-    const T* Ab = A + idx_off(d.ab, bidx);
-    const T* Bb = B + idx_off(d.bb, bidx);
+    const in_t* Ab = A + idx_off(d.ab, bidx);
+    const in_t* Bb = B + idx_off(d.bb, bidx);
     out_t* Cb = C + idx_off(d.cb, bidx);
 
     const int lane = threadIdx.x & 63;
@@ -126,14 +196,23 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const T* 
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = acc4{0, 0, 0, 0};
 
-    const bool a_kfast = (d.ak.s0 == 1);
-    const bool b_kfast = (d.bk.s0 == 1);
+    SlabLoader<T> la, lb;
+    la.init(Ab, d.am, d.ak, m0, d.M, kend, d.ak.s0 == 1);
+    lb.init(Bb, d.bn, d.bk, n0, d.N, kend, d.bk.s0 == 1);
+    if (kbeg < kend) {
+        la.fetch(kbeg);
+        lb.fetch(kbeg);
+    }
 
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
-        load_tile<T>(As, Ab, d.am, d.ak, m0, k0, d.M, kend, a_kfast);
-        load_tile<T>(Bs, Bb, d.bn, d.bk, n0, k0, d.N, kend, b_kfast);
+        la.commit(As);
+        lb.commit(Bs);
         __syncthreads();
-        if constexpr (sizeof(T) == 2) {
+        if (k0 + BK < kend) {
+            la.fetch(k0 + BK);
+            lb.fetch(k0 + BK);
+        }
+        if constexpr (sizeof(lds_t) == 2) {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 16) {
                 s4_t a[2], b[2];
@@ -153,7 +232,7 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const T* 
         } else {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
-                T a[2], b[2];
+                lds_t a[2], b[2];
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
                     a[i] = As[kk + lg][wm + 16 * i + lr];
@@ -213,16 +292,19 @@ __global__ void reduce_splits(ContractDesc d, int splits, const O* __restrict__ 
 template <typename T>
 void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st, Arena* ar) {
     if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
+    using in_t = typename Traits<T>::in_t;
     if (bounds_checking()) {
         using out_t = typename Traits<T>::out_t;
         const int64_t ea = idx_max(d.ab, d.batch) + idx_max(d.am, d.M) + idx_max(d.ak, d.K) + 1;
         const int64_t eb = idx_max(d.bb, d.batch) + idx_max(d.bk, d.K) + idx_max(d.bn, d.N) + 1;
         const int64_t ec = idx_max(d.cb, d.batch) + idx_max(d.cm, d.M) + idx_max(d.cn, d.N) + 1;
-        check_range(A, ea * sizeof(T), "contract A");
-        check_range(B, eb * sizeof(T), "contract B");
+        check_range(A, ea * sizeof(in_t), "contract A");
+        check_range(B, eb * sizeof(in_t), "contract B");
         check_range(C, ec * sizeof(out_t), "contract C");
     }
-    const int cls = sizeof(T) == 8 ? TTSG_ST_CONTRACT_F64 : (sizeof(T) == 4 ? TTSG_ST_CONTRACT_F32 : TTSG_ST_CONTRACT_BF16);
+    const int cls = sizeof(typename Traits<T>::lds_t) == 8
+                        ? TTSG_ST_CONTRACT_F64
+                        : (sizeof(typename Traits<T>::lds_t) == 4 ? TTSG_ST_CONTRACT_F32 : TTSG_ST_CONTRACT_BF16);
     double flops = 0.0, bytes = 0.0;
     if (stats_on()) {
         using out_t = typename Traits<T>::out_t;
@@ -231,7 +313,7 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         const double ua = (double)d.M * d.K * (d.ab.s0 == 0 ? 1.0 : nb);
         const double ub = (double)d.K * d.N * (d.bb.s0 == 0 ? 1.0 : nb);
         const double uc = (double)d.M * d.N * nb * (d.beta != 0.0 ? 2.0 : 1.0);
-        bytes = (ua + ub) * sizeof(T) + uc * sizeof(out_t);
+        bytes = (ua + ub) * sizeof(in_t) + uc * sizeof(out_t);
     }
     StatScope scope(cls, flops, bytes, st);
     using out_t = typename Traits<T>::out_t;
@@ -251,12 +333,13 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
             splits = (d.K + kchunk - 1) / kchunk;
         }
     }
+    scope.shape(d.M, d.N, d.K, d.batch, splits);
     if (splits > 1) {
         const size_t mark = ar->mark();
         out_t* part = ar->get<out_t>((size_t)splits * d.batch * d.M * d.N);
         const int zt = d.batch * splits;
-        hipLaunchKernelGGL(contract_kernel<T>, dim3(gx, gy, zt), block, 0, st, d, static_cast<const T*>(A),
-                           static_cast<const T*>(B), static_cast<out_t*>(C), 0, splits, kchunk, part,
+        hipLaunchKernelGGL(contract_kernel<T>, dim3(gx, gy, zt), block, 0, st, d, static_cast<const in_t*>(A),
+                           static_cast<const in_t*>(B), static_cast<out_t*>(C), 0, splits, kchunk, part,
                            scope.slot());
         const int64_t total = (int64_t)d.batch * d.M * d.N;
         const int rb = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 8192));
@@ -266,8 +349,8 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         for (int b0 = 0; b0 < d.batch; b0 += 65535) {
             int nb = d.batch - b0 < 65535 ? d.batch - b0 : 65535;
             dim3 grid(gx, gy, nb);
-            hipLaunchKernelGGL(contract_kernel<T>, grid, block, 0, st, d, static_cast<const T*>(A),
-                               static_cast<const T*>(B), static_cast<out_t*>(C), b0, 1, d.K,
+            hipLaunchKernelGGL(contract_kernel<T>, grid, block, 0, st, d, static_cast<const in_t*>(A),
+                               static_cast<const in_t*>(B), static_cast<out_t*>(C), b0, 1, d.K,
                                static_cast<out_t*>(nullptr), scope.slot());
         }
     }
@@ -303,7 +386,7 @@ void contract(Prec p, const ContractDesc& d, const void* A, const void* B, void*
     switch (p) {
         case Prec::F64: launch<double>(d, A, B, C, st, ar); break;
         case Prec::F32: launch<float>(d, A, B, C, st, ar); break;
-        case Prec::BF16: launch<uint16_t>(d, A, B, C, st, ar); break;
+        case Prec::BF16: launch<Bf16>(d, A, B, C, st, ar); break;
     }
 }
 

@@ -14,6 +14,8 @@
 // into LDS) to its slice.
 #include <algorithm>
 
+#include <mutex>
+
 #include "tt_ops.h"
 
 namespace ttsg {
@@ -318,7 +320,9 @@ __global__ __launch_bounds__(QT) void k_qr_apply_leaf(int m, int c, int k, const
 
 // Dynamic LDS above the default limit must be requested per kernel; the
 // request (dynamic bytes) plus the kernel's static LDS must fit in 160 KB.
+std::mutex g_lds_mu;
 void allow_lds(const void* fn, size_t bytes, size_t& granted) {
+    std::lock_guard<std::mutex> lk(g_lds_mu);
     if (bytes <= granted) return;
     TTSG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     granted = bytes;

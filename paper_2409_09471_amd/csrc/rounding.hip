@@ -145,6 +145,16 @@ void upload_perm(const std::vector<int>& perm, const std::vector<double>& fac, i
 
 }  // namespace
 
+size_t tt_svd_extra_bytes(int d, const int* n, const int* r) {
+    size_t sum = 0, mx = 0;
+    for (int mu = 0; mu < d; ++mu) {
+        const size_t e = (size_t)r[mu] * n[mu] * r[mu + 1];
+        sum += e;
+        mx = std::max(mx, e);
+    }
+    return (sum + 2 * mx + 6 * 64 * 64 + 256) * sizeof(double) + (size_t)(d + 1) * 64;
+}
+
 double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vector<double*>& w,
                       const std::vector<int64_t>& cap_elems, double tol, int maxrank, Arena& ar, hipStream_t st,
                       double* norm_before) {
@@ -167,32 +177,63 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
     int* perm_dev = ar.get<int>(maxr);
     double* fac_dev = ar.get<double>(maxr);
 
-    // 1) right-to-left QR orthogonalization
-    for (int mu = d - 1; mu >= 1; --mu) {
-        const int rl = r[mu], rr = r[mu + 1], m = n[mu] * rr, c = rl;
-        const int k = std::min(m, c);
-        if (tsqr_fits(m, c)) {
-            // the row-major core is the column-major m x c matrix C^T
-            const size_t mk = ar.mark();
-            TsqrPlan plan;
-            plan.factor(m, c, w[mu], m, ar, st);
-            double* I = ar.get<double>((int64_t)c * c);
-            eye(c, I, st);
-            copy_f64((int64_t)c * c, plan.R, Rm, st);          // R: c x c, ld c (k == c)
-            plan.apply(c, I, c, w[mu], m, false, ar, st);      // Q^T as the new row-major core
-            ar.release(mk);
-        } else {
-            copy_f64((int64_t)m * c, w[mu], A, st);            // column-major m x c == row-major core
-            qr_householder(1, m, c, A, m, 0, tau, 0, st);
-            qr_form_q(1, m, c, A, m, 0, tau, 0, w[mu], m, 0, st);  // Q^T as the new row-major core
-            extract_r(k, c, A, m, Rm, k, st);
+    // 1) right-to-left QR orthogonalization.  Bonds whose unfolding fits
+    // CholQR2 use it (matrix-core Gram products); if any of them reports an
+    // untrustworthy factorization, the cores are restored from a snapshot and
+    // the sweep is redone with Householder QR.
+    int* flags = ar.get<int>(d + 1);
+    zero_flags(d + 1, flags, st);
+    std::vector<int> r_in = r;
+    bool any_chol = false;
+    for (int mu = d - 1; mu >= 1; --mu) any_chol = any_chol || cholqr_fits(n[mu] * r[mu + 1], r[mu]);
+    std::vector<double*> snap(d, nullptr);
+    if (any_chol)
+        for (int mu = 0; mu < d; ++mu) {
+            snap[mu] = ar.get<double>((int64_t)r[mu] * n[mu] * r[mu + 1]);
+            copy_f64((int64_t)r[mu] * n[mu] * r[mu + 1], w[mu], snap[mu], st);
         }
-        const int rll = r[mu - 1], nl = n[mu - 1];
-        // T (rll*nl x k) = W_{mu-1} (rll*nl x rl) * R^T
-        // B[l][kk] = R[kk][l] = Rm[l*k + kk]: the column-major R read row-major
-        gemm_rm_rm(rll * nl, k, rl, w[mu - 1], rl, Rm, k, T, k, st, &ar);
-        copy_f64((int64_t)rll * nl * k, T, w[mu - 1], st);
-        r[mu] = k;
+    auto orthogonalize = [&](bool allow_chol) {
+        for (int mu = d - 1; mu >= 1; --mu) {
+            const int rl = r[mu], rr = r[mu + 1], m = n[mu] * rr, c = rl;
+            const int k = std::min(m, c);
+            if (allow_chol && cholqr_fits(m, c)) {
+                // the row-major core is the column-major m x c matrix C^T; Q^T
+                // overwrites it as the new row-major core
+                cholqr2(m, c, w[mu], 1, m, w[mu], 1, m, Rm, flags, ar, st);
+            } else if (tsqr_fits(m, c)) {
+                const size_t mk = ar.mark();
+                TsqrPlan plan;
+                plan.factor(m, c, w[mu], m, ar, st);
+                double* I = ar.get<double>((int64_t)c * c);
+                eye(c, I, st);
+                copy_f64((int64_t)c * c, plan.R, Rm, st);          // R: c x c, ld c (k == c)
+                plan.apply(c, I, c, w[mu], m, false, ar, st);      // Q^T as the new row-major core
+                ar.release(mk);
+            } else {
+                copy_f64((int64_t)m * c, w[mu], A, st);            // column-major m x c == row-major core
+                qr_householder(1, m, c, A, m, 0, tau, 0, st);
+                qr_form_q(1, m, c, A, m, 0, tau, 0, w[mu], m, 0, st);  // Q^T as the new row-major core
+                extract_r(k, c, A, m, Rm, k, st);
+            }
+            const int rll = r[mu - 1], nl = n[mu - 1];
+            // T (rll*nl x k) = W_{mu-1} (rll*nl x rl) * R^T
+            // B[l][kk] = R[kk][l] = Rm[l*k + kk]: the column-major R read row-major
+            gemm_rm_rm(rll * nl, k, rl, w[mu - 1], rl, Rm, k, T, k, st, &ar);
+            copy_f64((int64_t)rll * nl * k, T, w[mu - 1], st);
+            r[mu] = k;
+        }
+    };
+    orthogonalize(true);
+    if (any_chol) {
+        int hflag = 0;
+        TTSG_HIP(hipMemcpyAsync(&hflag, flags, sizeof(int), hipMemcpyDeviceToHost, st));
+        TTSG_HIP(hipStreamSynchronize(st));
+        if (hflag != 0) {
+            stats_event(TTSG_ST_QR_REDO);
+            r = r_in;
+            for (int mu = 0; mu < d; ++mu) copy_f64((int64_t)r[mu] * n[mu] * r[mu + 1], snap[mu], w[mu], st);
+            orthogonalize(false);
+        }
     }
     sumsq((int64_t)r[0] * n[0] * r[1], w[0], part, scal, st);
     const double nrm = std::sqrt(read_scalar(scal, st));
@@ -214,27 +255,50 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
         int k;
         std::vector<int> perm;
         if (m >= c) {
+            // QR of the unfolding: CholQR2 (Q row-major m x c in Q) when it fits,
+            // TSQR or single-workgroup Householder otherwise or when CholQR2
+            // flags the factorization
+            bool chol = cholqr_fits(m, c);
             const bool tsqr = tsqr_fits(m, c);
             TsqrPlan plan;
             const size_t mk = ar.mark();
-            transpose2d(m, c, w[mu], c, A, m, st);           // column-major m x c
-            if (tsqr) {
-                plan.factor(m, c, A, m, ar, st);
-                copy_f64((int64_t)c * c, plan.R, Rm, st);
-            } else {
-                qr_householder(1, m, c, A, m, 0, tau, 0, st);
-                qr_form_q(1, m, c, A, m, 0, tau, 0, Q, m, 0, st);
-                extract_r(c, c, A, m, Rm, c, st);
+            auto householder = [&]() {
+                transpose2d(m, c, w[mu], c, A, m, st);           // column-major m x c
+                if (tsqr) {
+                    plan.factor(m, c, A, m, ar, st);
+                    copy_f64((int64_t)c * c, plan.R, Rm, st);
+                } else {
+                    qr_householder(1, m, c, A, m, 0, tau, 0, st);
+                    qr_form_q(1, m, c, A, m, 0, tau, 0, Q, m, 0, st);
+                    extract_r(c, c, A, m, Rm, c, st);
+                }
+            };
+            auto small_svd = [&]() {
+                // SVD of R through one-sided Jacobi on R^T (rows of a QR factor of a
+                // graded unfolding converge in few sweeps): R^T V' = U' S gives
+                // R = V' S U'^T, i.e. U_R = V' and S V_R^T = (U' S)^T.  Relative
+                // orthogonality 1e-11 is far below every rounding tolerance used.
+                transpose2d(c, c, Rm, c, QV, c, st);              // QV = R^T (column-major)
+                svd_small(c, QV, V, sig, st, 1e-11);
+                hsig.assign(c, 0.0);
+                TTSG_HIP(hipMemcpyAsync(hsig.data(), sig, c * sizeof(double), hipMemcpyDeviceToHost, st));
+            };
+            if (chol) {
+                cholqr2(m, c, w[mu], c, 1, Q, c, 1, Rm, flags + 1 + mu, ar, st);
+                small_svd();
+                int hflag = 0;
+                TTSG_HIP(hipMemcpyAsync(&hflag, flags + 1 + mu, sizeof(int), hipMemcpyDeviceToHost, st));
+                TTSG_HIP(hipStreamSynchronize(st));
+                if (hflag != 0) {
+                    stats_event(TTSG_ST_QR_REDO);
+                    chol = false;
+                }
             }
-            // SVD of R through one-sided Jacobi on R^T (rows of a QR factor of a
-            // graded unfolding converge in few sweeps): R^T V' = U' S gives
-            // R = V' S U'^T, i.e. U_R = V' and S V_R^T = (U' S)^T.  Relative
-            // orthogonality 1e-11 is far below every rounding tolerance used.
-            transpose2d(c, c, Rm, c, QV, c, st);              // QV = R^T (column-major)
-            svd_small(c, QV, V, sig, st, 1e-11);
-            hsig.assign(c, 0.0);
-            TTSG_HIP(hipMemcpyAsync(hsig.data(), sig, c * sizeof(double), hipMemcpyDeviceToHost, st));
-            TTSG_HIP(hipStreamSynchronize(st));
+            if (!chol) {
+                householder();
+                small_svd();
+                TTSG_HIP(hipStreamSynchronize(st));
+            }
             perm = argsort_desc(hsig);
             std::vector<double> sd(c);
             for (int t = 0; t < c; ++t) sd[t] = hsig[perm[t]];
@@ -247,7 +311,16 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             // Uk (c x k, column-major) = V'[:, perm]
             gather_cols(c, k, V, c, T, c, perm_dev, fac_dev, st);
             // new core (row-major m x k) = Q (m x c) * Uk
-            if (tsqr) {
+            if (chol) {
+                ContractDesc dq = cdesc(m, k, c);
+                dq.am = idx1(c);
+                dq.ak = idx1(1);
+                dq.bk = idx1(1);
+                dq.bn = idx1(c);
+                dq.cm = idx1(k);
+                dq.cn = idx1(1);
+                contract(Prec::F64, dq, Q, T, w[mu], st, &ar);
+            } else if (tsqr) {
                 plan.apply(k, T, c, w[mu], k, true, ar, st);
             } else {
                 gemm_cm_cm(m, k, c, Q, m, T, c, w[mu], k, st, &ar);

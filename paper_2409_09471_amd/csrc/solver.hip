@@ -261,7 +261,7 @@ size_t SgmresSolver::scratch_bytes() const {
 void SgmresSolver::carve(Arena& ar) {
     const int d = in_.d;
     const ttsg_sgmres_opts& o = in_.o;
-    p_ = o.precision == TTSG_PREC_F64 ? Prec::F64 : Prec::F32;
+    p_ = o.precision == TTSG_PREC_F64 ? Prec::F64 : (o.precision == TTSG_PREC_MIXED ? Prec::F32 : Prec::BF16);
     maxit_ = o.maxit;
     m_ = o.restart > 0 ? std::min(o.restart, o.maxit) : o.maxit;
     q_ = std::max(1, o.q);
@@ -632,7 +632,10 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
                 std::vector<double*> psi, om;
                 sk_ptrs(skC_, psi, om);
                 std::vector<const double*> cpsi(psi.begin(), psi.end()), com(om.begin(), om.end());
-                const double rc = p_ == Prec::F64 ? o.rcond : std::max(o.rcond, 1e-6);
+                // sketches of A v_k carry the working precision's rounding: singular
+                // values of Omega below it are noise, not directions
+                const double rc = p_ == Prec::F64 ? o.rcond
+                                                  : std::max(o.rcond, p_ == Prec::F32 ? 1e-6 : 4e-3);
                 stta_recover(d, n, in_.rho, in_.rx, cpsi, com, rc, slots_[fs], slot_r_[fs], scratch_, st_);
             }
             add_phase(TTSG_PH_RECOVER, t1);

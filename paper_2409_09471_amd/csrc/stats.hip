@@ -5,6 +5,8 @@
 // duration of a launch is therefore the time its kernel actually ran, not the
 // gap between host-side events (which would include submission latency
 // whenever the stream had drained).
+#include <cstdio>
+#include <cstdlib>
 #include <mutex>
 
 #include "ttsg_internal.h"
@@ -16,6 +18,7 @@ struct Rec {
     int cls;
     double flops, bytes;
     int64_t slot;
+    int shp[5];
 };
 
 constexpr int64_t kSlots = 1 << 20;
@@ -29,6 +32,13 @@ int64_t g_next = 0;
 
 bool stats_on() { return g_on; }
 
+int64_t g_events[TTSG_ST_CLASSES] = {};
+void stats_event(int cls) {
+    if (!g_on || cls < 0 || cls >= TTSG_ST_CLASSES) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    ++g_events[cls];
+}
+
 StatScope::StatScope(int cls, double flops, double bytes, hipStream_t st) {
     (void)st;
     if (!g_on) return;
@@ -36,7 +46,20 @@ StatScope::StatScope(int cls, double flops, double bytes, hipStream_t st) {
     if (g_next >= kSlots) return;           // beyond the slot budget: not measured
     const int64_t id = g_next++;
     slot_ = g_slots + id;
-    g_recs.push_back(Rec{cls, flops, bytes, id});
+    rec_ = (int64_t)g_recs.size();
+    g_recs.push_back(Rec{cls, flops, bytes, id, {0, 0, 0, 0, 0}});
+}
+
+void StatScope::shape(int a, int b, int c, int d, int e) {
+    if (rec_ < 0) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (rec_ >= (int64_t)g_recs.size()) return;
+    int* p = g_recs[rec_].shp;
+    p[0] = a;
+    p[1] = b;
+    p[2] = c;
+    p[3] = d;
+    p[4] = e;
 }
 
 StatScope::~StatScope() = default;
@@ -49,6 +72,7 @@ int ttsg_stats_enable(int32_t on) {
     std::lock_guard<std::mutex> lk(ttsg::g_mu);
     ttsg::g_recs.clear();
     ttsg::g_next = 0;
+    for (auto& e : ttsg::g_events) e = 0;
     if (on) {
         if (ttsg::g_slots == nullptr) {
             if (hipMalloc(&ttsg::g_slots, ttsg::kSlots * sizeof(ttsg::DevSlot)) != hipSuccess) return -TTSG_ERR_HIP;
@@ -77,8 +101,15 @@ int ttsg_stats_read(ttsg_stats* out) {
     if (ttsg::g_next > 0 &&
         hipMemcpy(h.data(), ttsg::g_slots, ttsg::g_next * sizeof(ttsg::DevSlot), hipMemcpyDeviceToHost) != hipSuccess)
         return -TTSG_ERR_HIP;
+    const char* logp = std::getenv("TTSG_SHAPE_LOG");
+    FILE* log = (logp != nullptr && logp[0] != 0) ? std::fopen(logp, "a") : nullptr;
     for (const auto& r : ttsg::g_recs) {
         const ttsg::DevSlot& s = h[r.slot];
+        if (log != nullptr && s.end != 0 && s.start_inv != 0) {
+            const unsigned long long t0 = ~s.start_inv;
+            std::fprintf(log, "%d %d %d %d %d %d %.9f %.6e\n", r.cls, r.shp[0], r.shp[1], r.shp[2], r.shp[3], r.shp[4],
+                         s.end > t0 ? (double)(s.end - t0) / (1e3 * rate_khz) : 0.0, r.flops);
+        }
         if (s.end == 0 || s.start_inv == 0) continue;      // launch without workgroups
         const unsigned long long t0 = ~s.start_inv;
         const double sec = s.end > t0 ? (double)(s.end - t0) / (1e3 * rate_khz) : 0.0;
@@ -88,6 +119,11 @@ int ttsg_stats_read(ttsg_stats* out) {
         out->bytes[c] += r.bytes;
         out->seconds[c] += sec;
         if (c == TTSG_ST_SVD && s.aux > (unsigned long long)out->flops[7]) out->flops[7] = (double)s.aux;
+    }
+    if (log != nullptr) std::fclose(log);
+    for (int c = 0; c < TTSG_ST_CLASSES; ++c) {
+        out->launches[c] += ttsg::g_events[c];
+        ttsg::g_events[c] = 0;
     }
     ttsg::g_recs.clear();
     ttsg::g_next = 0;

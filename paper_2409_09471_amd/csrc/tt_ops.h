@@ -57,7 +57,7 @@ struct OpView {
 };
 
 // Element size of a precision's storage type.
-inline size_t elem_size(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2); }
+inline size_t elem_size(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
 // ---------------------------------------------------------------------------
 // STTA sketch (Sec. 3.3) of x or A x.  Y holds d-1 cores (modes 0..d-2),
@@ -130,6 +130,9 @@ struct TsqrPlan {
 // TT-SVD rounding in place: cores `w` (capacity per core given by cap_elems)
 // with ranks r; on return r holds the new ranks.  Returns ||T||_F.
 // tol is relative, maxrank 0 = none.  Synchronizes the stream.
+// Arena bytes that tt_svd_inplace needs beyond 6 cores of the largest size
+// (core snapshot for the Householder redo and the CholQR2 scratch).
+size_t tt_svd_extra_bytes(int d, const int* n, const int* r);
 double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vector<double*>& w,
                       const std::vector<int64_t>& cap_elems, double tol, int maxrank, Arena& ar,
                       hipStream_t st, double* norm_before = nullptr);
@@ -171,6 +174,15 @@ void tt_add_block(int d, const int* n, const std::vector<int>& ra, const std::ve
                   const std::vector<int>& rb, const std::vector<const double*>& b, double bscale,
                   const std::vector<double*>& out, std::vector<int>& rout, hipStream_t st,
                   double ascale = 1.0);
+
+// CholQR2 of the m x c matrix X (element (i, j) at X[i*xr + j*xc]) into Q
+// (same convention, strides qr/qc) and upper R (c x c, column-major).  Raises
+// flag[0] = 1 on the device when the factorization is not trustworthy
+// (cholqr.hip); requires cholqr_fits(m, c).
+bool cholqr_fits(int m, int c);
+void cholqr2(int m, int c, const double* X, int64_t xr, int64_t xc, double* Q, int64_t qr, int64_t qc, double* R,
+             int* flag, Arena& ar, hipStream_t st);
+void zero_flags(int n, int* f, hipStream_t st);
 
 // -<lambda, L_k x> for every mode k (grad.hip); result in out_dev[0..d-1].
 void grad_kron_sum(int d, const int* n, const std::vector<const double*>& L, const std::vector<int>& rl,

@@ -256,7 +256,6 @@ inline char* adv(const void* p, int64_t elems, Prec pr) {
 
 void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::vector<const void*>& x,
                  double* const* Psi, double* const* Omega, Arena& ar, hipStream_t st) {
-    TTSG_CHECK(o.p != Prec::BF16, TTSG_ERR_ARG, "stta_sketch: bf16 operands are converted by the caller");
     const int d = o.d;
     const int* n = o.n;
     const Prec p = o.p;
@@ -338,7 +337,6 @@ void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::
 void kr_sketch_run(Prec p, int d, const int* n, int s, const std::vector<int>& R,
                    const std::vector<const void*>& SA, const std::vector<int>& r,
                    const std::vector<const void*>& x, double* w, Arena& ar, hipStream_t st) {
-    TTSG_CHECK(p != Prec::BF16, TTSG_ERR_ARG, "kr_sketch: bf16 not supported");
     const size_t es = elem_size(p);
     const size_t mark = ar.mark();
     int64_t pmax = 1, xmax = 1;
@@ -371,7 +369,6 @@ void kr_sketch_run(Prec p, int d, const int* n, int s, const std::vector<int>& R
 void inner_run(Prec p, int d, const int* n, const std::vector<int>& R, const std::vector<const void*>& D,
                const std::vector<int>& rx_, const std::vector<const void*>& x, const std::vector<int>& rz,
                const std::vector<const void*>& z, double* out_dev, Arena& ar, hipStream_t st) {
-    TTSG_CHECK(p != Prec::BF16, TTSG_ERR_ARG, "inner: bf16 not supported");
     const size_t es = elem_size(p);
     const size_t mark = ar.mark();
     const bool op = !D.empty();

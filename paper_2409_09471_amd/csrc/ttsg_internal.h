@@ -83,11 +83,17 @@ struct DevSlot {
     unsigned long long pad;
 };
 bool stats_on();
+// Count one host-side event of class cls while measurement is on.
+void stats_event(int cls);
 struct StatScope {
     StatScope(int cls, double flops, double bytes, hipStream_t st);
     ~StatScope();
     DevSlot* slot() const { return slot_; }
+    // Attach the launch shape (e.g. M, N, K, batch, splits) to the record; it is
+    // written out by ttsg_stats_read when TTSG_SHAPE_LOG names a file.
+    void shape(int a, int b, int c, int d, int e);
     DevSlot* slot_ = nullptr;
+    int64_t rec_ = -1;
 };
 
 __device__ __forceinline__ void slot_begin(DevSlot* s) {
@@ -111,12 +117,14 @@ struct ContractDesc {
     double alpha, beta;
 };
 
-// Element types of the contraction kernels.
+// Arithmetic of the contraction kernels.  F32 and BF16 share float32
+// storage; BF16 rounds the operands to bfloat16 as they enter the matrix cores.
 enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
 
 class Arena;
-// Launchers (contract.hip).  A/B are float64 for F64, float32 for F32, and
-// bf16 (uint16_t storage) for BF16; C is float64 for F64 and float32 otherwise.
+// Launchers (contract.hip).  A/B are float64 for F64 and float32 otherwise
+// (BF16 multiplies their bfloat16 roundings); C is float64 for F64 and float32
+// otherwise.
 // With an arena, reductions too long for the output tiles to fill the chip are
 // split over several workgroups (partials in the arena, summed in fixed order).
 void contract(Prec p, const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st,

@@ -48,10 +48,11 @@ def lib():
 EXPORTED = [
     "ttsg_last_error", "ttsg_version", "ttsg_matvec", "ttsg_kr_sketch", "ttsg_stta_sketch",
     "ttsg_round_rand", "ttsg_round_svd", "ttsg_sgmres_solve", "ttsg_true_residual", "ttsg_dot",
-    "ttsg_grad_kron_sum", "ttsg_tt_axpby", "ttsg_stats_enable", "ttsg_stats_read",
+    "ttsg_sgmres_solve_batched", "ttsg_grad_kron_sum", "ttsg_tt_axpby", "ttsg_stats_enable", "ttsg_stats_read",
 ]
 
-STAT_CLASSES = {0: "contract_f64", 1: "contract_f32", 2: "contract_bf16", 3: "qr", 4: "svd_jacobi"}
+STAT_CLASSES = {0: "contract_f64", 1: "contract_f32", 2: "contract_bf16", 3: "qr", 4: "svd_jacobi",
+                5: "qr_redo"}
 
 
 class Stats(ctypes.Structure):
@@ -331,3 +332,91 @@ def sgmres_solve(A, b, S, X, Y, rx, rho, *, maxit: int, tol: float, q: int = 1, 
         true_history=[th[i] for i in range(min(info.cycles, max_cycles))],
         phase_seconds={PHASES[i]: ph[i] for i in range(8)} if phase_timing else {},
     )
+
+
+class _System(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("n", ctypes.c_void_p), ("R", ctypes.c_void_p), ("A", ctypes.c_void_p),
+                ("rb", ctypes.c_void_p), ("b", ctypes.c_void_p), ("s", ctypes.c_int32), ("S", ctypes.c_void_p),
+                ("rho", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("rx", ctypes.c_void_p), ("X", ctypes.c_void_p),
+                ("opts", ctypes.c_void_p), ("x", ctypes.c_void_p), ("x_r", ctypes.c_void_p), ("info", ctypes.c_void_p),
+                ("status", ctypes.c_int32)]
+
+
+@dataclass
+class BatchSystem:
+    """One system of a batched solve (cores are CUDA float64 tensors)."""
+    A: List[torch.Tensor]
+    b: List[torch.Tensor]
+    S: List[torch.Tensor]
+    X: List[torch.Tensor]
+    Y: List[torch.Tensor]
+    rx: List[int]
+    rho: List[int]
+    maxit: int
+    tol: float
+    q: int = 1
+    round_tol: float = 1e-7
+    maxrank: int = 0
+    restart: int = 0
+    final_tol: float = 0.0
+    stop_safety: float = 0.1
+    rcond: float = 1e-12
+    precision: int = PREC_F64
+    max_cycles: int = 50
+
+
+def sgmres_solve_batched(systems: Sequence[BatchSystem], concurrency: int = 8) -> List[SolveResult]:
+    """Solve independent systems concurrently (ttsg_sgmres_solve_batched)."""
+    keep = []
+    arr = (_System * len(systems))()
+    outs = []
+
+    def addr(obj):
+        keep.append(obj)
+        return ctypes.cast(obj, ctypes.c_void_p)
+
+    for i, q in enumerate(systems):
+        d = len(q.b)
+        n = sizes_of(q.b)
+        dev = q.b[0].device
+        opts = SgmresOpts(maxit=q.maxit, restart=q.restart, q=q.q, maxrank=q.maxrank, precision=q.precision,
+                          max_cycles=q.max_cycles, tol=q.tol, round_tol=q.round_tol, final_tol=q.final_tol,
+                          stop_safety=q.stop_safety, rcond=q.rcond)
+        sh = (ctypes.c_double * q.maxit)()
+        rh = (ctypes.c_int32 * q.maxit)()
+        th = (ctypes.c_double * q.max_cycles)()
+        info = SgmresInfo(sketched_history=sh, rank_history=rh, true_history=th, phase_seconds=None)
+        x = [torch.zeros((q.rx[k], n[k], q.rx[k + 1]), dtype=torch.float64, device=dev) for k in range(d)]
+        xr = (ctypes.c_int32 * (d + 1))()
+        keep.extend([opts, info, sh, rh, th, x, xr])
+        e = arr[i]
+        e.d = d
+        e.n = addr(_i32(n))
+        e.R = addr(_i32(op_ranks(q.A)))
+        e.A = addr(_ptrs(q.A))
+        e.rb = addr(_i32(ranks_of(q.b)))
+        e.b = addr(_ptrs(q.b))
+        e.s = int(q.S[0].shape[0])
+        e.S = addr(_ptrs(q.S))
+        e.rho = addr(_i32(q.rho))
+        e.Y = addr(_ptrs(q.Y))
+        e.rx = addr(_i32(q.rx))
+        e.X = addr(_ptrs(q.X))
+        e.opts = ctypes.cast(ctypes.pointer(opts), ctypes.c_void_p)
+        e.x = addr(_ptrs(x))
+        e.x_r = ctypes.cast(xr, ctypes.c_void_p)
+        e.info = ctypes.cast(ctypes.pointer(info), ctypes.c_void_p)
+        outs.append((x, xr, info, sh, rh, th, q))
+    _check(lib().ttsg_sgmres_solve_batched(len(systems), arr, int(concurrency), _stream()),
+           "ttsg_sgmres_solve_batched")
+    res = []
+    for i, (x, xr, info, sh, rh, th, q) in enumerate(outs):
+        it = info.iterations
+        res.append(SolveResult(
+            x=_trim(x, list(xr)), status=arr[i].status, iterations=it, cycles=info.cycles,
+            true_residual=info.true_residual, sketched_residual=info.sketched_residual, max_rank=info.max_rank,
+            sketched_history=[sh[j] for j in range(min(it, q.maxit))],
+            rank_history=[rh[j] for j in range(min(it, q.maxit))],
+            true_history=[th[j] for j in range(min(info.cycles, q.max_cycles))]))
+    return res
+

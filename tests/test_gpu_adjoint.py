@@ -77,7 +77,8 @@ def test_adjoint_gradient_small_matches_closed_form():
     _, adjoint = _lib()
     c = syn.config_c4(d=4, n=8)
     loss_ref, g_ref = og.loss_and_grad(c["theta"], [c["L"]] * 4, c["b"], c["x_target"])
-    P = _problem(c, maxit=400, tol=1e-10, q=2, round_tol=1e-12, maxrank=64, restart=25)
+    P = _problem(c, maxit=400, tol=1e-10, q=2, round_tol=1e-12, final_tol=0.0, maxrank=64, restart=25,
+                 stop_safety=0.1)
     th = torch.tensor(c["theta"], dtype=torch.float64, requires_grad=True)
     loss = adjoint.kron_sum_solve_loss(th, P)
     loss.backward()
@@ -93,7 +94,8 @@ def test_adjoint_lambda_is_gradient_wrt_b():
     closed-form loss along a random rank-2 direction db."""
     ttsg, adjoint = _lib()
     c = syn.config_c4(d=4, n=8)
-    P = _problem(c, maxit=400, tol=1e-10, q=2, round_tol=1e-12, maxrank=64, restart=25)
+    P = _problem(c, maxit=400, tol=1e-10, q=2, round_tol=1e-12, final_tol=0.0, maxrank=64, restart=25,
+                 stop_safety=0.1)
     th = torch.tensor(c["theta"], dtype=torch.float64, requires_grad=True)
     adjoint.kron_sum_solve_loss(th, P).backward()
     lam = P.last["lam"]
@@ -136,7 +138,8 @@ def test_adjoint_gradient_nonsymmetric_dense():
     assert np.linalg.norm(g_fd - g_ref) <= 1e-5 * np.linalg.norm(g_ref)
     S, X, Y, rx, rho = syn._sketches(rng, [n] * d, 400, 64, 20)
     c = dict(L=Lm, d=d, b=b, x_target=xt, S=S, X=X, Y=Y, rx=rx, rho=rho)
-    P = _problem(c, maxit=300, tol=1e-11, q=2, round_tol=1e-13, maxrank=64, restart=25)
+    P = _problem(c, maxit=300, tol=1e-11, q=2, round_tol=1e-13, final_tol=0.0, maxrank=64, restart=25,
+                 stop_safety=0.1)
     th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
     loss = adjoint.kron_sum_solve_loss(th, P)
     loss.backward()

@@ -1,0 +1,110 @@
+"""GPU tests of the batched solve: independent systems of uneven order, mode
+size and right-hand-side rank run concurrently on worker streams.
+
+Each system of a batch must come out bit for bit as when it is solved alone
+(the kernels are deterministic: split-K partials are summed in a fixed order
+and no result depends on which stream or when a kernel ran); in FP64 every
+system must converge to the true residual asked for, as the oracle's sketched
+TT-GMRES does on the same inputs, with the same early residual history.  (In the mixed mode one
+of these tiny systems stalls near a sketched residual of 3e-4, so there only
+the exact agreement with the lone solve is required.)"""
+import numpy as np
+import pytest
+import torch
+
+import synthetic as syn
+from oracle import operators as oops
+from oracle import solvers as osol
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _ttsg():
+    from paper_2409_09471_amd import ttsg
+    return ttsg
+
+
+def _systems(specs, precision, maxit=250):
+    ttsg = _ttsg()
+    out, ws = [], []
+    for i, d, n, rb in specs:
+        w = syn.config_c3_system(i, d, n, rb, s=600, maxit=maxit)
+        ws.append(w)
+        out.append(ttsg.BatchSystem(
+            A=ttsg.kron_sum_operator(w.terms, DEV), b=ttsg.to_device(w.b, DEV), S=ttsg.to_device(w.S, DEV),
+            X=ttsg.to_device(w.X, DEV), Y=ttsg.to_device(w.Y, DEV), rx=w.rx, rho=w.rho, maxit=w.maxit, tol=w.tol,
+            q=w.q, round_tol=w.round_tol, maxrank=w.cap, stop_safety=w.stop_safety, precision=precision))
+    return out, ws
+
+
+# (seed index, d, n, rank of b): uneven systems of the batched workload's
+# family (Laplacian, caps 32) small enough for the oracle; each converges to
+# 1e-6 within 100 iterations (one of them after a restart cycle).
+SPECS = [(0, 4, 8, 2), (1, 5, 8, 2), (3, 3, 8, 1), (5, 2, 16, 1), (8, 4, 8, 3), (11, 4, 6, 2), (12, 3, 10, 3)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_equals_one_by_one(precision):
+    ttsg = _ttsg()
+    systems, _ = _systems(SPECS, precision)
+    alone = [ttsg.sgmres_solve_batched([q], concurrency=1)[0] for q in systems]
+    batched = ttsg.sgmres_solve_batched(systems, concurrency=3)
+    for a, b in zip(alone, batched):
+        assert b.status == a.status
+        assert b.iterations == a.iterations
+        assert b.true_residual == a.true_residual
+        if precision == 0:
+            assert b.status == ttsg.OK and b.true_residual <= 1e-6
+        assert [int(c.shape[0]) for c in b.x] == [int(c.shape[0]) for c in a.x]
+        for ca, cb in zip(a.x, b.x):
+            assert torch.equal(ca, cb)
+
+
+def test_batched_matches_single_entry_point():
+    """The batched path and ttsg_sgmres_solve on the caller's stream agree."""
+    ttsg = _ttsg()
+    systems, _ = _systems(SPECS[:3], 0)
+    batched = ttsg.sgmres_solve_batched(systems, concurrency=2)
+    for q, b in zip(systems, batched):
+        r = ttsg.sgmres_solve(q.A, q.b, q.S, q.X, q.Y, q.rx, q.rho, maxit=q.maxit, tol=q.tol, q=q.q,
+                              round_tol=q.round_tol, maxrank=q.maxrank, stop_safety=q.stop_safety)
+        assert r.iterations == b.iterations
+        assert abs(r.true_residual - b.true_residual) <= 1e-12 * max(r.true_residual, 1e-300)
+
+
+def test_batched_small_systems_match_oracle():
+    """FP64: every system of the batch converges to the requested true residual,
+    as the oracle's sketched TT-GMRES does on the same inputs, and the first ten
+    sketched residuals agree with the oracle's to 1e-6 relative.  Later
+    iterations differ by the rounding noise of the basis (1e-7 relative per
+    rounding, different QR algorithms on the two sides), which changes how many
+    iterations a system needs, so iteration counts are not compared."""
+    ttsg = _ttsg()
+    specs = [SPECS[0], SPECS[2], SPECS[5]]
+    systems, ws = _systems(specs, 0)
+    res = ttsg.sgmres_solve_batched(systems, concurrency=3)
+    for w, r in zip(ws, res):
+        A = oops.tt_kron_sum(w.terms)
+        x, info = osol.tt_sgmres(A, w.b, w.S, w.X, w.Y, maxit=w.maxit, tol=w.tol, q=w.q, round_tol=w.round_tol,
+                                 maxrank=w.cap, stop_safety=w.stop_safety)
+        assert r.status == ttsg.OK and r.true_residual <= 1e-6
+        assert osol.true_residual(A, w.b, x) <= 1e-6
+        ko = info["sketched_residuals"]
+        for k in range(min(10, len(ko), len(r.sketched_history))):
+            assert abs(r.sketched_history[k] - ko[k]) <= 1e-6 * ko[k], (k, r.sketched_history[k], ko[k])
+
+
+def test_batched_reports_bad_system():
+    """A malformed system (rank of b above the STTA ranks) makes the batch fail
+    with that system's index in the message."""
+    ttsg = _ttsg()
+    systems, _ = _systems(SPECS[:3], 0)
+    bad = systems[1]
+    d = len(bad.b)
+    big = syn.gaussian_tt(np.random.default_rng(1), [int(c.shape[1]) for c in bad.b],
+                          [1] + [bad.rx[k] + 1 for k in range(1, d)] + [1])
+    bad.b = ttsg.to_device(big, DEV)
+    with pytest.raises(ttsg.TTSGError, match="system 1"):
+        ttsg.sgmres_solve_batched(systems, concurrency=2)
