@@ -17,8 +17,10 @@ Prints one JSON line.  Only N = 1 is supported (one GPU).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -63,14 +65,15 @@ def solve(w, t, precision, phase_timing=False):
                              precision=precision, phase_timing=phase_timing)
 
 
-def timed_solves(w, t, precision, steps, warmup):
+def timed_solves(w, t, precision, steps, warmup, measure=True):
+    """Wall-clock time of `steps` solves (measurement off), then (measure=True)
+    one more solve with the per-launch device timers on for the kernel figures."""
     import torch
     from paper_2409_09471_amd import ttsg
     for i in range(warmup):
         r = solve(w, t, precision)
         print(f"# warmup {i}: its={r.iterations} true_res={r.true_residual:.3e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    ttsg.stats_enable(True)
     t0 = time.perf_counter()
     results = []
     for i in range(steps):
@@ -79,8 +82,12 @@ def timed_solves(w, t, precision, steps, warmup):
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    stats = ttsg.stats_read()
-    ttsg.stats_enable(False)
+    stats = {}
+    if measure:
+        ttsg.stats_enable(True)
+        solve(w, t, precision)
+        stats = ttsg.stats_read()
+        ttsg.stats_enable(False)
     return elapsed, results, stats
 
 
@@ -106,6 +113,30 @@ def rounding_gflops(w, t):
     ttsg.stats_enable(False)
     fl = sum(v["flops"] for v in st.values()) / reps
     return dict(seconds=el, gflop=fl / 1e9, gflops_per_s=fl / el / 1e9)
+
+
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "contract_kernel_hbm_counters_convdiff_d10_n64.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2409_09471_amd", "csrc", "contract.hip")
+
+
+def counter_traffic(cls):
+    """HBM bytes per launch of the contraction class `cls` from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when that summary was taken on a
+    different version of the kernel source (or is missing)."""
+    if not os.path.exists(COUNTER_SUMMARY):
+        return None
+    fields = {}
+    for line in open(COUNTER_SUMMARY):
+        m = re.match(r"^- (\w+): (\S+)", line.strip())
+        if m:
+            fields[m.group(1)] = m.group(2)
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha or fields.get("class") != cls:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(w, gpu_iterations, budget_s):
@@ -178,7 +209,7 @@ def main():
         "converged": converged, "iterations": last.iterations, "true_residual": last.true_residual,
         "sketched_residual": last.sketched_residual, "max_rank": last.max_rank,
     }
-    # per-class kernel figures over the timed region (HIP events on the launch stream)
+    # per-class kernel figures of one measured solve (device wall-clock per launch)
     kern = {}
     for k, v in stats.items():
         kern[k] = dict(launches=v["launches"], seconds=round(v["seconds"], 6),
@@ -193,11 +224,11 @@ def main():
         ach = v["flops"] / v["launches"] / (v["seconds"] / v["launches"])
         out["roofline"] = {"kernel": f"contract_kernel<{ {'f64': 'double', 'f32': 'float', 'bf16': 'bf16'}[dt]}>",
                            "bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[dt] / 1e12, "unit": "TFLOP/s",
-                           "frac": ach / PEAK[dt], "traffic": None,
+                           "frac": ach / PEAK[dt], "traffic": counter_traffic(cls),
                            "flop_per_launch": v["flops"] / v["launches"],
                            "avg_launch_us": v["seconds"] / v["launches"] * 1e6}
     if prec == ttsg.PREC_MIXED and not args.no_fp64_leg:
-        el64, res64, _ = timed_solves(w, t, ttsg.PREC_F64, 1, 0)
+        el64, res64, _ = timed_solves(w, t, ttsg.PREC_F64, 1, 0, measure=False)
         out["fp64_seconds"] = el64
         out["fp64_iterations"] = res64[-1].iterations
         out["fp64_true_residual"] = res64[-1].true_residual

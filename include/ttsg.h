@@ -94,7 +94,8 @@ int ttsg_matvec(int32_t d, const int32_t* n, const int32_t* R, const double* con
 /* without forming A x.  (S x)_j = prod_k sum_i S_k[j, i] C_k[:, i, :].       */
 /* ------------------------------------------------------------------------- */
 /* w: DEVICE float64 array of length s.  R/A may be NULL (plain sketch).
- * precision: TTSG_PREC_F64 or TTSG_PREC_MIXED (float32 contractions).
+ * precision: TTSG_PREC_F64, TTSG_PREC_MIXED (float32 contractions) or
+ * TTSG_PREC_BF16 (bfloat16 matrix-core inputs, float32 accumulation).
  * Does not synchronize. */
 int ttsg_kr_sketch(int32_t d, const int32_t* n, int32_t s, const double* const* S,
                    const int32_t* R, const double* const* A,
@@ -293,7 +294,7 @@ int ttsg_stats_enable(int32_t on);
 /* Synchronize the device, resolve the recorded slots into *out and clear.
  * When the environment variable TTSG_SHAPE_LOG names a file, one line per
  * measured launch is appended to it: class, M, N, K, batch, split count (0s
- * for non-contractions), seconds, flops. */
+ * for non-contractions), seconds, flops, auxiliary maximum (Jacobi sweeps). */
 int ttsg_stats_read(ttsg_stats* out);
 
 #ifdef __cplusplus

@@ -99,8 +99,7 @@ int ttsg_kr_sketch(int32_t d, const int32_t* n, int32_t s, const double* const* 
         check_shape(d, n, r, "kr_sketch x");
         TTSG_CHECK(s >= 1, TTSG_ERR_ARG, "kr_sketch: s < 1");
         TTSG_CHECK(w != nullptr, TTSG_ERR_ARG, "kr_sketch: null output");
-        TTSG_CHECK(precision == TTSG_PREC_F64 || precision == TTSG_PREC_MIXED, TTSG_ERR_ARG,
-                   "kr_sketch: precision must be F64 or MIXED");
+        (void)prec_of(precision);
         check_ptrs(d, (const void* const*)Sf, "kr_sketch S");
         check_ptrs(d, (const void* const*)x, "kr_sketch x");
         const bool op = A != nullptr;
@@ -204,8 +203,7 @@ int ttsg_stta_sketch(int32_t d, const int32_t* n, const int32_t* rho, const doub
         check_shape(d, n, rho, "stta rho");
         check_shape(d, n, rx, "stta rx");
         TTSG_CHECK(d >= 2, TTSG_ERR_ARG, "stta: d must be >= 2");
-        TTSG_CHECK(precision == TTSG_PREC_F64 || precision == TTSG_PREC_MIXED, TTSG_ERR_ARG,
-                   "stta: precision must be F64 or MIXED");
+        (void)prec_of(precision);
         check_ptrs(d - 1, (const void* const*)Y, "stta Y");
         check_ptrs(d - 1, (const void* const*)X, "stta X");
         check_ptrs(d, (const void* const*)x, "stta x");

@@ -41,50 +41,54 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
     __syncthreads();
     // Right-looking Cholesky on the upper triangle.  Step j reads row j and
     // writes the scaled row as R^T into the (unused) lower triangle and the
-    // rank-1 update into rows > j, so one barrier per step suffices.
+    // rank-1 update into rows > j, so one barrier per step suffices.  Thread
+    // (rg, l) owns column l and every fourth row of the update.
+    const int l = tid & 63, rg = tid >> 6;
     for (int j = 0; j < c; ++j) {
         double p = A[j][j];
         const double dj = d0[j];
         const bool ok = p > 1e-10 * dj && p <= 4.0 * dj && dj < INFINITY;
         if (!ok) p = (dj > 0.0 && dj < INFINITY) ? dj : 1.0;   // keep going; the flag discards the result
         const double rjj = sqrt(p);
-        const double inv_p = 1.0 / p;
         if (tid == 0) {
             rd[j] = rjj;
             if (!ok) s_bad = 1;
         }
-        const int w = c - j - 1;
-        for (int l = j + 1 + tid; l < c; l += CQ_T) A[l][j] = A[j][l] / rjj;
-        for (int e = tid; e < w * w; e += CQ_T) {
-            const int i = j + 1 + e / w, l = j + 1 + e % w;
-            if (i <= l) A[i][l] -= A[j][i] * A[j][l] * inv_p;
+        if (l > j && l < c) {
+            const double ajl = A[j][l];
+            if (rg == 0) A[l][j] = ajl / rjj;
+            const double f = ajl / p;
+            for (int i = j + 1 + rg; i <= l; i += 4) A[i][l] -= A[j][i] * f;
         }
         __syncthreads();
     }
     // R (upper): R[j][l] = A[l][j] for l > j, rd[j] on the diagonal
     for (int e = tid; e < c * c; e += CQ_T) {
-        const int l = e / c, j = e - l * c;
-        const double v = l > j ? A[l][j] : (l == j ? rd[j] : 0.0);
-        R[j + (int64_t)l * c] = v;
-        if (second_pass && fabs(v - (l == j ? 1.0 : 0.0)) > 0.1) s_bad = 1;
+        const int cl = e / c, j = e - cl * c;
+        const double v = cl > j ? A[cl][j] : (cl == j ? rd[j] : 0.0);
+        R[j + (int64_t)cl * c] = v;
+        if (second_pass && fabs(v - (cl == j ? 1.0 : 0.0)) > 0.1) s_bad = 1;
+    }
+    // R^-1 by right-looking back substitution on the upper triangle (R^T stays
+    // in the lower one): acc starts as I; step j takes row j of R^-1 as
+    // acc[j][:] / R[j][j] and removes R[i][j] times it from the rows i < j.
+    // Rows are divided by their pivots at the end, so row j is never written
+    // while step j reads it.
+    for (int e = tid; e < c * c; e += CQ_T) {
+        const int cl = e / c, i = e - cl * c;
+        if (i <= cl) A[i][cl] = i == cl ? 1.0 : 0.0;
     }
     __syncthreads();
-    // R^-1 (upper) into the upper triangle, bottom row first:
-    // Ri[i][l] = -(sum_{t=i+1..l} R[i][t] Ri[t][l]) / R[i][i].  Four lanes share
-    // a column and split the sum.
-    const int col = tid >> 2, part = tid & 3;
-    for (int i = c - 1; i >= 0; --i) {
-        double s = 0.0;
-        if (col < c && col > i)
-            for (int t = i + 1 + part; t <= col; t += 4) s += A[t][i] * A[t][col];
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
-        if (col < c && part == 0 && col >= i) A[i][col] = col == i ? 1.0 / rd[i] : -s / rd[i];
+    for (int j = c - 1; j >= 1; --j) {
+        if (l >= j && l < c) {
+            const double rjl = A[j][l] / rd[j];
+            for (int i = rg; i < j; i += 4) A[i][l] -= A[j][i] * rjl;
+        }
         __syncthreads();
     }
     for (int e = tid; e < c * c; e += CQ_T) {
-        const int l = e / c, i = e - l * c;
-        Ri[i + (int64_t)l * c] = l >= i ? A[i][l] : 0.0;
+        const int cl = e / c, i = e - cl * c;
+        Ri[i + (int64_t)cl * c] = i <= cl ? A[i][cl] / rd[i] : 0.0;
     }
     if (tid == 0 && s_bad) flag[0] = 1;
     slot_end(slot);

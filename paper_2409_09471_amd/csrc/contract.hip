@@ -271,21 +271,45 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
     slot_end(slot);
 }
 
-template <typename O>
-__global__ void reduce_splits(ContractDesc d, int splits, const O* __restrict__ part, O* __restrict__ C) {
+// Sum of the split-K partials.  Each output element belongs to a group of G
+// lanes: lane g adds splits g, g + G, ... in order, then the group combines
+// its lanes with a fixed xor tree -- the same order on every run.
+template <typename O, int G>
+__global__ __launch_bounds__(256) void reduce_splits(ContractDesc d, int splits, const O* __restrict__ part,
+                                                     O* __restrict__ C) {
     const int64_t per = (int64_t)d.M * d.N;
     const int64_t total = per * d.batch;
     const O alpha = (O)d.alpha, beta = (O)d.beta;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int b = (int)(e / per);
-        const int64_t mn = e - (int64_t)b * per;
-        const int m = (int)(mn / d.N), n = (int)(mn - (int64_t)m * d.N);
+    const int g = threadIdx.x & (G - 1);
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / G);
+    for (int64_t e = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G; e < total; e += stride) {
         O acc = 0;
-        for (int s = 0; s < splits; ++s) acc += part[(int64_t)s * total + e];
-        const int64_t off = idx_off(d.cb, b) + idx_off(d.cm, m) + idx_off(d.cn, n);
-        O v = alpha * acc;
-        if (beta != O(0)) v += beta * C[off];
-        C[off] = v;
+        for (int s = g; s < splits; s += G) acc += part[(int64_t)s * total + e];
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+        if (g == 0) {
+            const int b = (int)(e / per);
+            const int64_t mn = e - (int64_t)b * per;
+            const int m = (int)(mn / d.N), n = (int)(mn - (int64_t)m * d.N);
+            const int64_t off = idx_off(d.cb, b) + idx_off(d.cm, m) + idx_off(d.cn, n);
+            O v = alpha * acc;
+            if (beta != O(0)) v += beta * C[off];
+            C[off] = v;
+        }
+    }
+}
+
+template <typename O>
+void launch_reduce(const ContractDesc& d, int splits, const O* part, O* C, hipStream_t st) {
+    const int64_t total = (int64_t)d.batch * d.M * d.N;
+    const int G = splits <= 4 ? 4 : (splits <= 8 ? 8 : (splits <= 16 ? 16 : 32));
+    const int64_t per_block = 256 / G;
+    const int rb = (int)std::max<int64_t>(1, std::min<int64_t>((total + per_block - 1) / per_block, 16384));
+    switch (G) {
+        case 4: hipLaunchKernelGGL((reduce_splits<O, 4>), dim3(rb), dim3(256), 0, st, d, splits, part, C); break;
+        case 8: hipLaunchKernelGGL((reduce_splits<O, 8>), dim3(rb), dim3(256), 0, st, d, splits, part, C); break;
+        case 16: hipLaunchKernelGGL((reduce_splits<O, 16>), dim3(rb), dim3(256), 0, st, d, splits, part, C); break;
+        default: hipLaunchKernelGGL((reduce_splits<O, 32>), dim3(rb), dim3(256), 0, st, d, splits, part, C); break;
     }
 }
 
@@ -324,9 +348,12 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
     // split-K when the output tiles alone cannot fill the chip
     constexpr int BK = Traits<T>::BK;
     const int64_t wgs = (int64_t)gx * gy * d.batch;
+    // (at least four k-slabs per split, at most 64 splits, about two
+    // workgroups per CU in total)
     int splits = 1, kchunk = d.K;
-    if (ar != nullptr && wgs < 512 && d.K >= 4 * BK) {
-        int want = (int)std::min<int64_t>((1024 + wgs - 1) / wgs, d.K / (2 * BK));
+    if (ar != nullptr && wgs < 512 && d.K >= 8 * BK) {
+        int want = (int)std::min<int64_t>((512 + wgs - 1) / wgs, d.K / (4 * BK));
+        want = std::min(want, 64);
         want = std::min<int64_t>(want, 65535 / std::max(d.batch, 1));
         if (want >= 2) {
             kchunk = ((d.K + want - 1) / want + BK - 1) / BK * BK;
@@ -341,9 +368,7 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         hipLaunchKernelGGL(contract_kernel<T>, dim3(gx, gy, zt), block, 0, st, d, static_cast<const in_t*>(A),
                            static_cast<const in_t*>(B), static_cast<out_t*>(C), 0, splits, kchunk, part,
                            scope.slot());
-        const int64_t total = (int64_t)d.batch * d.M * d.N;
-        const int rb = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 8192));
-        hipLaunchKernelGGL(reduce_splits<out_t>, dim3(rb), dim3(256), 0, st, d, splits, part, static_cast<out_t*>(C));
+        launch_reduce<out_t>(d, splits, part, static_cast<out_t*>(C), st);
         ar->release(mark);
     } else {
         for (int b0 = 0; b0 < d.batch; b0 += 65535) {

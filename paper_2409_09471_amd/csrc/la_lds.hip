@@ -21,7 +21,7 @@
 namespace ttsg {
 namespace {
 
-constexpr int JT = 1024;   // threads of the Jacobi workgroup
+constexpr int JT = 512;    // threads of the Jacobi workgroup (32 lane groups of 16)
 constexpr int QT = 1024;   // threads of the QR leaf workgroups
 constexpr int LEAF = 256;  // maximum rows of a TSQR leaf
 
@@ -58,7 +58,26 @@ template <int G> __device__ __forceinline__ double gsum(double v) {
 // forms the pair's three dot products over its strided rows, reduces them in
 // registers, and rotates the same rows, so a round of the circle method costs
 // a single barrier.  The pairs of every round come from a table built once.
-constexpr int JG = 32;
+constexpr int JG = 16;
+constexpr int JROWS = 8;   // rows of a column held per lane: m <= JG * JROWS
+
+// Data-parallel-primitive move of a double within a row of 16 lanes.
+template <int CTRL> __device__ __forceinline__ double dpp_mov(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over the 16 lanes of a row: quad swaps (xor 1, xor 2), then the half-row
+// and row mirrors.  Every step adds two partial sums in commuted order on the
+// two lanes involved, so all 16 lanes end with bit-identical totals.
+__device__ __forceinline__ double row_sum16(double v) {
+    v += dpp_mov<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return v;
+}
 __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps, DevSlot* slot) {
     extern __shared__ double lds[];
     slot_begin(slot);
@@ -132,25 +151,38 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
                 if (p >= c || q >= c) continue;
                 double* ap = A + p * ldm;
                 double* aq = A + q * ldm;
+                // the pair's rows stay in registers between the dot products
+                // and the rotation (m <= JG * JROWS)
+                double xp[JROWS], xq[JROWS];
                 double al = 0.0, be = 0.0, ga = 0.0;
-                for (int i = lt; i < m; i += JG) {
-                    const double x = ap[i], y = aq[i];
-                    al += x * x;
-                    be += y * y;
-                    ga += x * y;
+#pragma unroll
+                for (int t = 0; t < JROWS; ++t) {
+                    const int i = lt + t * JG;
+                    xp[t] = 0.0;
+                    xq[t] = 0.0;
+                    if (i < m) {
+                        xp[t] = ap[i];
+                        xq[t] = aq[i];
+                    }
+                    al += xp[t] * xp[t];
+                    be += xq[t] * xq[t];
+                    ga += xp[t] * xq[t];
                 }
-                al = gsum<JG>(al);
-                be = gsum<JG>(be);
-                ga = gsum<JG>(ga);
+                al = row_sum16(al);
+                be = row_sum16(be);
+                ga = row_sum16(ga);
                 if (al <= tiny || be <= tiny || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
                 const double zeta = (be - al) / (2.0 * ga);
                 const double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
                 const double cs = 1.0 / sqrt(1.0 + t * t);
                 const double sn = cs * t;
-                for (int i = lt; i < m; i += JG) {
-                    const double x = ap[i], y = aq[i];
-                    ap[i] = cs * x - sn * y;
-                    aq[i] = sn * x + cs * y;
+#pragma unroll
+                for (int u = 0; u < JROWS; ++u) {
+                    const int i = lt + u * JG;
+                    if (i < m) {
+                        ap[i] = cs * xp[u] - sn * xq[u];
+                        aq[i] = sn * xp[u] + cs * xq[u];
+                    }
                 }
                 double* vp = V + p * ldv;
                 double* vq = V + q * ldv;
@@ -183,7 +215,7 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
         const double* al = A + l * ldm;
         double s2 = 0.0;
         for (int i = lt; i < m; i += JG) s2 += al[i] * al[i];
-        s2 = gsum<JG>(s2);
+        s2 = row_sum16(s2);
         if (lt == 0) jb.sig[bi][l] = sqrt(s2);
     }
     slot_end(slot, (unsigned long long)sweeps_done);
@@ -318,6 +350,102 @@ __global__ __launch_bounds__(QT) void k_qr_apply_leaf(int m, int c, int k, const
     slot_end(slot);
 }
 
+struct QrBatch {
+    int count;
+    int m[32], c[32], lda[32];
+    const double* A[32];
+    double* Q[32];
+    double* R[32];
+};
+
+// Householder QR of one small matrix per workgroup with the explicit Q:
+// the factorization follows k_qr_leaf (one wavefront forms each reflector,
+// lane groups of QG update the trailing columns), then the reflectors are
+// applied in reverse order to the first c columns of the identity.
+__global__ __launch_bounds__(QT) void k_qr_small(QrBatch jb, DevSlot* slot) {
+    extern __shared__ double lds[];
+    slot_begin(slot);
+    __shared__ double s_tau[64];
+    const int bi = blockIdx.x;
+    const int rows = jb.m[bi], c = jb.c[bi], lda = jb.lda[bi];
+    const double* Ag = jb.A[bi];
+    const int ldt = rows | 1;
+    double* T = lds;
+    double* X = lds + (size_t)ldt * c;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int grp = tid / QG, lt = tid - grp * QG, ngrp = QT / QG;
+    for (int e = tid; e < rows * c; e += blockDim.x) {
+        const int j = e / rows, r = e - j * rows;
+        T[j * ldt + r] = Ag[(int64_t)j * lda + r];
+        X[j * ldt + r] = (r == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int kk = rows < c ? rows : c;
+    for (int j = 0; j < kk; ++j) {
+        double* col = T + j * ldt;
+        if (wave == 0) {
+            double sacc = 0.0;
+            for (int r = j + 1 + lane; r < rows; r += 64) sacc += col[r] * col[r];
+            sacc = wsum(sacc);
+            const double alpha = col[j];
+            double tt = 0.0, sc = 0.0, beta = alpha;
+            if (sacc != 0.0) {
+                beta = -copysign(sqrt(alpha * alpha + sacc), alpha);
+                tt = (beta - alpha) / beta;
+                sc = 1.0 / (alpha - beta);
+            }
+            for (int r = j + 1 + lane; r < rows; r += 64) col[r] *= sc == 0.0 ? 1.0 : sc;
+            if (lane == 0) {
+                col[j] = beta;
+                s_tau[j] = tt;
+            }
+        }
+        __syncthreads();
+        const double t = s_tau[j];
+        if (t != 0.0) {
+            for (int l = j + 1 + grp; l < c; l += ngrp) {
+                double* cl = T + l * ldt;
+                double w = 0.0;
+                for (int r = j + 1 + lt; r < rows; r += QG) w += col[r] * cl[r];
+                w = gsum<QG>(w);
+                w = t * (w + cl[j]);
+                if (lt == 0) cl[j] -= w;
+                for (int r = j + 1 + lt; r < rows; r += QG) cl[r] -= w * col[r];
+            }
+        }
+        __syncthreads();
+    }
+    // Q = H_0 ... H_{kk-1} [I; 0]
+    for (int j = kk - 1; j >= 0; --j) {
+        const double tj = s_tau[j];
+        if (tj != 0.0) {
+            const double* v = T + j * ldt;
+            for (int l = grp; l < c; l += ngrp) {
+                double* xl = X + l * ldt;
+                double w = 0.0;
+                for (int r = j + 1 + lt; r < rows; r += QG) w += v[r] * xl[r];
+                w = gsum<QG>(w);
+                w = tj * (w + xl[j]);
+                if (lt == 0) xl[j] -= w;
+                for (int r = j + 1 + lt; r < rows; r += QG) xl[r] -= w * v[r];
+            }
+        }
+        __syncthreads();
+    }
+    double* Qg = jb.Q[bi];
+    double* Rg = jb.R[bi];
+    for (int e = tid; e < rows * c; e += blockDim.x) {
+        const int j = e / rows, r = e - j * rows;
+        Qg[(int64_t)j * rows + r] = X[j * ldt + r];
+    }
+    for (int e = tid; e < c * c; e += blockDim.x) {
+        const int j = e / c, r = e - j * c;
+        Rg[(int64_t)j * c + r] = (r <= j && r < kk) ? T[j * ldt + r] : 0.0;
+    }
+    slot_end(slot);
+}
+
 // Dynamic LDS above the default limit must be requested per kernel; the
 // request (dynamic bytes) plus the kernel's static LDS must fit in 160 KB.
 std::mutex g_lds_mu;
@@ -327,7 +455,7 @@ void allow_lds(const void* fn, size_t bytes, size_t& granted) {
     TTSG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     granted = bytes;
 }
-size_t g_lds_jacobi = 0, g_lds_leaf = 0, g_lds_apply = 0;
+size_t g_lds_jacobi = 0, g_lds_leaf = 0, g_lds_apply = 0, g_lds_small = 0;
 
 int choose_leaves(int m, int c) {
     int nl = (m + LEAF - 1) / LEAF;
@@ -340,7 +468,9 @@ int choose_leaves(int m, int c) {
 size_t jacobi_lds_bytes(int m, int c) { return ((size_t)(m | 1) * c + (size_t)(c | 1) * c) * 8; }
 
 // dynamic LDS (matrix + rotations) plus ~26 KB of static scratch must fit in 160 KB
-bool jacobi_lds_fits(int m, int c) { return m >= c && c <= 64 && jacobi_lds_bytes(m, c) <= 128 * 1024; }
+bool jacobi_lds_fits(int m, int c) {
+    return m >= c && c <= 64 && m <= JG * JROWS && jacobi_lds_bytes(m, c) <= 128 * 1024;
+}
 
 void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st) {
     size_t i = 0;
@@ -372,6 +502,41 @@ void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st) {
         StatScope scope(TTSG_ST_SVD, flops, 0.0, st);
         allow_lds(reinterpret_cast<const void*>(&k_jacobi_lds), lds, g_lds_jacobi);
         hipLaunchKernelGGL(k_jacobi_lds, dim3(cnt), dim3(JT), lds, st, jb, 30, scope.slot());
+        TTSG_HIP(hipGetLastError());
+    }
+}
+
+size_t qr_small_lds_bytes(int m, int c) { return 2 * (size_t)(m | 1) * c * 8; }
+bool qr_small_fits(int m, int c) { return m >= c && c <= 64 && qr_small_lds_bytes(m, c) <= 140 * 1024; }
+
+void qr_small_batched(const std::vector<QrJob>& jobs, hipStream_t st) {
+    size_t i = 0;
+    while (i < jobs.size()) {
+        QrBatch jb{};
+        size_t lds = 0;
+        int cnt = 0;
+        double flops = 0.0;
+        for (; i < jobs.size() && cnt < 32; ++i, ++cnt) {
+            const QrJob& j = jobs[i];
+            TTSG_CHECK(qr_small_fits(j.m, j.c), TTSG_ERR_ARG, "qr job does not fit in LDS");
+            jb.m[cnt] = j.m;
+            jb.c[cnt] = j.c;
+            jb.lda[cnt] = j.lda;
+            jb.A[cnt] = j.A;
+            jb.Q[cnt] = j.Q;
+            jb.R[cnt] = j.R;
+            lds = std::max(lds, qr_small_lds_bytes(j.m, j.c));
+            flops += 4.0 * j.m * j.c * (double)j.c - 4.0 / 3.0 * j.c * (double)j.c * j.c;
+            if (bounds_checking()) {
+                check_range(j.A, ((int64_t)(j.c - 1) * j.lda + j.m) * 8, "qr_small A");
+                check_range(j.Q, (int64_t)j.m * j.c * 8, "qr_small Q");
+                check_range(j.R, (int64_t)j.c * j.c * 8, "qr_small R");
+            }
+        }
+        jb.count = cnt;
+        StatScope scope(TTSG_ST_QR, flops, 0.0, st);
+        allow_lds(reinterpret_cast<const void*>(&k_qr_small), lds, g_lds_small);
+        hipLaunchKernelGGL(k_qr_small, dim3(cnt), dim3(QT), lds, st, jb, scope.slot());
         TTSG_HIP(hipGetLastError());
     }
 }

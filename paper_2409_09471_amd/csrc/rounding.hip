@@ -403,7 +403,9 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
     std::vector<int*> permb(d);
     std::vector<double*> facb(d);
     std::vector<TsqrPlan> plans(d);
-    std::vector<bool> use_tsqr(d, false);
+    std::vector<bool> use_tsqr(d, false), use_small(d, false);
+    std::vector<double*> Rsm(d, nullptr);
+    std::vector<QrJob> qjobs;
     int64_t maxT = 1;
     for (int b = 1; b <= d - 1; ++b) {
         const int m = rho[b], c = rx[b];
@@ -418,8 +420,13 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         permb[b] = ar.get<int>(c);
         facb[b] = ar.get<double>(2 * (int64_t)c);
         transpose2d(m, c, Omega[b - 1], c, Ab[b], m, st);        // column-major m x c
-        use_tsqr[b] = tsqr_fits(m, c);
-        if (use_tsqr[b]) {
+        use_small[b] = qr_small_fits(m, c);
+        use_tsqr[b] = !use_small[b] && tsqr_fits(m, c);
+        if (use_small[b]) {
+            Qb[b] = ar.get<double>((int64_t)m * c);
+            Rsm[b] = ar.get<double>((int64_t)c * c);
+            qjobs.push_back(QrJob{m, c, m, Ab[b], Qb[b], Rsm[b]});
+        } else if (use_tsqr[b]) {
             plans[b].factor(m, c, Ab[b], m, ar, st);
             transpose2d(c, c, plans[b].R, c, Rt[b], c, st);       // R (column-major) -> R^T
         } else {
@@ -432,11 +439,20 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
             transpose2d(c, c, Rm, c, Rt[b], c, st);
         }
     }
+    // all small QRs of the bonds in one launch
+    if (!qjobs.empty()) {
+        qr_small_batched(qjobs, st);
+        for (int b = 1; b <= d - 1; ++b)
+            if (use_small[b]) transpose2d(rx[b], rx[b], Rsm[b], rx[b], Rt[b], rx[b], st);
+    }
     {
         std::vector<JacobiJob> jobs;
         for (int b = 1; b <= d - 1; ++b) {
+            // singular values below rcond * s_max are dropped, so rotations
+            // that leave 1e-3 rcond of non-orthogonality change nothing kept
+            const double jt = std::max(4.0 * rx[b] * 2.220446049250313e-16, 1e-3 * rcond);
             if (jacobi_lds_fits(rx[b], rx[b]))
-                jobs.push_back(JacobiJob{rx[b], rx[b], rx[b], Rt[b], Wb[b], Sb[b]});
+                jobs.push_back(JacobiJob{rx[b], rx[b], rx[b], Rt[b], Wb[b], Sb[b], jt});
             else
                 svd_jacobi(1, rx[b], rx[b], Rt[b], rx[b], 0, Wb[b], rx[b], 0, Sb[b], 0, st);
         }
@@ -473,7 +489,17 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         gather_cols(c, k, Rt[b], c, Vk[b], c, permb[b], facb[b], st);
         // G_b (row-major k x rho == column-major rho x k) = Q W[:, keep] / s
         gather_cols(c, k, Wb[b], c, Wk[b], c, permb[b], facb[b], st);
-        if (use_tsqr[b]) {
+        if (use_small[b]) {
+            // G_b (column-major m x k) = Q (column-major m x c) * W[:, keep] / s
+            ContractDesc dg = cdesc(m, k, c);
+            dg.am = idx1(1);
+            dg.ak = idx1(m);
+            dg.bk = idx1(1);
+            dg.bn = idx1(c);
+            dg.cm = idx1(1);
+            dg.cn = idx1(m);
+            contract(Prec::F64, dg, Qb[b], Wk[b], Gb[b], st, &ar);
+        } else if (use_tsqr[b]) {
             plans[b].apply(k, Wk[b], c, Gb[b], m, false, ar, st);
         } else {
             gemm_cm_cm(m, k, c, Qb[b], m, Wk[b], c, T, k, st, &ar);   // row-major m x k

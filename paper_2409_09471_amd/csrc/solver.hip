@@ -445,6 +445,10 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     so_op.R = in_.R;
     so_op.D = Dv;
     so_plain.R = R1;
+    // FP64 sketches of A x for the restart residual
+    SketchOperands so_op64 = so_plain;
+    so_op64.R = in_.R;
+    so_op64.D.assign(in_.A.begin(), in_.A.end());
 
     auto sk_ptrs = [&](double* base, std::vector<double*>& psi, std::vector<double*>& om) {
         psi.assign(d, nullptr);
@@ -502,15 +506,11 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     }
     const double Sb = std::sqrt(read(scal_));
 
-    // ---- buffers for A x, b - A x ----------------------------------------
-    std::vector<double*> G(d), Rsum(d);
-    {
-        for (int mu = 0; mu < d; ++mu) {
-            const int64_t nn = n[mu];
-            const int64_t gl = (int64_t)in_.R[mu] * in_.rx[mu], gr = (int64_t)in_.R[mu + 1] * in_.rx[mu + 1];
-            G[mu] = scratch_.get<double>(gl * nn * gr);
-            Rsum[mu] = scratch_.get<double>((gl + in_.rb[mu]) * nn * (gr + in_.rb[mu + 1]));
-        }
+    // ---- buffer for A x (true residual) -------------------------------------
+    std::vector<double*> G(d);
+    for (int mu = 0; mu < d; ++mu) {
+        const int64_t gl = (int64_t)in_.R[mu] * in_.rx[mu], gr = (int64_t)in_.R[mu + 1] * in_.rx[mu + 1];
+        G[mu] = scratch_.get<double>(gl * n[mu] * gr);
     }
     auto true_res = [&](const std::vector<int>& xr, const std::vector<double*>& xc) -> double {
         // ||b - A x||^2 = ||b||^2 - 2 <A x, b> + ||A x||^2  (FP64 throughout)
@@ -550,21 +550,31 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
                 copy_f64((int64_t)in_.rb[mu] * n[mu] * in_.rb[mu + 1], in_.b[mu], slots_[s0][mu], st_);
             beta = tt_norm_copy(slot_r_[s0], cvec(slots_[s0]));
         } else {
-            std::vector<int> gr(d + 1), rr;
-            for (int k = 0; k <= d; ++k) gr[k] = in_.R[k] * xcur_r_[k];
-            for (int mu = 0; mu < d; ++mu)
-                matvec_core(xcur_r_[mu], n[mu], xcur_r_[mu + 1], in_.R[mu], in_.R[mu + 1], in_.A[mu], xcur_[mu],
-                            false, G[mu], st_);
-            std::vector<double*> bb(in_.b.size());
-            for (int mu = 0; mu < d; ++mu) bb[mu] = const_cast<double*>(in_.b[mu]);
-            tt_add_block(d, n, in_.rb, bb, gr, cvec(G), -1.0, Rsum, rr, st_);
-            std::vector<int64_t> caps(d);
-            int cap = 0;
-            for (int k = 0; k <= d; ++k) cap = std::max(cap, in_.rx[k]);
-            tt_svd_inplace(d, n, rr, Rsum, caps, 1e-12, cap, scratch_, st_, nullptr);
-            slot_r_[s0] = rr;
-            for (int mu = 0; mu < d; ++mu)
-                copy_f64((int64_t)rr[mu] * n[mu] * rr[mu + 1], Rsum[mu], slots_[s0][mu], st_);
+            // r0 = b - A x by the method's randomized rounding: FP64 STTA
+            // sketches of b and of A x (operator fused, A x never formed) are
+            // subtracted, recovered at the STTA ranks and recompressed by TT-SVD
+            // at 1e-12 -- instead of a TT-SVD of the rank R r_x + r_b block sum.
+            {
+                std::vector<double*> pb, ob, pa, oa;
+                sk_ptrs(skA_, pb, ob);
+                sk_ptrs(skC_, pa, oa);
+                std::vector<const void*> b64(in_.b.begin(), in_.b.end()), x64(xcur_.begin(), xcur_.end());
+                stta_sketch(so_plain, in_.rb, b64, pb.data(), ob.data(), scratch_, st_);
+                stta_sketch(so_op64, xcur_r_, x64, pa.data(), oa.data(), scratch_, st_);
+                axpby(sk_len_, 1.0, skA_, -1.0, skC_, st_);      // skC = Psi(b) - Psi(A x)
+                std::vector<const double*> cpsi(pa.begin(), pa.end()), com(oa.begin(), oa.end());
+                // Psi(b) and Psi(A x) are O(||b||) while their difference is
+                // O(res ||b||): the difference carries FP64 rounding of relative
+                // size eps / res, and singular values of its Omega below that
+                // are noise that the pseudo-inverse must not amplify
+                const double rc = std::max(o.rcond, 64.0 * 2.220446049250313e-16 / std::max(last_true, 1e-300));
+                std::vector<int> rr;
+                stta_recover(d, n, in_.rho, in_.rx, cpsi, com, rc, slots_[s0], rr, scratch_, st_);
+                int cap = 0;
+                for (int k = 0; k <= d; ++k) cap = std::max(cap, in_.rx[k]);
+                tt_svd_inplace(d, n, rr, slots_[s0], cap_, 1e-12, cap, scratch_, st_, nullptr);
+                slot_r_[s0] = rr;
+            }
             beta = tt_norm_copy(slot_r_[s0], cvec(slots_[s0]));
         }
         if (beta == 0.0) {
@@ -585,6 +595,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
 
         int kk = 0;  // columns of W in this cycle
         bool breakdown = false;
+        std::vector<double> cyc_res;  // sketched residuals of this cycle
         for (int k = 0; k < m_ && total < maxit_; ++k) {
             const int vk = window.back();
             // 1) w_k = S A v_k
@@ -666,6 +677,16 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             }
             if (sres <= stop) break;
             if (k + 1 >= m_ || total >= maxit_) break;
+            // Low-precision sketches of A v_k put a floor under what one cycle can
+            // reach (about the working precision's rounding relative to the
+            // cycle's r0).  When the sketched residual has fallen by less than 20%
+            // over the last kStall iterations the cycle ends; the next one restarts
+            // from the FP64 residual b - A x (iterative refinement).
+            cyc_res.push_back(sres);
+            constexpr int kStall = 8;
+            if (p_ != Prec::F64 && (int)cyc_res.size() > kStall &&
+                sres > 0.8 * cyc_res[cyc_res.size() - 1 - kStall])
+                break;
             // 6) v_{k+1} and its sketch
             t1 = now();
             scale_f64((int64_t)slot_r_[fs][0] * n[0] * slot_r_[fs][1], 1.0 / h, slots_[fs][0], st_);

@@ -5,6 +5,7 @@
 // duration of a launch is therefore the time its kernel actually ran, not the
 // gap between host-side events (which would include submission latency
 // whenever the stream had drained).
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
@@ -21,7 +22,7 @@ struct Rec {
     int shp[5];
 };
 
-constexpr int64_t kSlots = 1 << 20;
+constexpr int64_t kSlots = 1 << 18;
 std::mutex g_mu;
 std::vector<Rec> g_recs;
 bool g_on = false;
@@ -105,14 +106,16 @@ int ttsg_stats_read(ttsg_stats* out) {
     FILE* log = (logp != nullptr && logp[0] != 0) ? std::fopen(logp, "a") : nullptr;
     for (const auto& r : ttsg::g_recs) {
         const ttsg::DevSlot& s = h[r.slot];
-        if (log != nullptr && s.end != 0 && s.start_inv != 0) {
-            const unsigned long long t0 = ~s.start_inv;
-            std::fprintf(log, "%d %d %d %d %d %d %.9f %.6e\n", r.cls, r.shp[0], r.shp[1], r.shp[2], r.shp[3], r.shp[4],
-                         s.end > t0 ? (double)(s.end - t0) / (1e3 * rate_khz) : 0.0, r.flops);
+        unsigned long long t0 = ~0ull, t1 = 0;
+        for (int l = 0; l < ttsg::kSlotLanes; ++l) {
+            if (s.start_inv[l] != 0) t0 = std::min(t0, ~s.start_inv[l]);
+            t1 = std::max(t1, s.end[l]);
         }
-        if (s.end == 0 || s.start_inv == 0) continue;      // launch without workgroups
-        const unsigned long long t0 = ~s.start_inv;
-        const double sec = s.end > t0 ? (double)(s.end - t0) / (1e3 * rate_khz) : 0.0;
+        if (t1 == 0 || t0 == ~0ull) continue;      // launch without workgroups
+        const double sec = t1 > t0 ? (double)(t1 - t0) / (1e3 * rate_khz) : 0.0;
+        if (log != nullptr)
+            std::fprintf(log, "%d %d %d %d %d %d %.9f %.6e %llu\n", r.cls, r.shp[0], r.shp[1], r.shp[2], r.shp[3],
+                         r.shp[4], sec, r.flops, (unsigned long long)s.aux);
         const int c = r.cls;
         out->launches[c] += 1;
         out->flops[c] += r.flops;

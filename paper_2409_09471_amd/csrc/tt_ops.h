@@ -105,6 +105,18 @@ bool jacobi_lds_fits(int m, int c);
 // One launch for up to 32 matrices (more are split into several launches).
 void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st);
 
+// Householder QR of several small column-major matrices in one launch (one
+// workgroup each, the matrix and Q in LDS): Q (m x c, column-major, ld m) and
+// R (c x c, column-major, ld c, zero below the diagonal).
+struct QrJob {
+    int m, c, lda;
+    const double* A;
+    double* Q;
+    double* R;
+};
+bool qr_small_fits(int m, int c);
+void qr_small_batched(const std::vector<QrJob>& jobs, hipStream_t st);
+
 bool tsqr_fits(int m, int c);
 // Tall-skinny QR of a column-major m x c matrix (m >= c, c <= 64) by a tree of
 // LDS Householder leaves.  factor() leaves R (c x c, column-major, ld c, zero

@@ -76,11 +76,15 @@ bool bounds_checking();
 // of the wall clock (so host gaps between launches are not counted), plus an
 // auxiliary maximum (e.g. Jacobi sweeps).  Kernels take the slot pointer
 // (nullptr when measurement is off) and call slot_begin / slot_end.
+// A launch's workgroups spread their atomics over kSlotLanes sub-slots (by
+// flat workgroup index, which also spreads them over the XCDs), so that a
+// launch of thousands of workgroups does not serialize on one address.
+constexpr int kSlotLanes = 8;
 struct DevSlot {
-    unsigned long long start_inv;   // max over workgroups of ~t_start
-    unsigned long long end;         // max over workgroups of t_end
+    unsigned long long start_inv[kSlotLanes];   // max over workgroups of ~t_start
+    unsigned long long end[kSlotLanes];         // max over workgroups of t_end
     unsigned long long aux;
-    unsigned long long pad;
+    unsigned long long pad[7];
 };
 bool stats_on();
 // Count one host-side event of class cls while measurement is on.
@@ -96,15 +100,18 @@ struct StatScope {
     int64_t rec_ = -1;
 };
 
+__device__ __forceinline__ int slot_lane() {
+    return (int)((blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)) & (kSlotLanes - 1));
+}
 __device__ __forceinline__ void slot_begin(DevSlot* s) {
-    if (s != nullptr && threadIdx.x == 0) atomicMax(&s->start_inv, ~(unsigned long long)wall_clock64());
+    if (s != nullptr && threadIdx.x == 0) atomicMax(&s->start_inv[slot_lane()], ~(unsigned long long)wall_clock64());
 }
 // Call from all threads of the workgroup (contains a barrier when s != nullptr).
 __device__ __forceinline__ void slot_end(DevSlot* s, unsigned long long aux = 0) {
     if (s == nullptr) return;
     __syncthreads();
     if (threadIdx.x == 0) {
-        atomicMax(&s->end, (unsigned long long)wall_clock64());
+        atomicMax(&s->end[slot_lane()], (unsigned long long)wall_clock64());
         if (aux) atomicMax(&s->aux, aux);
     }
 }
