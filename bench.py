@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="wall-clock budget of the oracle sample")
     ap.add_argument("--no-fp64-leg", action="store_true", help="skip timing the FP64 path beside the mixed one")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default contraction tiles (no tuned table, no tuning)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer with a plain device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -65,13 +67,16 @@ def solve(w, t, precision, phase_timing=False):
                              precision=precision, phase_timing=phase_timing)
 
 
-def timed_solves(w, t, precision, steps, warmup, measure=True):
+def timed_solves(w, t, precision, steps, warmup, measure=True, tune=False):
     """Wall-clock time of `steps` solves (measurement off), then (measure=True)
-    one more solve with the per-launch device timers on for the kernel figures."""
+    one more solve with the per-launch device timers on for the kernel figures.
+    With tune=True the first warmup solve runs with the tile autotuner on."""
     import torch
     from paper_2409_09471_amd import ttsg
     for i in range(warmup):
+        ttsg.autotune(tune and i == 0)
         r = solve(w, t, precision)
+        ttsg.autotune(False)
         print(f"# warmup {i}: its={r.iterations} true_res={r.true_residual:.3e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -116,6 +121,7 @@ def rounding_gflops(w, t):
 
 
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "contract_kernel_hbm_counters_convdiff_d10_n64.md")
+TILE_TABLE = os.path.join(ROOT, "paper_2409_09471_amd", "tiles_gfx950.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2409_09471_amd", "csrc", "contract.hip")
 
 
@@ -194,7 +200,15 @@ def main():
         del src, dst
     w, t = build_inputs("cuda:0")
     prec = ttsg.PREC_MIXED if args.precision == "mixed" else ttsg.PREC_F64
-    el, results, stats = timed_solves(w, t, prec, args.steps, args.warmup)
+    # contraction tiles: the committed table from the tile tuner, else tune
+    # during the first warmup solve
+    tune = False
+    if not args.no_autotune:
+        if os.path.exists(TILE_TABLE):
+            ttsg.autotune_load(TILE_TABLE)
+        else:
+            tune = True
+    el, results, stats = timed_solves(w, t, prec, args.steps, max(args.warmup, 1 if tune else 0), tune=tune)
     per = el / args.steps
     last = results[-1]
     converged = all(r.status == ttsg.OK for r in results)
@@ -228,7 +242,7 @@ def main():
                            "flop_per_launch": v["flops"] / v["launches"],
                            "avg_launch_us": v["seconds"] / v["launches"] * 1e6}
     if prec == ttsg.PREC_MIXED and not args.no_fp64_leg:
-        el64, res64, _ = timed_solves(w, t, ttsg.PREC_F64, 1, 0, measure=False)
+        el64, res64, _ = timed_solves(w, t, ttsg.PREC_F64, 1, 1 if tune else 0, measure=False, tune=tune)
         out["fp64_seconds"] = el64
         out["fp64_iterations"] = res64[-1].iterations
         out["fp64_true_residual"] = res64[-1].true_residual

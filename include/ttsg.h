@@ -267,6 +267,27 @@ int ttsg_tt_axpby(int32_t d, const int32_t* n, double alpha, const int32_t* rx, 
                   ttsg_stream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* Contraction tile autotuner.  Every contraction runs one of four tile      */
+/* variants of the matrix-core kernel (64x64, 32x64, 64x32 or 32x32 entries  */
+/* of C per workgroup); all of them sum in the same order, so the choice     */
+/* never changes a result bit.  While tuning is on, the first contraction of */
+/* each new shape class (precision; log2 of M, N, K and batch; split-K or    */
+/* not; which operands have unit-stride reductions) times the four variants */
+/* on that call's operands (output to a scratch buffer, one stream sync) and */
+/* keeps the fastest.  Untuned classes use 32-wide tiles along dimensions    */
+/* <= 32 and 64-wide ones otherwise.                                         */
+/* ------------------------------------------------------------------------- */
+/* on != 0 starts tuning new classes, 0 stops; returns the previous setting. */
+int ttsg_autotune(int32_t on);
+/* Write the table as text (one line per class); returns the entry count or  */
+/* -TTSG_ERR_ARG when the file cannot be written.                            */
+int ttsg_autotune_save(const char* path);
+/* Merge a saved table; returns the entries read or -TTSG_ERR_ARG.           */
+int ttsg_autotune_load(const char* path);
+/* Forget every tuned class; returns how many there were.                    */
+int ttsg_autotune_clear(void);
+
+/* ------------------------------------------------------------------------- */
 /* Measurement: per-kernel-class counters.  While enabled, every contraction */
 /* and factorization launch records on the GPU the wall-clock time at which  */
 /* its first workgroup started and its last one ended (one small device slot */

@@ -455,6 +455,24 @@ int ttsg_sgmres_solve(int32_t d, const int32_t* n, const int32_t* R, const doubl
     });
 }
 
+int ttsg_autotune(int32_t on) { return ttsg::autotune_set(on); }
+
+int ttsg_autotune_save(const char* path) {
+    if (path == nullptr) return -TTSG_ERR_ARG;
+    const int n = ttsg::autotune_save(path);
+    if (n < 0) set_err("autotune_save: cannot write the file");
+    return n < 0 ? -TTSG_ERR_ARG : n;
+}
+
+int ttsg_autotune_load(const char* path) {
+    if (path == nullptr) return -TTSG_ERR_ARG;
+    const int n = ttsg::autotune_load(path);
+    if (n < 0) set_err("autotune_load: cannot read the file");
+    return n < 0 ? -TTSG_ERR_ARG : n;
+}
+
+int ttsg_autotune_clear(void) { return ttsg::autotune_clear(); }
+
 int ttsg_sgmres_solve_batched(int32_t count, ttsg_system* sys, int32_t concurrency, ttsg_stream_t stream) {
     return guarded([&]() {
         TTSG_CHECK(count >= 0, TTSG_ERR_ARG, "batched: count < 0");

@@ -19,7 +19,10 @@
 // column (l % 16) of B for the k-group (l / 16); the accumulator of lane l holds
 // column (l % 16), rows given by Traits<T>::acc_row.
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 
 #include "ttsg_internal.h"
 
@@ -30,8 +33,7 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef short s4_t __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64;
-constexpr int BN = 64;
+constexpr int BM64 = 64;   // tile edge that the split-K decision is based on
 
 // float32 -> bfloat16 bits, round to nearest even (NaN stays a quiet NaN).
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
@@ -82,12 +84,12 @@ template <> struct Traits<Bf16> {
 // computed once per tile, so a slab costs one (k-fast) or PER (row-fast) index
 // evaluations.  fetch() issues the global loads of the next slab before the
 // matrix-core work on the current one, commit() writes them to LDS after it.
-template <typename T>
+template <typename T, int ROWS>
 struct SlabLoader {
     using in_t = typename Traits<T>::in_t;
     using lds_t = typename Traits<T>::lds_t;
     static constexpr int BK = Traits<T>::BK;
-    static constexpr int PER = BM * BK / 256;
+    static constexpr int PER = ROWS * BK / 256;
     const in_t* G;
     Idx2 kix;
     int kend;
@@ -111,7 +113,7 @@ struct SlabLoader {
                 ro[t] = gr < nrows ? idx_off(rowix, gr) : -1;
             }
         } else {
-            fixed = tid % BM;
+            fixed = tid % ROWS;
             const int gr = row0 + fixed;
             ro[0] = gr < nrows ? idx_off(rowix, gr) : -1;
 #pragma unroll
@@ -129,19 +131,19 @@ struct SlabLoader {
         } else {
 #pragma unroll
             for (int t = 0; t < PER; ++t) {
-                const int gk = k0 + tid / BM + (256 / BM) * t;
+                const int gk = k0 + tid / ROWS + (256 / ROWS) * t;
                 buf[t] = (gk < kend && ro[t] >= 0) ? G[ro[t] + idx_off(kix, gk)] : in_t(0);
             }
         }
     }
-    __device__ __forceinline__ void commit(lds_t (*S)[BM + 1]) const {
+    __device__ __forceinline__ void commit(lds_t (*S)[ROWS + 1]) const {
         const int tid = threadIdx.x;
         if (k_fast) {
 #pragma unroll
             for (int t = 0; t < PER; ++t) S[fixed][tid / BK + (256 / BK) * t] = Traits<T>::stage(buf[t]);
         } else {
 #pragma unroll
-            for (int t = 0; t < PER; ++t) S[tid / BM + (256 / BM) * t][fixed] = Traits<T>::stage(buf[t]);
+            for (int t = 0; t < PER; ++t) S[tid / ROWS + (256 / ROWS) * t][fixed] = Traits<T>::stage(buf[t]);
         }
     }
 };
@@ -156,7 +158,7 @@ __device__ __forceinline__ f4_t mfma(float a, float b, f4_t c) {
 // With splits > 1 every workgroup reduces one K-chunk of kchunk values and
 // writes its unscaled partial tile to part[split][batch][M][N]; a second
 // kernel sums the partials in a fixed order (deterministic) into C.
-template <typename T>
+template <typename T, int WM, int WN>
 __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typename Traits<T>::in_t* __restrict__ A,
                                                        const typename Traits<T>::in_t* __restrict__ B,
                                                        typename Traits<T>::out_t* __restrict__ C,
@@ -168,8 +170,9 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
     using lds_t = typename Traits<T>::lds_t;
     using out_t = typename Traits<T>::out_t;
     constexpr int BK = Traits<T>::BK;
-    __shared__ lds_t As[BK][BM + 1];
-    __shared__ lds_t Bs[BK][BN + 1];
+    constexpr int TM = 32 * WM, TN = 32 * WN;   // tile: 2 x 2 wavefronts of WM x WN MFMA blocks
+    __shared__ lds_t As[BK][TM + 1];
+    __shared__ lds_t Bs[BK][TN + 1];
 
     slot_begin(slot);
     const int zz = batch0 + blockIdx.z;
@@ -177,26 +180,27 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
     const int split = zz - bidx * splits;
     const int kbeg = split * kchunk;
     const int kend = min(d.K, kbeg + kchunk);
-    const int m0 = blockIdx.y * BM;
-    const int n0 = blockIdx.x * BN;
+    const int m0 = blockIdx.y * TM;
+    const int n0 = blockIdx.x * TN;
     const in_t* Ab = A + idx_off(d.ab, bidx);
     const in_t* Bb = B + idx_off(d.bb, bidx);
     out_t* Cb = C + idx_off(d.cb, bidx);
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int wm = (wave >> 1) * 32;
-    const int wn = (wave & 1) * 32;
+    const int wm = (wave >> 1) * 16 * WM;
+    const int wn = (wave & 1) * 16 * WN;
     const int lr = lane & 15;
     const int lg = lane >> 4;
 
-    acc4 acc[2][2];
+    acc4 acc[WM][WN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = acc4{0, 0, 0, 0};
+        for (int j = 0; j < WN; ++j) acc[i][j] = acc4{0, 0, 0, 0};
 
-    SlabLoader<T> la, lb;
+    SlabLoader<T, TM> la;
+    SlabLoader<T, TN> lb;
     la.init(Ab, d.am, d.ak, m0, d.M, kend, d.ak.s0 == 1);
     lb.init(Bb, d.bn, d.bk, n0, d.N, kend, d.bk.s0 == 1);
     if (kbeg < kend) {
@@ -215,33 +219,33 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
         if constexpr (sizeof(lds_t) == 2) {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 16) {
-                s4_t a[2], b[2];
+                s4_t a[WM], b[WN];
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < WM; ++i)
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        a[i][t] = (short)As[kk + 4 * lg + t][wm + 16 * i + lr];
-                        b[i][t] = (short)Bs[kk + 4 * lg + t][wn + 16 * i + lr];
-                    }
+                    for (int t = 0; t < 4; ++t) a[i][t] = (short)As[kk + 4 * lg + t][wm + 16 * i + lr];
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < WN; ++j)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j)
+                    for (int t = 0; t < 4; ++t) b[j][t] = (short)Bs[kk + 4 * lg + t][wn + 16 * j + lr];
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
             }
         } else {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
-                lds_t a[2], b[2];
+                lds_t a[WM], b[WN];
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    a[i] = As[kk + lg][wm + 16 * i + lr];
-                    b[i] = Bs[kk + lg][wn + 16 * i + lr];
-                }
+                for (int i = 0; i < WM; ++i) a[i] = As[kk + lg][wm + 16 * i + lr];
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < WN; ++j) b[j] = Bs[kk + lg][wn + 16 * j + lr];
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
             }
         }
         __syncthreads();
@@ -250,9 +254,9 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
     const out_t alpha = (out_t)d.alpha;
     const out_t beta = (out_t)d.beta;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < WN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int row = m0 + wm + 16 * i + Traits<T>::acc_row(lg, r);
@@ -313,6 +317,133 @@ void launch_reduce(const ContractDesc& d, int splits, const O* part, O* C, hipSt
     }
 }
 
+// ---------------------------------------------------------------------------
+// Tile variants and the autotuner.  Variant v runs WM x WN MFMA blocks per
+// wavefront: 0 = 64 x 64 tiles, 1 = 32 x 64, 2 = 64 x 32, 3 = 32 x 32 (M x N).
+// The tuner times every variant the first time a shape class is met while
+// tuning is on and keeps the fastest; the table can be saved and loaded.
+// ---------------------------------------------------------------------------
+constexpr int kVariants = 4;
+constexpr int kVarWM[kVariants] = {2, 1, 2, 1};
+constexpr int kVarWN[kVariants] = {2, 2, 1, 1};
+
+template <typename T, int WM, int WN>
+void run_tiles(const ContractDesc& d, const typename Traits<T>::in_t* A, const typename Traits<T>::in_t* B,
+               typename Traits<T>::out_t* C, int splits, int kchunk, hipStream_t st, Arena* ar, DevSlot* slot) {
+    using out_t = typename Traits<T>::out_t;
+    const int gx = (d.N + 32 * WN - 1) / (32 * WN);
+    const int gy = (d.M + 32 * WM - 1) / (32 * WM);
+    if (splits > 1) {
+        const size_t mark = ar->mark();
+        out_t* part = ar->get<out_t>((size_t)splits * d.batch * d.M * d.N);
+        hipLaunchKernelGGL((contract_kernel<T, WM, WN>), dim3(gx, gy, d.batch * splits), dim3(256), 0, st, d, A, B,
+                           C, 0, splits, kchunk, part, slot);
+        launch_reduce<out_t>(d, splits, part, C, st);
+        ar->release(mark);
+    } else {
+        for (int b0 = 0; b0 < d.batch; b0 += 65535) {
+            const int nb = d.batch - b0 < 65535 ? d.batch - b0 : 65535;
+            hipLaunchKernelGGL((contract_kernel<T, WM, WN>), dim3(gx, gy, nb), dim3(256), 0, st, d, A, B, C, b0, 1,
+                               d.K, static_cast<out_t*>(nullptr), slot);
+        }
+    }
+    TTSG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void run_variant(int v, const ContractDesc& d, const typename Traits<T>::in_t* A, const typename Traits<T>::in_t* B,
+                 typename Traits<T>::out_t* C, int splits, int kchunk, hipStream_t st, Arena* ar, DevSlot* slot) {
+    switch (v) {
+        case 1: run_tiles<T, 1, 2>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+        case 2: run_tiles<T, 2, 1>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+        case 3: run_tiles<T, 1, 1>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+        default: run_tiles<T, 2, 2>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+    }
+}
+
+// Without a tuned entry: the smallest tile that covers a dimension of <= 32.
+int default_variant(const ContractDesc& d) {
+    const bool sm = d.M <= 32, sn = d.N <= 32;
+    return sm && sn ? 3 : (sm ? 1 : (sn ? 2 : 0));
+}
+
+struct TuneKey {
+    int cls, lm, ln, lk, lb, split, afast, bfast;
+    bool operator<(const TuneKey& o) const {
+        const int a[8] = {cls, lm, ln, lk, lb, split, afast, bfast};
+        const int b[8] = {o.cls, o.lm, o.ln, o.lk, o.lb, o.split, o.afast, o.bfast};
+        for (int i = 0; i < 8; ++i)
+            if (a[i] != b[i]) return a[i] < b[i];
+        return false;
+    }
+};
+
+int ceil_log2(int64_t x) {
+    int l = 0;
+    while ((int64_t(1) << l) < x) ++l;
+    return l;
+}
+
+TuneKey tune_key(int cls, const ContractDesc& d, int splits) {
+    return TuneKey{cls, ceil_log2(d.M), ceil_log2(d.N), ceil_log2(d.K), ceil_log2(d.batch), splits > 1 ? 1 : 0,
+                   d.ak.s0 == 1 ? 1 : 0, d.bk.s0 == 1 ? 1 : 0};
+}
+
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+bool g_tune_on = false;
+
+int tuned_variant(const TuneKey& k) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(k);
+    return it == g_tune.end() ? -1 : it->second;
+}
+bool autotune_on() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune_on;
+}
+
+// Time every variant (three launches each, HIP events on the stream) with the
+// output redirected to a scratch buffer, record and return the fastest.
+template <typename T>
+int tune(const TuneKey& key, const ContractDesc& d, const void* A, const void* B, int splits, int kchunk,
+         hipStream_t st, Arena* ar) {
+    using in_t = typename Traits<T>::in_t;
+    using out_t = typename Traits<T>::out_t;
+    ContractDesc dc = d;
+    dc.beta = 0.0;
+    dc.cb = idx1((int64_t)d.M * d.N);
+    dc.cm = idx1(d.N);
+    dc.cn = idx1(1);
+    out_t* scratch = nullptr;
+    TTSG_HIP(hipMallocAsync(reinterpret_cast<void**>(&scratch), (size_t)d.batch * d.M * d.N * sizeof(out_t), st));
+    hipEvent_t ev[kVariants + 1];
+    for (auto& e : ev) TTSG_HIP(hipEventCreate(&e));
+    TTSG_HIP(hipEventRecord(ev[0], st));
+    for (int v = 0; v < kVariants; ++v) {
+        for (int rep = 0; rep < 3; ++rep)
+            run_variant<T>(v, dc, static_cast<const in_t*>(A), static_cast<const in_t*>(B), scratch, splits, kchunk,
+                           st, ar, nullptr);
+        TTSG_HIP(hipEventRecord(ev[v + 1], st));
+    }
+    TTSG_HIP(hipEventSynchronize(ev[kVariants]));
+    int best = 0;
+    float best_ms = 0.0f;
+    for (int v = 0; v < kVariants; ++v) {
+        float ms = 0.0f;
+        TTSG_HIP(hipEventElapsedTime(&ms, ev[v], ev[v + 1]));
+        if (v == 0 || ms < best_ms) {
+            best = v;
+            best_ms = ms;
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    TTSG_HIP(hipFreeAsync(scratch, st));
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+    return best;
+}
+
 template <typename T>
 void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st, Arena* ar) {
     if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
@@ -341,15 +472,14 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
     }
     StatScope scope(cls, flops, bytes, st);
     using out_t = typename Traits<T>::out_t;
-    dim3 block(256);
-    const int gx = (d.N + BN - 1) / BN;
-    const int gy = (d.M + BM - 1) / BM;
-    TTSG_CHECK(gy < 65536, TTSG_ERR_ARG, "contraction: M too large");
-    // split-K when the output tiles alone cannot fill the chip
+    // split-K when the output tiles alone cannot fill the chip (at least four
+    // k-slabs per split, at most 64 splits, about two workgroups per CU).  The
+    // decision uses 64 x 64 tiles whatever tile variant runs, so every variant
+    // sums in the same order and gives bit-identical results.
     constexpr int BK = Traits<T>::BK;
-    const int64_t wgs = (int64_t)gx * gy * d.batch;
-    // (at least four k-slabs per split, at most 64 splits, about two
-    // workgroups per CU in total)
+    const int64_t gx64 = (d.N + BM64 - 1) / BM64, gy64 = (d.M + BM64 - 1) / BM64;
+    TTSG_CHECK((d.M + 31) / 32 < 65536, TTSG_ERR_ARG, "contraction: M too large");
+    const int64_t wgs = gx64 * gy64 * d.batch;
     int splits = 1, kchunk = d.K;
     if (ar != nullptr && wgs < 512 && d.K >= 8 * BK) {
         int want = (int)std::min<int64_t>((512 + wgs - 1) / wgs, d.K / (4 * BK));
@@ -361,25 +491,12 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         }
     }
     scope.shape(d.M, d.N, d.K, d.batch, splits);
-    if (splits > 1) {
-        const size_t mark = ar->mark();
-        out_t* part = ar->get<out_t>((size_t)splits * d.batch * d.M * d.N);
-        const int zt = d.batch * splits;
-        hipLaunchKernelGGL(contract_kernel<T>, dim3(gx, gy, zt), block, 0, st, d, static_cast<const in_t*>(A),
-                           static_cast<const in_t*>(B), static_cast<out_t*>(C), 0, splits, kchunk, part,
-                           scope.slot());
-        launch_reduce<out_t>(d, splits, part, static_cast<out_t*>(C), st);
-        ar->release(mark);
-    } else {
-        for (int b0 = 0; b0 < d.batch; b0 += 65535) {
-            int nb = d.batch - b0 < 65535 ? d.batch - b0 : 65535;
-            dim3 grid(gx, gy, nb);
-            hipLaunchKernelGGL(contract_kernel<T>, grid, block, 0, st, d, static_cast<const in_t*>(A),
-                               static_cast<const in_t*>(B), static_cast<out_t*>(C), b0, 1, d.K,
-                               static_cast<out_t*>(nullptr), scope.slot());
-        }
-    }
-    TTSG_HIP(hipGetLastError());
+    const TuneKey key = tune_key(cls, d, splits);
+    int variant = tuned_variant(key);
+    if (variant < 0 && autotune_on()) variant = tune<T>(key, d, A, B, splits, kchunk, st, ar);
+    if (variant < 0) variant = default_variant(d);
+    run_variant<T>(variant, d, static_cast<const in_t*>(A), static_cast<const in_t*>(B), static_cast<out_t*>(C),
+                   splits, kchunk, st, ar, scope.slot());
 }
 
 }  // namespace
@@ -413,6 +530,54 @@ void contract(Prec p, const ContractDesc& d, const void* A, const void* B, void*
         case Prec::F32: launch<float>(d, A, B, C, st, ar); break;
         case Prec::BF16: launch<Bf16>(d, A, B, C, st, ar); break;
     }
+}
+
+int autotune_set(int on) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const int old = g_tune_on ? 1 : 0;
+    g_tune_on = on != 0;
+    return old;
+}
+
+int autotune_save(const char* path) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE* f = std::fopen(path, "w");
+    if (f == nullptr) return -1;
+    std::fprintf(f, "# ttsg contraction tile table: class log2M log2N log2K log2batch split afast bfast variant\n");
+    for (const auto& kv : g_tune) {
+        const TuneKey& k = kv.first;
+        std::fprintf(f, "%d %d %d %d %d %d %d %d %d\n", k.cls, k.lm, k.ln, k.lk, k.lb, k.split, k.afast, k.bfast,
+                     kv.second);
+    }
+    std::fclose(f);
+    return (int)g_tune.size();
+}
+
+int autotune_load(const char* path) {
+    FILE* f = std::fopen(path, "r");
+    if (f == nullptr) return -1;
+    std::map<TuneKey, int> t;
+    char line[256];
+    while (std::fgets(line, sizeof line, f) != nullptr) {
+        if (line[0] == '#') continue;
+        TuneKey k{};
+        int v = 0;
+        if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d", &k.cls, &k.lm, &k.ln, &k.lk, &k.lb, &k.split, &k.afast,
+                        &k.bfast, &v) == 9 &&
+            v >= 0 && v < kVariants)
+            t[k] = v;
+    }
+    std::fclose(f);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : t) g_tune[kv.first] = kv.second;
+    return (int)t.size();
+}
+
+int autotune_clear() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const int n = (int)g_tune.size();
+    g_tune.clear();
+    return n;
 }
 
 }  // namespace ttsg

@@ -651,7 +651,10 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             }
             add_phase(TTSG_PH_RECOVER, t1);
             t1 = now();
-            const double h = tt_svd_inplace(d, n, slot_r_[fs], slots_[fs], cap_, o.round_tol, o.maxrank, scratch_,
+            // bfloat16 sketches of A v_k err by about its unit roundoff (2^-8):
+            // directions below that are noise and are not kept in the basis
+            const double basis_tol = p_ == Prec::BF16 ? std::max(o.round_tol, 0.00390625) : o.round_tol;
+            const double h = tt_svd_inplace(d, n, slot_r_[fs], slots_[fs], cap_, basis_tol, o.maxrank, scratch_,
                                             st_, nullptr);
             add_phase(TTSG_PH_TTSVD, t1);
             TTSG_CHECK(std::isfinite(h), TTSG_ERR_NONFINITE, "non-finite basis vector");

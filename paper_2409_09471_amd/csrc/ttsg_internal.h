@@ -136,6 +136,11 @@ class Arena;
 // split over several workgroups (partials in the arena, summed in fixed order).
 void contract(Prec p, const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st,
               Arena* ar = nullptr);
+// Tile autotuner of the contraction kernel (contract.hip).
+int autotune_set(int on);
+int autotune_save(const char* path);
+int autotune_load(const char* path);
+int autotune_clear();
 
 // Element-wise helpers (misc.hip).
 void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);   // y = a x + b y

@@ -48,7 +48,8 @@ def lib():
 EXPORTED = [
     "ttsg_last_error", "ttsg_version", "ttsg_matvec", "ttsg_kr_sketch", "ttsg_stta_sketch",
     "ttsg_round_rand", "ttsg_round_svd", "ttsg_sgmres_solve", "ttsg_true_residual", "ttsg_dot",
-    "ttsg_sgmres_solve_batched", "ttsg_grad_kron_sum", "ttsg_tt_axpby", "ttsg_stats_enable", "ttsg_stats_read",
+    "ttsg_sgmres_solve_batched", "ttsg_autotune", "ttsg_autotune_save", "ttsg_autotune_load", "ttsg_autotune_clear",
+    "ttsg_grad_kron_sum", "ttsg_tt_axpby", "ttsg_stats_enable", "ttsg_stats_read",
 ]
 
 STAT_CLASSES = {0: "contract_f64", 1: "contract_f32", 2: "contract_bf16", 3: "qr", 4: "svd_jacobi",
@@ -58,6 +59,23 @@ STAT_CLASSES = {0: "contract_f64", 1: "contract_f32", 2: "contract_bf16", 3: "qr
 class Stats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 8), ("flops", ctypes.c_double * 8),
                 ("bytes", ctypes.c_double * 8), ("seconds", ctypes.c_double * 8)]
+
+
+def autotune(on: bool = True) -> bool:
+    """Start (or stop) timing the tile variants of new contraction shape classes."""
+    return bool(lib().ttsg_autotune(int(on)))
+
+
+def autotune_save(path: str) -> int:
+    return _check(lib().ttsg_autotune_save(os.fsencode(path)), "ttsg_autotune_save")
+
+
+def autotune_load(path: str) -> int:
+    return _check(lib().ttsg_autotune_load(os.fsencode(path)), "ttsg_autotune_load")
+
+
+def autotune_clear() -> int:
+    return lib().ttsg_autotune_clear()
 
 
 def stats_enable(on: bool = True) -> None:

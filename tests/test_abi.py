@@ -57,3 +57,20 @@ def test_argument_validation_without_gpu(lib):
     assert rc == -1
     lib.ttsg_last_error.restype = ctypes.c_char_p
     assert b"boundary ranks" in lib.ttsg_last_error()
+
+
+def test_autotune_table_round_trip(tmp_path):
+    """The tile table is host state: saving, clearing and loading it needs no GPU."""
+    from paper_2409_09471_amd import ttsg
+    ttsg.autotune_clear()
+    assert ttsg.autotune_save(str(tmp_path / "empty.txt")) == 0
+    table = tmp_path / "t.txt"
+    table.write_text("# comment\n0 6 6 12 0 1 1 0 3\n1 5 8 6 10 0 0 1 2\n0 1 1 1 1 0 0 0 9\n")
+    assert ttsg.autotune_load(str(table)) == 2          # the variant-9 line is rejected
+    out = tmp_path / "out.txt"
+    assert ttsg.autotune_save(str(out)) == 2
+    lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert sorted(lines) == sorted(["0 6 6 12 0 1 1 0 3", "1 5 8 6 10 0 0 1 2"])
+    assert ttsg.autotune_clear() == 2
+    with pytest.raises(ttsg.TTSGError):
+        ttsg.autotune_load(str(tmp_path / "missing.txt"))
