@@ -58,21 +58,7 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
             const double ajl = A[j][l];
             if (rg == 0) A[l][j] = ajl / rjj;
             const double f = ajl / p;
-            // all loads of the thread's rows first, then the stores: one LDS
-            // round trip per step instead of one per row
-            double rj[CQ_MAX / 4], al[CQ_MAX / 4];
-#pragma unroll
-            for (int t = 0; t < CQ_MAX / 4; ++t) {
-                const int i = j + 1 + rg + 4 * t;
-                const int ic = i <= l ? i : l;      // in-range index even where unused
-                rj[t] = i <= l ? A[j][ic] : 0.0;
-                al[t] = i <= l ? A[ic][l] : 0.0;
-            }
-#pragma unroll
-            for (int t = 0; t < CQ_MAX / 4; ++t) {
-                const int i = j + 1 + rg + 4 * t;
-                if (i <= l) A[i][l] = al[t] - rj[t] * f;
-            }
+            for (int i = j + 1 + rg; i <= l; i += 4) A[i][l] -= A[j][i] * f;
         }
         __syncthreads();
     }
@@ -96,19 +82,7 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
     for (int j = c - 1; j >= 1; --j) {
         if (l >= j && l < c) {
             const double rjl = A[j][l] / rd[j];
-            double rij[CQ_MAX / 4], acc[CQ_MAX / 4];
-#pragma unroll
-            for (int t = 0; t < CQ_MAX / 4; ++t) {
-                const int i = rg + 4 * t;
-                const int ic = i < j ? i : 0;       // in-range index even where unused
-                rij[t] = i < j ? A[j][ic] : 0.0;
-                acc[t] = i < j ? A[ic][l] : 0.0;
-            }
-#pragma unroll
-            for (int t = 0; t < CQ_MAX / 4; ++t) {
-                const int i = rg + 4 * t;
-                if (i < j) A[i][l] = acc[t] - rij[t] * rjl;
-            }
+            for (int i = rg; i < j; i += 4) A[i][l] -= A[j][i] * rjl;
         }
         __syncthreads();
     }

@@ -78,12 +78,30 @@ __device__ __forceinline__ double row_sum16(double v) {
     v += dpp_mov<0x140>(v);   // row_mirror
     return v;
 }
+
+// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
+// each (the estimates carry about half the double mantissa; each step doubles
+// the correct bits).  Shorter dependency chains than IEEE division and sqrt.
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    r = r * fma(-h, r * r, 1.5);
+    r = r * fma(-h, r * r, 1.5);
+    return r;
+}
 __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps, DevSlot* slot) {
     extern __shared__ double lds[];
     slot_begin(slot);
     int sweeps_done = 0;
     __shared__ short tab[2 * 32 * 63];      // (p, q) of pair k in round r, c <= 64
     __shared__ int s_rot;
+    __shared__ unsigned long long s_moff;
     const int bi = blockIdx.x;
     const int m = jb.m[bi], c = jb.c[bi], lda = jb.lda[bi];
     const double tol = jb.tol[bi];
@@ -123,6 +141,7 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
     __shared__ double s_fro;
     if (tid == 0) {
         s_rot = 0;
+        s_moff = 0ull;
         s_fro = 0.0;
     }
     __syncthreads();
@@ -144,6 +163,7 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
     const double tiny = nz * nz * s_fro;
     for (int sweep = 0; sweep < maxsweeps && cp > 1; ++sweep) {
         int rotated = 0;
+        double mo = 0.0;   // largest |cos| between a pair's columns met in this sweep
         sweeps_done = sweep + 1;
         for (int r = 0; r < nround; ++r) {
             for (int k = grp; k < npair; k += ngrp) {
@@ -171,10 +191,23 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
                 al = row_sum16(al);
                 be = row_sum16(be);
                 ga = row_sum16(ga);
-                if (al <= tiny || be <= tiny || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
-                const double zeta = (be - al) / (2.0 * ga);
-                const double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
-                const double cs = 1.0 / sqrt(1.0 + t * t);
+                if (al <= tiny || be <= tiny) continue;
+                const double off = fabs(ga) * rsq_nr(al) * rsq_nr(be);
+                mo = fmax(mo, off);
+                if (!(off > tol)) continue;
+                // rotation angle: t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+                // zeta = (be - al) / (2 ga); c = 1 / sqrt(1 + t^2), s = c t
+                const double zeta = (be - al) * rcp_nr(2.0 * ga);
+                const double az = fabs(zeta);
+                double t;
+                if (az < 1e150) {
+                    const double q = fma(zeta, zeta, 1.0);
+                    t = rcp_nr(az + q * rsq_nr(q));
+                } else {
+                    t = 0.5 * rcp_nr(az);
+                }
+                t = copysign(t, zeta);
+                const double cs = rsq_nr(fma(t, t, 1.0));
                 const double sn = cs * t;
 #pragma unroll
                 for (int u = 0; u < JROWS; ++u) {
@@ -184,23 +217,44 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
                         aq[i] = sn * xp[u] + cs * xq[u];
                     }
                 }
+                // V's pair of columns: all loads, then all stores (c <= 4 JG)
                 double* vp = V + p * ldv;
                 double* vq = V + q * ldv;
-                for (int i = lt; i < c; i += JG) {
-                    const double x = vp[i], y = vq[i];
-                    vp[i] = cs * x - sn * y;
-                    vq[i] = sn * x + cs * y;
+                double yp[4], yq[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = lt + u * JG;
+                    const int ic = i < c ? i : 0;   // in-range index even where unused
+                    yp[u] = i < c ? vp[ic] : 0.0;
+                    yq[u] = i < c ? vq[ic] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = lt + u * JG;
+                    if (i < c) {
+                        vp[i] = cs * yp[u] - sn * yq[u];
+                        vq[i] = sn * yp[u] + cs * yq[u];
+                    }
                 }
                 rotated = 1;
             }
             __syncthreads();
         }
         if (rotated && lt == 0) s_rot = 1;
+        // non-negative doubles order like their bit patterns
+        if (lt == 0 && mo > 0.0) atomicMax(&s_moff, (unsigned long long)__double_as_longlong(mo));
         __syncthreads();
-        const int any = s_rot;      // every thread reads the flag ...
-        __syncthreads();            // ... before thread 0 clears it for the next sweep
-        if (tid == 0) s_rot = 0;
-        if (any == 0) break;
+        const int any = s_rot;      // every thread reads the flags ...
+        const double moff = __longlong_as_double((long long)s_moff);
+        __syncthreads();            // ... before thread 0 clears them for the next sweep
+        if (tid == 0) {
+            s_rot = 0;
+            s_moff = 0ull;
+        }
+        // Jacobi converges quadratically near the end: a sweep that started
+        // with every |cos| below sqrt(tol) / 10 leaves them near tol, so the
+        // confirming sweep without rotations is skipped
+        if (any == 0 || moff < 0.1 * sqrt(tol)) break;
     }
     __syncthreads();
     for (int e = tid; e < m * c; e += blockDim.x) {

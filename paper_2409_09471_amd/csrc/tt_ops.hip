@@ -185,10 +185,45 @@ void kr_precompute(Prec p, int s, int n, int Rl, int Rr, const void* S, const vo
     contract(p, d, S, D, SA, st);
 }
 
+namespace {
+// KR1 with a short operator-rank sum (Rl <= 4): one thread per output entry,
+// the Rl products summed in order -- a streaming write of s Rr rl n values.
+template <typename T>
+__global__ void k_kr1(int64_t total, int rl, int n, int Rl, int Rr, const T* __restrict__ P,
+                      const T* __restrict__ SA, T* __restrict__ X) {
+    const int64_t per_j = (int64_t)Rr * rl * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / per_j;
+        int64_t rem = e - j * per_j;
+        const int be = (int)(rem / ((int64_t)rl * n));
+        rem -= (int64_t)be * rl * n;
+        const int a = (int)(rem / n);
+        const int i = (int)(rem - (int64_t)a * n);
+        const T* pj = P + j * Rl * rl + a;
+        const T* sj = SA + ((j * Rl) * n + i) * Rr + be;
+        T acc = 0;
+        for (int al = 0; al < Rl; ++al) acc += pj[(int64_t)al * rl] * sj[(int64_t)al * n * Rr];
+        X[e] = acc;
+    }
+}
+}  // namespace
+
 void kr_step(Prec p, int s, int rl, int n, int rr, int Rl, int Rr, const void* P, const void* SA, const void* C,
              void* Xbuf, void* Pout, hipStream_t st, Arena* ar) {
     // KR1: X[j][be][a][i'] = sum_al P[j][al][a] SA[j][al][i'][be]
-    {
+    if (Rl <= 4 && p != Prec::BF16) {
+        const int64_t total = (int64_t)s * Rr * rl * n;
+        const int blocks = (int)std::min<int64_t>((total + 255) / 256, 1 << 16);
+        if (p == Prec::F64)
+            hipLaunchKernelGGL(k_kr1<double>, dim3(blocks), dim3(256), 0, st, total, rl, n, Rl, Rr,
+                               static_cast<const double*>(P), static_cast<const double*>(SA),
+                               static_cast<double*>(Xbuf));
+        else
+            hipLaunchKernelGGL(k_kr1<float>, dim3(blocks), dim3(256), 0, st, total, rl, n, Rl, Rr,
+                               static_cast<const float*>(P), static_cast<const float*>(SA), static_cast<float*>(Xbuf));
+        TTSG_HIP(hipGetLastError());
+    } else {
         ContractDesc d = cdesc(rl, Rr * n, Rl, s);
         d.ab = idx1((int64_t)Rl * rl);
         d.am = idx1(1);
