@@ -59,7 +59,7 @@ template <int G> __device__ __forceinline__ double gsum(double v) {
 // registers, and rotates the same rows, so a round of the circle method costs
 // a single barrier.  The pairs of every round come from a table built once.
 constexpr int JG = 16;
-constexpr int JROWS = 8;   // rows of a column held per lane: m <= JG * JROWS
+constexpr int JROWS = 8;   // rows of a column held per lane: m <= JG * JROWS (kernel JR <= JROWS)
 
 // Data-parallel-primitive move of a double within a row of 16 lanes.
 template <int CTRL> __device__ __forceinline__ double dpp_mov(double v) {
@@ -95,6 +95,7 @@ __device__ __forceinline__ double rsq_nr(double x) {
     r = r * fma(-h, r * r, 1.5);
     return r;
 }
+template <int JR>
 __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps, DevSlot* slot) {
     extern __shared__ double lds[];
     slot_begin(slot);
@@ -161,9 +162,10 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
     // so they are treated as converged
     const double nz = 2.0 * m * 2.220446049250313e-16;
     const double tiny = nz * nz * s_fro;
+    const double tol2 = tol * tol;
     for (int sweep = 0; sweep < maxsweeps && cp > 1; ++sweep) {
         int rotated = 0;
-        double mo = 0.0;   // largest |cos| between a pair's columns met in this sweep
+        double mo2 = 0.0;   // largest squared |cos| between a pair's columns met in this sweep
         sweeps_done = sweep + 1;
         for (int r = 0; r < nround; ++r) {
             for (int k = grp; k < npair; k += ngrp) {
@@ -172,11 +174,11 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
                 double* ap = A + p * ldm;
                 double* aq = A + q * ldm;
                 // the pair's rows stay in registers between the dot products
-                // and the rotation (m <= JG * JROWS)
-                double xp[JROWS], xq[JROWS];
+                // and the rotation (m <= JG * JR)
+                double xp[JR], xq[JR];
                 double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-                for (int t = 0; t < JROWS; ++t) {
+                for (int t = 0; t < JR; ++t) {
                     const int i = lt + t * JG;
                     xp[t] = 0.0;
                     xq[t] = 0.0;
@@ -192,25 +194,20 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
                 be = row_sum16(be);
                 ga = row_sum16(ga);
                 if (al <= tiny || be <= tiny) continue;
-                const double off = fabs(ga) * rsq_nr(al) * rsq_nr(be);
-                mo = fmax(mo, off);
-                if (!(off > tol)) continue;
-                // rotation angle: t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
-                // zeta = (be - al) / (2 ga); c = 1 / sqrt(1 + t^2), s = c t
-                const double zeta = (be - al) * rcp_nr(2.0 * ga);
-                const double az = fabs(zeta);
-                double t;
-                if (az < 1e150) {
-                    const double q = fma(zeta, zeta, 1.0);
-                    t = rcp_nr(az + q * rsq_nr(q));
-                } else {
-                    t = 0.5 * rcp_nr(az);
-                }
-                t = copysign(t, zeta);
+                const double g2 = ga * ga, ab = al * be;
+                mo2 = fmax(mo2, g2 * rcp_nr(ab));    // squared |cos| (off the rotation's path)
+                if (!(g2 > tol2 * ab)) continue;
+                // rotation angle: with dd = be - al, t = tan(theta) =
+                // 2 ga sign(dd) / (|dd| + sqrt(dd^2 + 4 ga^2)) (the smaller root of
+                // t^2 + (dd / ga) t - 1 = 0); c = 1 / sqrt(1 + t^2), s = c t
+                const double dd = be - al;
+                const double qq = fma(dd, dd, 4.0 * g2);
+                double t = 2.0 * ga * rcp_nr(fabs(dd) + qq * rsq_nr(qq));
+                if (dd < 0.0) t = -t;
                 const double cs = rsq_nr(fma(t, t, 1.0));
                 const double sn = cs * t;
 #pragma unroll
-                for (int u = 0; u < JROWS; ++u) {
+                for (int u = 0; u < JR; ++u) {
                     const int i = lt + u * JG;
                     if (i < m) {
                         ap[i] = cs * xp[u] - sn * xq[u];
@@ -242,7 +239,7 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
         }
         if (rotated && lt == 0) s_rot = 1;
         // non-negative doubles order like their bit patterns
-        if (lt == 0 && mo > 0.0) atomicMax(&s_moff, (unsigned long long)__double_as_longlong(mo));
+        if (lt == 0 && mo2 > 0.0) atomicMax(&s_moff, (unsigned long long)__double_as_longlong(mo2));
         __syncthreads();
         const int any = s_rot;      // every thread reads the flags ...
         const double moff = __longlong_as_double((long long)s_moff);
@@ -253,8 +250,8 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
         }
         // Jacobi converges quadratically near the end: a sweep that started
         // with every |cos| below sqrt(tol) / 10 leaves them near tol, so the
-        // confirming sweep without rotations is skipped
-        if (any == 0 || moff < 0.1 * sqrt(tol)) break;
+        // confirming sweep without rotations is skipped (moff is squared)
+        if (any == 0 || moff < 0.01 * tol) break;
     }
     __syncthreads();
     for (int e = tid; e < m * c; e += blockDim.x) {
@@ -410,6 +407,7 @@ struct QrBatch {
     const double* A[32];
     double* Q[32];
     double* R[32];
+    int* perm[32];   // nullptr: no column pivoting
 };
 
 // Householder QR of one small matrix per workgroup with the explicit Q:
@@ -420,8 +418,12 @@ __global__ __launch_bounds__(QT) void k_qr_small(QrBatch jb, DevSlot* slot) {
     extern __shared__ double lds[];
     slot_begin(slot);
     __shared__ double s_tau[64];
+    __shared__ double s_cn[64];    // squared norms of the columns' rows not yet factored
+    __shared__ int s_perm[64];
+    __shared__ int s_piv;
     const int bi = blockIdx.x;
     const int rows = jb.m[bi], c = jb.c[bi], lda = jb.lda[bi];
+    const bool pivot = jb.perm[bi] != nullptr;
     const double* Ag = jb.A[bi];
     const int ldt = rows | 1;
     double* T = lds;
@@ -435,9 +437,54 @@ __global__ __launch_bounds__(QT) void k_qr_small(QrBatch jb, DevSlot* slot) {
         X[j * ldt + r] = (r == j) ? 1.0 : 0.0;
     }
     __syncthreads();
+    if (pivot) {
+        for (int l = grp; l < c; l += ngrp) {
+            double s2 = 0.0;
+            for (int r = lt; r < rows; r += QG) s2 += T[l * ldt + r] * T[l * ldt + r];
+            s2 = gsum<QG>(s2);
+            if (lt == 0) s_cn[l] = s2;
+        }
+        for (int l = tid; l < c; l += blockDim.x) s_perm[l] = l;
+        __syncthreads();
+    }
     const int kk = rows < c ? rows : c;
     for (int j = 0; j < kk; ++j) {
         double* col = T + j * ldt;
+        if (pivot) {
+            // column pivoting: bring the column with the largest remaining norm to j
+            if (wave == 0) {
+                double v = (lane >= j && lane < c) ? s_cn[lane] : -1.0;
+                int idx = lane;
+                for (int o = 32; o > 0; o >>= 1) {
+                    const double v2 = __shfl_xor(v, o, 64);
+                    const int i2 = __shfl_xor(idx, o, 64);
+                    if (v2 > v || (v2 == v && i2 < idx)) {
+                        v = v2;
+                        idx = i2;
+                    }
+                }
+                if (lane == 0) s_piv = idx;
+            }
+            __syncthreads();
+            const int pj = s_piv;
+            if (pj != j) {
+                double* cp = T + pj * ldt;
+                for (int r = tid; r < rows; r += blockDim.x) {
+                    const double a = col[r];
+                    col[r] = cp[r];
+                    cp[r] = a;
+                }
+                if (tid == 0) {
+                    const double a = s_cn[j];
+                    s_cn[j] = s_cn[pj];
+                    s_cn[pj] = a;
+                    const int b = s_perm[j];
+                    s_perm[j] = s_perm[pj];
+                    s_perm[pj] = b;
+                }
+            }
+            __syncthreads();
+        }
         if (wave == 0) {
             double sacc = 0.0;
             for (int r = j + 1 + lane; r < rows; r += 64) sacc += col[r] * col[r];
@@ -457,15 +504,22 @@ __global__ __launch_bounds__(QT) void k_qr_small(QrBatch jb, DevSlot* slot) {
         }
         __syncthreads();
         const double t = s_tau[j];
-        if (t != 0.0) {
-            for (int l = j + 1 + grp; l < c; l += ngrp) {
-                double* cl = T + l * ldt;
+        for (int l = j + 1 + grp; l < c; l += ngrp) {
+            double* cl = T + l * ldt;
+            if (t != 0.0) {
                 double w = 0.0;
                 for (int r = j + 1 + lt; r < rows; r += QG) w += col[r] * cl[r];
                 w = gsum<QG>(w);
                 w = t * (w + cl[j]);
                 if (lt == 0) cl[j] -= w;
                 for (int r = j + 1 + lt; r < rows; r += QG) cl[r] -= w * col[r];
+            }
+            if (pivot) {
+                // norm of the rows below j, recomputed (no downdating)
+                double s2 = 0.0;
+                for (int r = j + 1 + lt; r < rows; r += QG) s2 += cl[r] * cl[r];
+                s2 = gsum<QG>(s2);
+                if (lt == 0) s_cn[l] = s2;
             }
         }
         __syncthreads();
@@ -497,6 +551,8 @@ __global__ __launch_bounds__(QT) void k_qr_small(QrBatch jb, DevSlot* slot) {
         const int j = e / c, r = e - j * c;
         Rg[(int64_t)j * c + r] = (r <= j && r < kk) ? T[j * ldt + r] : 0.0;
     }
+    if (pivot)
+        for (int l = tid; l < c; l += blockDim.x) jb.perm[bi][l] = s_perm[l];
     slot_end(slot);
 }
 
@@ -509,7 +565,7 @@ void allow_lds(const void* fn, size_t bytes, size_t& granted) {
     TTSG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     granted = bytes;
 }
-size_t g_lds_jacobi = 0, g_lds_leaf = 0, g_lds_apply = 0, g_lds_small = 0;
+size_t g_lds_jacobi = 0, g_lds_jacobi4 = 0, g_lds_leaf = 0, g_lds_apply = 0, g_lds_small = 0;
 
 int choose_leaves(int m, int c) {
     int nl = (m + LEAF - 1) / LEAF;
@@ -531,7 +587,7 @@ void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st) {
     while (i < jobs.size()) {
         JacobiBatch jb{};
         size_t lds = 0;
-        int cnt = 0;
+        int cnt = 0, mmax = 0;
         double flops = 0.0;
         for (; i < jobs.size() && cnt < 32; ++i, ++cnt) {
             const JacobiJob& j = jobs[i];
@@ -545,6 +601,7 @@ void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st) {
             // below m eps a computed dot product is rounding noise
             jb.tol[cnt] = j.tol > 0.0 ? j.tol : 4.0 * j.m * 2.220446049250313e-16;
             lds = std::max(lds, jacobi_lds_bytes(j.m, j.c));
+            mmax = std::max(mmax, j.m);
             flops += 0.5 * j.c * (j.c - 1.0) * (12.0 * j.m + 6.0 * j.c);
             if (bounds_checking()) {
                 check_range(j.A, ((int64_t)(j.c - 1) * j.lda + j.m) * 8, "jacobi_lds A");
@@ -554,8 +611,14 @@ void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st) {
         }
         jb.count = cnt;
         StatScope scope(TTSG_ST_SVD, flops, 0.0, st);
-        allow_lds(reinterpret_cast<const void*>(&k_jacobi_lds), lds, g_lds_jacobi);
-        hipLaunchKernelGGL(k_jacobi_lds, dim3(cnt), dim3(JT), lds, st, jb, 30, scope.slot());
+        // four register rows per lane cover every matrix of up to 64 rows
+        if (mmax <= 4 * JG) {
+            allow_lds(reinterpret_cast<const void*>(&k_jacobi_lds<4>), lds, g_lds_jacobi4);
+            hipLaunchKernelGGL(k_jacobi_lds<4>, dim3(cnt), dim3(JT), lds, st, jb, 30, scope.slot());
+        } else {
+            allow_lds(reinterpret_cast<const void*>(&k_jacobi_lds<JROWS>), lds, g_lds_jacobi);
+            hipLaunchKernelGGL(k_jacobi_lds<JROWS>, dim3(cnt), dim3(JT), lds, st, jb, 30, scope.slot());
+        }
         TTSG_HIP(hipGetLastError());
     }
 }
@@ -579,6 +642,7 @@ void qr_small_batched(const std::vector<QrJob>& jobs, hipStream_t st) {
             jb.A[cnt] = j.A;
             jb.Q[cnt] = j.Q;
             jb.R[cnt] = j.R;
+            jb.perm[cnt] = j.perm;
             lds = std::max(lds, qr_small_lds_bytes(j.m, j.c));
             flops += 4.0 * j.m * j.c * (double)j.c - 4.0 / 3.0 * j.c * (double)j.c * j.c;
             if (bounds_checking()) {

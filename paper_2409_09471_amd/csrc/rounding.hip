@@ -30,6 +30,18 @@ __global__ void k_gather_cols(int rows, int k, const double* __restrict__ src, i
     }
 }
 
+// Column t, row i of dst = fac[t] * src[perm[t]][i], written to row rowperm[i]
+// (the row permutation of a column-pivoted QR).
+__global__ void k_gather_cols_rows(int rows, int k, const double* __restrict__ src, int lds,
+                                   double* __restrict__ dst, int ldd, const int* __restrict__ perm,
+                                   const double* __restrict__ fac, const int* __restrict__ rowperm) {
+    int total = rows * k;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        int t = e / rows, i = e - t * rows;
+        dst[(int64_t)t * ldd + rowperm[i]] = fac[t] * src[(int64_t)perm[t] * lds + i];
+    }
+}
+
 __global__ void k_eye(int c, double* __restrict__ I) {
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < c * c; e += gridDim.x * blockDim.x)
         I[e] = (e / c == e % c) ? 1.0 : 0.0;
@@ -405,6 +417,7 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
     std::vector<TsqrPlan> plans(d);
     std::vector<bool> use_tsqr(d, false), use_small(d, false);
     std::vector<double*> Rsm(d, nullptr);
+    std::vector<int*> pivb(d, nullptr);
     std::vector<QrJob> qjobs;
     int64_t maxT = 1;
     for (int b = 1; b <= d - 1; ++b) {
@@ -423,9 +436,12 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         use_small[b] = qr_small_fits(m, c);
         use_tsqr[b] = !use_small[b] && tsqr_fits(m, c);
         if (use_small[b]) {
+            // column-pivoted: R^T is then graded and the Jacobi SVD below
+            // converges in fewer sweeps
             Qb[b] = ar.get<double>((int64_t)m * c);
             Rsm[b] = ar.get<double>((int64_t)c * c);
-            qjobs.push_back(QrJob{m, c, m, Ab[b], Qb[b], Rsm[b]});
+            pivb[b] = ar.get<int>(c);
+            qjobs.push_back(QrJob{m, c, m, Ab[b], Qb[b], Rsm[b], pivb[b]});
         } else if (use_tsqr[b]) {
             plans[b].factor(m, c, Ab[b], m, ar, st);
             transpose2d(c, c, plans[b].R, c, Rt[b], c, st);       // R (column-major) -> R^T
@@ -486,7 +502,14 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         TTSG_HIP(hipMemcpyAsync(facb[b], facs[b].data(), k * sizeof(double), hipMemcpyHostToDevice, st));
         const int m = rho[b], c = rx[b];
         // V'_b (column-major rx x k) = U_B[:, keep] = (U_B S)[:, keep] / s
-        gather_cols(c, k, Rt[b], c, Vk[b], c, permb[b], facb[b], st);
+        if (pivb[b] != nullptr) {
+            // Omega P = Q R: the right factor is P U_B, rows of U_B scattered by P
+            hipLaunchKernelGGL(k_gather_cols_rows, dim3(nb((int64_t)c * k)), dim3(256), 0, st, c, k, Rt[b], c,
+                               Vk[b], c, permb[b], facb[b], pivb[b]);
+            TTSG_HIP(hipGetLastError());
+        } else {
+            gather_cols(c, k, Rt[b], c, Vk[b], c, permb[b], facb[b], st);
+        }
         // G_b (row-major k x rho == column-major rho x k) = Q W[:, keep] / s
         gather_cols(c, k, Wb[b], c, Wk[b], c, permb[b], facb[b], st);
         if (use_small[b]) {

@@ -107,12 +107,15 @@ void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st);
 
 // Householder QR of several small column-major matrices in one launch (one
 // workgroup each, the matrix and Q in LDS): Q (m x c, column-major, ld m) and
-// R (c x c, column-major, ld c, zero below the diagonal).
+// R (c x c, column-major, ld c, zero below the diagonal).  With perm != nullptr
+// the columns are pivoted (largest remaining norm first): A P = Q R, column l
+// of A P being column perm[l] of A.
 struct QrJob {
     int m, c, lda;
     const double* A;
     double* Q;
     double* R;
+    int* perm = nullptr;
 };
 bool qr_small_fits(int m, int c);
 void qr_small_batched(const std::vector<QrJob>& jobs, hipStream_t st);
