@@ -18,7 +18,8 @@
 namespace ttsg {
 namespace {
 
-constexpr int CQ_T = 256;
+constexpr int CQ_T = 1024;
+constexpr int CQ_RG = CQ_T / 64;   // row groups: thread (rg, l) owns column l, rows = rg mod CQ_RG
 constexpr int CQ_MAX = 64;
 
 // Cholesky of the c x c symmetric G (column-major) into upper R (G = R^T R),
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
     // Right-looking Cholesky on the upper triangle.  Step j reads row j and
     // writes the scaled row as R^T into the (unused) lower triangle and the
     // rank-1 update into rows > j, so one barrier per step suffices.  Thread
-    // (rg, l) owns column l and every fourth row of the update.
+    // (rg, l) owns column l and every CQ_RG-th row of the update.
     const int l = tid & 63, rg = tid >> 6;
     for (int j = 0; j < c; ++j) {
         double p = A[j][j];
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
             const double ajl = A[j][l];
             if (rg == 0) A[l][j] = ajl / rjj;
             const double f = ajl / p;
-            for (int i = j + 1 + rg; i <= l; i += 4) A[i][l] -= A[j][i] * f;
+            for (int i = j + 1 + rg; i <= l; i += CQ_RG) A[i][l] -= A[j][i] * f;
         }
         __syncthreads();
     }
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
     for (int j = c - 1; j >= 1; --j) {
         if (l >= j && l < c) {
             const double rjl = A[j][l] / rd[j];
-            for (int i = rg; i < j; i += 4) A[i][l] -= A[j][i] * rjl;
+            for (int i = rg; i < j; i += CQ_RG) A[i][l] -= A[j][i] * rjl;
         }
         __syncthreads();
     }
