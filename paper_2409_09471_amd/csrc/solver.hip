@@ -190,7 +190,7 @@ class SgmresSolver {
         Arena ar;
         ar.measure();
         carve(ar);
-        return ar.used() + scratch_bytes() + (64u << 20);
+        return ar.used() + 3 * scratch_bytes() + (64u << 20);
     }
 
     int run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info, void* ws, size_t ws_bytes);
@@ -228,7 +228,9 @@ class SgmresSolver {
     std::vector<int> xcur_r_;
     double* scal_ = nullptr;
     int* flag_ = nullptr;
-    Arena scratch_;
+    Arena scratch_;    // main stream
+    Arena scratchK_;   // side stream K: Khatri-Rao column + least squares
+    Arena scratchH_;   // side stream H: sketch of v_k + coefficients h
 
     size_t scratch_bytes() const;
     void carve(Arena& ar);
@@ -380,13 +382,40 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     carve(meas);
     const size_t fixed = meas.used();
     const size_t scr = scratch_bytes();
-    Workspace wsp(ws, ws_bytes, fixed + scr + 4096, st_);
+    Workspace wsp(ws, ws_bytes, fixed + 3 * scr + 3 * 4096, st_);
     carve(wsp.arena);
     scratch_.reset(wsp.arena.get<char>(scr), scr);
+    scratchK_.reset(wsp.arena.get<char>(scr), scr);
+    scratchH_.reset(wsp.arena.get<char>(scr), scr);
+
+    // Within an iteration the Khatri-Rao column of A v_k (with the least-squares
+    // update) and the sketch of v_k plus the coefficients h do not depend on the
+    // STTA sketch of A v_k: they run on two side streams (default priority)
+    // while the main stream sketches A v_k, each with its own scratch.
+    struct SideStreams {
+        hipStream_t k = nullptr, h = nullptr;
+        hipEvent_t v = nullptr, hd = nullptr;
+        ~SideStreams() {
+            if (k) (void)hipStreamSynchronize(k);
+            if (h) (void)hipStreamSynchronize(h);
+            if (v) (void)hipEventDestroy(v);
+            if (hd) (void)hipEventDestroy(hd);
+            if (k) (void)hipStreamDestroy(k);
+            if (h) (void)hipStreamDestroy(h);
+        }
+    } side;
+    TTSG_HIP(hipStreamCreateWithFlags(&side.k, hipStreamNonBlocking));
+    TTSG_HIP(hipStreamCreateWithFlags(&side.h, hipStreamNonBlocking));
+    TTSG_HIP(hipEventCreateWithFlags(&side.v, hipEventDisableTiming));
+    TTSG_HIP(hipEventCreateWithFlags(&side.hd, hipEventDisableTiming));
 
     const bool timing = info && info->phase_seconds;
     auto now = [&]() {
-        if (timing) TTSG_HIP(hipStreamSynchronize(st_));
+        if (timing) {
+            TTSG_HIP(hipStreamSynchronize(st_));
+            TTSG_HIP(hipStreamSynchronize(side.k));
+            TTSG_HIP(hipStreamSynchronize(side.h));
+        }
         return clock::now();
     };
     auto add_phase = [&](int ph, clock::time_point t0) {
@@ -456,11 +485,11 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         for (int mu = 0; mu < d; ++mu) psi[mu] = base + psi_off_[mu];
         for (int b = 1; b < d; ++b) om[b - 1] = base + om_off_[b];
     };
-    auto sketch_slot = [&](int slot, double* out) {
+    auto sketch_slot = [&](int slot, double* out, Arena& ar, hipStream_t stream) {
         std::vector<double*> psi, om;
         sk_ptrs(out, psi, om);
         std::vector<const void*> c64(slots_[slot].begin(), slots_[slot].end());
-        stta_sketch(so_plain, slot_r_[slot], c64, psi.data(), om.data(), scratch_, st_);
+        stta_sketch(so_plain, slot_r_[slot], c64, psi.data(), om.data(), ar, stream);
     };
     auto read = [&](const double* dev) {
         double h = 0.0;
@@ -589,7 +618,6 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             kr_sketch_run(Prec::F64, d, n, s, R1, S64, slot_r_[s0], c64, z_, scratch_, st_);
         }
         scale_f64(s, beta, z_, st_);
-        sketch_slot(s0, sketches_);
         window.push_back(s0);
         add_phase(TTSG_PH_OTHER, t0);
 
@@ -598,30 +626,42 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         std::vector<double> cyc_res;  // sketched residuals of this cycle
         for (int k = 0; k < m_ && total < maxit_; ++k) {
             const int vk = window.back();
-            // 1) w_k = S A v_k
+            TTSG_HIP(hipEventRecord(side.v, st_));   // v_k (and S r0) are in place
+            // 1) (stream K) w_k = S A v_k, then the least-squares update of W_k
             auto t1 = now();
+            TTSG_HIP(hipStreamWaitEvent(side.k, side.v, 0));
             {
                 std::vector<const void*> SA64(SA64_.begin(), SA64_.end());
                 std::vector<const void*> c64(slots_[vk].begin(), slots_[vk].end());
-                kr_sketch_run(Prec::F64, d, n, s, in_.R, SA64, slot_r_[vk], c64, W_ + (int64_t)k * s, scratch_, st_);
+                kr_sketch_run(Prec::F64, d, n, s, in_.R, SA64, slot_r_[vk], c64, W_ + (int64_t)k * s, scratchK_,
+                              side.k);
             }
+            hipLaunchKernelGGL(k_ls_append, dim3(1), dim3(LS_THREADS), 0, side.k, s, k, m_ + 1, W_, Q_, Rls_, cls_,
+                               z_, lsres_);
+            TTSG_HIP(hipGetLastError());
             add_phase(TTSG_PH_KR, t1);
-            // 2) h_{i,k} for the window
+            // 2) (stream H) the STTA sketch of v_k, kept for the final solution,
+            // and h_{i,k} for the window
             t1 = now();
-            fill(1, 1.0, hco_, st_);
+            TTSG_HIP(hipStreamWaitEvent(side.h, side.v, 0));
+            sketch_slot(vk, sketches_ + (int64_t)k * sk_len_, scratchH_, side.h);
+            fill(1, 1.0, hco_, side.h);
             const int nw = (int)window.size();
             for (int t = 0; t < nw; ++t) {
                 const int vi = window[t];
                 inner_run(p_, d, n, in_.R, Dv, slot_r_[vk], slot_ops(vk), slot_r_[vi], slot_ops(vi), hco_ + 1 + t,
-                          scratch_, st_);
+                          scratchH_, side.h);
             }
+            TTSG_HIP(hipEventRecord(side.hd, side.h));
             add_phase(TTSG_PH_INNER, t1);
-            // 3) STTA sketch of A v_k, combined with the window sketches
+            // 3) (main) STTA sketch of A v_k, combined with the window sketches
+            // once stream H has delivered them and h
             t1 = now();
             {
                 std::vector<double*> psi, om;
                 sk_ptrs(skA_, psi, om);
                 stta_sketch(so_op, slot_r_[vk], slot_ops(vk), psi.data(), om.data(), scratch_, st_);
+                TTSG_HIP(hipStreamWaitEvent(st_, side.hd, 0));
                 // window entry t holds basis index (k - nw + 1 + t) of this cycle
                 std::vector<const double*> xs(1 + nw);
                 std::vector<double> sg(1 + nw, -1.0);
@@ -658,12 +698,11 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
                                             st_, nullptr);
             add_phase(TTSG_PH_TTSVD, t1);
             TTSG_CHECK(std::isfinite(h), TTSG_ERR_NONFINITE, "non-finite basis vector");
-            // 5) least squares
+            // 5) least-squares residual (stream K finished long ago)
             t1 = now();
-            hipLaunchKernelGGL(k_ls_append, dim3(1), dim3(LS_THREADS), 0, st_, s, k, m_ + 1, W_, Q_, Rls_, cls_,
-                               z_, lsres_);
-            TTSG_HIP(hipGetLastError());
-            const double sres = read(lsres_);
+            double sres = 0.0;
+            TTSG_HIP(hipMemcpyAsync(&sres, lsres_, sizeof(double), hipMemcpyDeviceToHost, side.k));
+            TTSG_HIP(hipStreamSynchronize(side.k));
             add_phase(TTSG_PH_LS, t1);
             TTSG_CHECK(std::isfinite(sres), TTSG_ERR_NONFINITE, "non-finite sketched residual");
             kk = k + 1;
@@ -690,11 +729,10 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             if (p_ != Prec::F64 && (int)cyc_res.size() > kStall &&
                 sres > 0.8 * cyc_res[cyc_res.size() - 1 - kStall])
                 break;
-            // 6) v_{k+1} and its sketch
+            // 6) v_{k+1} (its sketch is taken on stream H in the next iteration)
             t1 = now();
             scale_f64((int64_t)slot_r_[fs][0] * n[0] * slot_r_[fs][1], 1.0 / h, slots_[fs][0], st_);
             to_lp(fs);
-            sketch_slot(fs, sketches_ + (int64_t)(k + 1) * sk_len_);
             window.push_back(fs);
             if ((int)window.size() > q_) window.erase(window.begin());
             add_phase(TTSG_PH_STTA, t1);
