@@ -24,9 +24,13 @@ constexpr int CQ_MAX = 64;
 
 // Cholesky of the c x c symmetric G (column-major) into upper R (G = R^T R),
 // then R^-1; both written column-major with leading dimension c.
+// Second pass (R1 != nullptr): also forms the CholQR2 factor R2 R1 into Rp
+// (column-major) and, when RT != nullptr, its transpose.
 __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restrict__ G, double* __restrict__ R,
                                                     double* __restrict__ Ri, int* __restrict__ flag,
-                                                    int second_pass, DevSlot* slot) {
+                                                    int second_pass, const double* __restrict__ R1,
+                                                    double* __restrict__ Rp, double* __restrict__ RT,
+                                                    DevSlot* slot) {
     __shared__ double A[CQ_MAX][CQ_MAX + 1];
     __shared__ double d0[CQ_MAX], rd[CQ_MAX];
     __shared__ int s_bad;
@@ -70,6 +74,19 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
         R[j + (int64_t)cl * c] = v;
         if (second_pass && fabs(v - (cl == j ? 1.0 : 0.0)) > 0.1) s_bad = 1;
     }
+    if (R1 != nullptr) {
+        // (R2 R1)[i][l] = sum_{t=i..l} R2[i][t] R1[t][l], R2[i][t] = A[t][i] (t > i)
+        for (int e = tid; e < c * c; e += CQ_T) {
+            const int cl = e / c, i = e - cl * c;
+            double v = 0.0;
+            if (i <= cl) {
+                v = rd[i] * R1[i + (int64_t)cl * c];
+                for (int t = i + 1; t <= cl; ++t) v += A[t][i] * R1[t + (int64_t)cl * c];
+            }
+            Rp[i + (int64_t)cl * c] = v;
+            if (RT != nullptr) RT[cl + (int64_t)i * c] = v;
+        }
+    }
     // R^-1 by right-looking back substitution on the upper triangle (R^T stays
     // in the lower one): acc starts as I; step j takes row j of R^-1 as
     // acc[j][:] / R[j][j] and removes R[i][j] times it from the rows i < j.
@@ -111,7 +128,7 @@ void zero_flags(int n, int* f, hipStream_t st) {
 bool cholqr_fits(int m, int c) { return c >= 1 && c <= CQ_MAX && m >= c; }
 
 void cholqr2(int m, int c, const double* X, int64_t xr, int64_t xc, double* Q, int64_t qr, int64_t qc, double* R,
-             int* flag, Arena& ar, hipStream_t st) {
+             int* flag, Arena& ar, hipStream_t st, double* RT) {
     TTSG_CHECK(cholqr_fits(m, c), TTSG_ERR_ARG, "cholqr2: needs m >= c and c <= 64");
     const size_t mark = ar.mark();
     double* G = ar.get<double>((int64_t)c * c);
@@ -141,26 +158,18 @@ void cholqr2(int m, int c, const double* X, int64_t xr, int64_t xc, double* Q, i
         d.cn = idx1(zc);
         contract(Prec::F64, d, Y, Ri, Z, st, &ar);
     };
-    auto chol = [&](double* Rf, double* Rfi, int second) {
+    auto chol = [&](double* Rf, double* Rfi, int second, const double* Rprev, double* Rout, double* RTout) {
         StatScope sc(TTSG_ST_QR, (double)c * c * c / 3.0 + (double)c * c * c / 3.0, 0.0, st);
-        hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(CQ_T), 0, st, c, G, Rf, Rfi, flag, second, sc.slot());
+        hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(CQ_T), 0, st, c, G, Rf, Rfi, flag, second, Rprev, Rout, RTout,
+                           sc.slot());
         TTSG_HIP(hipGetLastError());
     };
     gram(X, xr, xc);
-    chol(R1, R1i, 0);
+    chol(R1, R1i, 0, nullptr, nullptr, nullptr);
     times_inv(X, xr, xc, R1i, Q1, c, 1);
     gram(Q1, c, 1);
-    chol(R2, R2i, 1);
+    chol(R2, R2i, 1, R1, R, RT);   // also R = R2 R1 (and R^T)
     times_inv(Q1, c, 1, R2i, Q, qr, qc);
-    // R = R2 R1 (upper triangular, column-major)
-    ContractDesc d = cdesc(c, c, c);
-    d.am = idx1(1);
-    d.ak = idx1(c);
-    d.bk = idx1(1);
-    d.bn = idx1(c);
-    d.cm = idx1(1);
-    d.cn = idx1(c);
-    contract(Prec::F64, d, R2, R1, R, st, &ar);
     ar.release(mark);
 }
 

@@ -254,20 +254,33 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
         if (any == 0 || moff < 0.01 * tol) break;
     }
     __syncthreads();
-    for (int e = tid; e < m * c; e += blockDim.x) {
-        int j = e / m, i = e - j * m;
-        Ag[(int64_t)j * lda + i] = A[j * ldm + i];
-    }
-    for (int e = tid; e < c * c; e += blockDim.x) {
-        int j = e / c, i = e - j * c;
-        Vg[(int64_t)j * c + i] = V[j * ldv + i];
-    }
+    // singular values = column norms; the output is sorted in descending order
+    // (ties by column index), so callers can take leading columns directly
+    __shared__ double s_sig[64];
+    __shared__ int s_rank[64];
     for (int l = grp; l < c; l += ngrp) {
         const double* al = A + l * ldm;
         double s2 = 0.0;
         for (int i = lt; i < m; i += JG) s2 += al[i] * al[i];
         s2 = row_sum16(s2);
-        if (lt == 0) jb.sig[bi][l] = sqrt(s2);
+        if (lt == 0) s_sig[l] = sqrt(s2);
+    }
+    __syncthreads();
+    for (int l = tid; l < c; l += blockDim.x) {
+        const double v = s_sig[l];
+        int rk = 0;
+        for (int t = 0; t < c; ++t) rk += (s_sig[t] > v || (s_sig[t] == v && t < l)) ? 1 : 0;
+        s_rank[l] = rk;
+        jb.sig[bi][rk] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < m * c; e += blockDim.x) {
+        int j = e / m, i = e - j * m;
+        Ag[(int64_t)s_rank[j] * lda + i] = A[j * ldm + i];
+    }
+    for (int e = tid; e < c * c; e += blockDim.x) {
+        int j = e / c, i = e - j * c;
+        Vg[(int64_t)s_rank[j] * c + i] = V[j * ldv + i];
     }
     slot_end(slot, (unsigned long long)sweeps_done);
 }

@@ -285,19 +285,19 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
                     extract_r(c, c, A, m, Rm, c, st);
                 }
             };
-            auto small_svd = [&]() {
+            auto small_svd = [&](bool have_rt) {
                 // SVD of R through one-sided Jacobi on R^T (rows of a QR factor of a
                 // graded unfolding converge in few sweeps): R^T V' = U' S gives
                 // R = V' S U'^T, i.e. U_R = V' and S V_R^T = (U' S)^T.  Relative
                 // orthogonality 1e-11 is far below every rounding tolerance used.
-                transpose2d(c, c, Rm, c, QV, c, st);              // QV = R^T (column-major)
+                if (!have_rt) transpose2d(c, c, Rm, c, QV, c, st);   // QV = R^T (column-major)
                 svd_small(c, QV, V, sig, st, 1e-11);
                 hsig.assign(c, 0.0);
                 TTSG_HIP(hipMemcpyAsync(hsig.data(), sig, c * sizeof(double), hipMemcpyDeviceToHost, st));
             };
             if (chol) {
-                cholqr2(m, c, w[mu], c, 1, Q, c, 1, Rm, flags + 1 + mu, ar, st);
-                small_svd();
+                cholqr2(m, c, w[mu], c, 1, Q, c, 1, Rm, flags + 1 + mu, ar, st, QV);   // QV = R^T
+                small_svd(true);
                 int hflag = 0;
                 TTSG_HIP(hipMemcpyAsync(&hflag, flags + 1 + mu, sizeof(int), hipMemcpyDeviceToHost, st));
                 TTSG_HIP(hipStreamSynchronize(st));
@@ -308,7 +308,7 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             }
             if (!chol) {
                 householder();
-                small_svd();
+                small_svd(false);
                 TTSG_HIP(hipStreamSynchronize(st));
             }
             perm = argsort_desc(hsig);
@@ -316,12 +316,19 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             for (int t = 0; t < c; ++t) sd[t] = hsig[perm[t]];
             k = trunc_rank(sd, delta, maxrank);
             k = std::min(k, c);
-            std::vector<int> pk(perm.begin(), perm.begin() + k);
-            hold_i.push_back(pk);
-            hold_d.push_back(std::vector<double>(k, 1.0));
-            upload_perm(hold_i.back(), hold_d.back(), perm_dev, fac_dev, st);
-            // Uk (c x k, column-major) = V'[:, perm]
-            gather_cols(c, k, V, c, T, c, perm_dev, fac_dev, st);
+            // the LDS Jacobi returns its columns sorted by singular value, so
+            // the kept vectors are the leading columns; otherwise gather them
+            bool sorted = true;
+            for (int t = 0; t < c; ++t) sorted = sorted && perm[t] == t;
+            const double* Uk = V;
+            if (!sorted) {
+                std::vector<int> pk(perm.begin(), perm.begin() + k);
+                hold_i.push_back(pk);
+                hold_d.push_back(std::vector<double>(k, 1.0));
+                upload_perm(hold_i.back(), hold_d.back(), perm_dev, fac_dev, st);
+                gather_cols(c, k, V, c, T, c, perm_dev, fac_dev, st);   // Uk (c x k, column-major) = V'[:, perm]
+                Uk = T;
+            }
             // new core (row-major m x k) = Q (m x c) * Uk
             if (chol) {
                 ContractDesc dq = cdesc(m, k, c);
@@ -331,16 +338,19 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
                 dq.bn = idx1(c);
                 dq.cm = idx1(k);
                 dq.cn = idx1(1);
-                contract(Prec::F64, dq, Q, T, w[mu], st, &ar);
+                contract(Prec::F64, dq, Q, Uk, w[mu], st, &ar);
             } else if (tsqr) {
-                plan.apply(k, T, c, w[mu], k, true, ar, st);
+                plan.apply(k, Uk, c, w[mu], k, true, ar, st);
             } else {
-                gemm_cm_cm(m, k, c, Q, m, T, c, w[mu], k, st, &ar);
+                gemm_cm_cm(m, k, c, Q, m, Uk, c, w[mu], k, st, &ar);
             }
             ar.release(mk);
-            // S V_R^T (row-major k x c == column-major c x k) = (U' S)[:, perm]
-            gather_cols(c, k, QV, c, Rm, c, perm_dev, fac_dev, st);
-            copy_f64((int64_t)c * k, Rm, QV, st);
+            // S V_R^T (row-major k x c == column-major c x k) = (U' S)[:, perm]:
+            // the leading k columns of QV when sorted
+            if (!sorted) {
+                gather_cols(c, k, QV, c, Rm, c, perm_dev, fac_dev, st);
+                copy_f64((int64_t)c * k, Rm, QV, st);
+            }
         } else {
             // wide unfolding: M^T (c x m) is the row-major core read column-major
             copy_f64((int64_t)m * c, w[mu], A, st);
