@@ -23,9 +23,19 @@ constexpr int CQ_RG = CQ_T / 64;   // row groups: thread (rg, l) owns column l, 
 constexpr int CQ_MAX = 64;
 
 // Cholesky of the c x c symmetric G (column-major) into upper R (G = R^T R),
-// then R^-1; both written column-major with leading dimension c.
+// and R^-1; both written column-major with leading dimension c.
 // Second pass (R1 != nullptr): also forms the CholQR2 factor R2 R1 into Rp
 // (column-major) and, when RT != nullptr, its transpose.
+//
+// One elimination sweep gives both factors.  With G = L D L^T (L unit lower,
+// D the pivots), step j takes the multipliers m_i = S[j][i] / S[j][j] of the
+// current Schur complement S (upper triangle of A) and
+//   - updates S[i][l] -= m_i S[j][l] for j < i <= l,
+//   - applies the same row operation to W = L^-1 (strict lower triangle of A,
+//     unit diagonal implied): W[i][l] -= m_i W[j][l] for i > j, l <= j.
+// Row j is final once step j starts and no step writes it afterwards, so one
+// barrier per step suffices.  Then R[j][l] = S_j[j][l] / sqrt(d_j) (row j of
+// the upper triangle) and R^-1 = W^T D^-1/2, i.e. R^-1[a][b] = W[b][a] / sqrt(d_b).
 __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restrict__ G, double* __restrict__ R,
                                                     double* __restrict__ Ri, int* __restrict__ flag,
                                                     int second_pass, const double* __restrict__ R1,
@@ -38,76 +48,54 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
     const int tid = threadIdx.x;
     for (int e = tid; e < c * c; e += CQ_T) {
         const int l = e / c, i = e - l * c;
-        A[i][l] = G[i + (int64_t)l * c];
+        A[i][l] = i <= l ? G[i + (int64_t)l * c] : 0.0;
     }
     if (tid == 0) s_bad = 0;
     __syncthreads();
     for (int j = tid; j < c; j += CQ_T) d0[j] = A[j][j];
     __syncthreads();
-    // Right-looking Cholesky on the upper triangle.  Step j reads row j and
-    // writes the scaled row as R^T into the (unused) lower triangle and the
-    // rank-1 update into rows > j, so one barrier per step suffices.  Thread
-    // (rg, l) owns column l and every CQ_RG-th row of the update.
+    // thread (rg, l) owns column l and every CQ_RG-th row below the pivot:
+    // Schur rows j < i <= l for l > j, rows of W below j for l <= j
     const int l = tid & 63, rg = tid >> 6;
     for (int j = 0; j < c; ++j) {
         double p = A[j][j];
         const double dj = d0[j];
         const bool ok = p > 1e-10 * dj && p <= 4.0 * dj && dj < INFINITY;
         if (!ok) p = (dj > 0.0 && dj < INFINITY) ? dj : 1.0;   // keep going; the flag discards the result
-        const double rjj = sqrt(p);
         if (tid == 0) {
-            rd[j] = rjj;
+            rd[j] = sqrt(p);
             if (!ok) s_bad = 1;
         }
-        if (l > j && l < c) {
-            const double ajl = A[j][l];
-            if (rg == 0) A[l][j] = ajl / rjj;
-            const double f = ajl / p;
-            for (int i = j + 1 + rg; i <= l; i += CQ_RG) A[i][l] -= A[j][i] * f;
+        if (l < c) {
+            const double ip = 1.0 / p;
+            const double x = l == j ? 1.0 : A[j][l];
+            const int hi = l > j ? l : c - 1;
+            for (int i = j + 1 + rg; i <= hi; i += CQ_RG) A[i][l] -= (A[j][i] * ip) * x;
         }
         __syncthreads();
     }
-    // R (upper): R[j][l] = A[l][j] for l > j, rd[j] on the diagonal
     for (int e = tid; e < c * c; e += CQ_T) {
         const int cl = e / c, j = e - cl * c;
-        const double v = cl > j ? A[cl][j] : (cl == j ? rd[j] : 0.0);
+        const double v = cl > j ? A[j][cl] / rd[j] : (cl == j ? rd[j] : 0.0);
         R[j + (int64_t)cl * c] = v;
         if (second_pass && fabs(v - (cl == j ? 1.0 : 0.0)) > 0.1) s_bad = 1;
+        Ri[j + (int64_t)cl * c] = j <= cl ? (j == cl ? 1.0 : A[cl][j]) / rd[cl] : 0.0;
     }
     if (R1 != nullptr) {
-        // (R2 R1)[i][l] = sum_{t=i..l} R2[i][t] R1[t][l], R2[i][t] = A[t][i] (t > i)
+        // (R2 R1)[i][l] = sum_{t=i..l} R2[i][t] R1[t][l], R2[i][t] = A[i][t] / rd[i] (t > i)
         for (int e = tid; e < c * c; e += CQ_T) {
             const int cl = e / c, i = e - cl * c;
             double v = 0.0;
             if (i <= cl) {
-                v = rd[i] * R1[i + (int64_t)cl * c];
-                for (int t = i + 1; t <= cl; ++t) v += A[t][i] * R1[t + (int64_t)cl * c];
+                double acc = 0.0;
+                for (int t = i + 1; t <= cl; ++t) acc += A[i][t] * R1[t + (int64_t)cl * c];
+                v = rd[i] * R1[i + (int64_t)cl * c] + acc / rd[i];
             }
             Rp[i + (int64_t)cl * c] = v;
             if (RT != nullptr) RT[cl + (int64_t)i * c] = v;
         }
     }
-    // R^-1 by right-looking back substitution on the upper triangle (R^T stays
-    // in the lower one): acc starts as I; step j takes row j of R^-1 as
-    // acc[j][:] / R[j][j] and removes R[i][j] times it from the rows i < j.
-    // Rows are divided by their pivots at the end, so row j is never written
-    // while step j reads it.
-    for (int e = tid; e < c * c; e += CQ_T) {
-        const int cl = e / c, i = e - cl * c;
-        if (i <= cl) A[i][cl] = i == cl ? 1.0 : 0.0;
-    }
     __syncthreads();
-    for (int j = c - 1; j >= 1; --j) {
-        if (l >= j && l < c) {
-            const double rjl = A[j][l] / rd[j];
-            for (int i = rg; i < j; i += CQ_RG) A[i][l] -= A[j][i] * rjl;
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < c * c; e += CQ_T) {
-        const int cl = e / c, i = e - cl * c;
-        Ri[i + (int64_t)cl * c] = i <= cl ? A[i][cl] / rd[i] : 0.0;
-    }
     if (tid == 0 && s_bad) flag[0] = 1;
     slot_end(slot);
 }

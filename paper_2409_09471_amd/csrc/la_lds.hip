@@ -100,7 +100,6 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
     extern __shared__ double lds[];
     slot_begin(slot);
     int sweeps_done = 0;
-    __shared__ short tab[2 * 32 * 63];      // (p, q) of pair k in round r, c <= 64
     __shared__ int s_rot;
     __shared__ unsigned long long s_moff;
     const int bi = blockIdx.x;
@@ -124,19 +123,6 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
     const int cp = c + (c & 1);
     const int npair = cp / 2;
     const int nround = cp - 1;
-    for (int e = tid; e < nround * npair; e += blockDim.x) {
-        const int r = e / npair, k = e - r * npair;
-        int p, q;
-        if (k == 0) {
-            p = cp - 1;
-            q = r;
-        } else {
-            p = (r + k) % (cp - 1);
-            q = (r - k + cp - 1) % (cp - 1);
-        }
-        tab[2 * e] = (short)p;
-        tab[2 * e + 1] = (short)q;
-    }
     const int grp = tid / JG, lt = tid - grp * JG;
     const int ngrp = JT / JG;
     __shared__ double s_fro;
@@ -167,15 +153,20 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
         int rotated = 0;
         double mo2 = 0.0;   // largest squared |cos| between a pair's columns met in this sweep
         sweeps_done = sweep + 1;
+        // circle method, pair k = grp of round r (c <= 64: one pair per lane
+        // group): k = 0 pairs the fixed column cp-1 with r; k > 0 pairs
+        // (r + k, r - k) mod cp-1; both indices advance by one per round
+        int p = grp == 0 ? cp - 1 : grp, q = grp == 0 ? 0 : cp - 1 - grp;
         for (int r = 0; r < nround; ++r) {
-            for (int k = grp; k < npair; k += ngrp) {
-                const int p = tab[2 * (r * npair + k)], q = tab[2 * (r * npair + k) + 1];
-                if (p >= c || q >= c) continue;
+            if (grp < npair && p < c && q < c) {
                 double* ap = A + p * ldm;
                 double* aq = A + q * ldm;
+                double* vp = V + p * ldv;
+                double* vq = V + q * ldv;
                 // the pair's rows stay in registers between the dot products
-                // and the rotation (m <= JG * JR)
-                double xp[JR], xq[JR];
+                // and the rotation (m <= JG * JR); the rotation accumulator's
+                // columns are read with them so their latency overlaps
+                double xp[JR], xq[JR], yp[4], yq[4];
                 double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
                 for (int t = 0; t < JR; ++t) {
@@ -186,38 +177,7 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
                         xp[t] = ap[i];
                         xq[t] = aq[i];
                     }
-                    al += xp[t] * xp[t];
-                    be += xq[t] * xq[t];
-                    ga += xp[t] * xq[t];
                 }
-                al = row_sum16(al);
-                be = row_sum16(be);
-                ga = row_sum16(ga);
-                if (al <= tiny || be <= tiny) continue;
-                const double g2 = ga * ga, ab = al * be;
-                mo2 = fmax(mo2, g2 * rcp_nr(ab));    // squared |cos| (off the rotation's path)
-                if (!(g2 > tol2 * ab)) continue;
-                // rotation angle: with dd = be - al, t = tan(theta) =
-                // 2 ga sign(dd) / (|dd| + sqrt(dd^2 + 4 ga^2)) (the smaller root of
-                // t^2 + (dd / ga) t - 1 = 0); c = 1 / sqrt(1 + t^2), s = c t
-                const double dd = be - al;
-                const double qq = fma(dd, dd, 4.0 * g2);
-                double t = 2.0 * ga * rcp_nr(fabs(dd) + qq * rsq_nr(qq));
-                if (dd < 0.0) t = -t;
-                const double cs = rsq_nr(fma(t, t, 1.0));
-                const double sn = cs * t;
-#pragma unroll
-                for (int u = 0; u < JR; ++u) {
-                    const int i = lt + u * JG;
-                    if (i < m) {
-                        ap[i] = cs * xp[u] - sn * xq[u];
-                        aq[i] = sn * xp[u] + cs * xq[u];
-                    }
-                }
-                // V's pair of columns: all loads, then all stores (c <= 4 JG)
-                double* vp = V + p * ldv;
-                double* vq = V + q * ldv;
-                double yp[4], yq[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int i = lt + u * JG;
@@ -226,14 +186,52 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
                     yq[u] = i < c ? vq[ic] : 0.0;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int i = lt + u * JG;
-                    if (i < c) {
-                        vp[i] = cs * yp[u] - sn * yq[u];
-                        vq[i] = sn * yp[u] + cs * yq[u];
+                for (int t = 0; t < JR; ++t) {
+                    al += xp[t] * xp[t];
+                    be += xq[t] * xq[t];
+                    ga += xp[t] * xq[t];
+                }
+                al = row_sum16(al);
+                be = row_sum16(be);
+                ga = row_sum16(ga);
+                const double g2 = ga * ga, ab = al * be;
+                if (al > tiny && be > tiny) {
+                    mo2 = fmax(mo2, g2 * rcp_nr(ab));    // squared |cos| (off the rotation's path)
+                    if (g2 > tol2 * ab) {
+                        // rotation angle: with dd = be - al, t = tan(theta) =
+                        // 2 ga sign(dd) / (|dd| + sqrt(dd^2 + 4 ga^2)) (the smaller root of
+                        // t^2 + (dd / ga) t - 1 = 0); c = 1 / sqrt(1 + t^2), s = c t
+                        const double dd = be - al;
+                        const double qq = fma(dd, dd, 4.0 * g2);
+                        double t = 2.0 * ga * rcp_nr(fabs(dd) + qq * rsq_nr(qq));
+                        if (dd < 0.0) t = -t;
+                        const double cs = rsq_nr(fma(t, t, 1.0));
+                        const double sn = cs * t;
+#pragma unroll
+                        for (int u = 0; u < JR; ++u) {
+                            const int i = lt + u * JG;
+                            if (i < m) {
+                                ap[i] = cs * xp[u] - sn * xq[u];
+                                aq[i] = sn * xp[u] + cs * xq[u];
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int i = lt + u * JG;
+                            if (i < c) {
+                                vp[i] = cs * yp[u] - sn * yq[u];
+                                vq[i] = sn * yp[u] + cs * yq[u];
+                            }
+                        }
+                        rotated = 1;
                     }
                 }
-                rotated = 1;
+            }
+            if (grp == 0) {
+                q += 1;
+            } else {
+                p = p + 1 == cp - 1 ? 0 : p + 1;
+                q = q + 1 == cp - 1 ? 0 : q + 1;
             }
             __syncthreads();
         }
