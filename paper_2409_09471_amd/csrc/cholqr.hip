@@ -42,7 +42,7 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
                                                     double* __restrict__ Rp, double* __restrict__ RT,
                                                     DevSlot* slot) {
     __shared__ double A[CQ_MAX][CQ_MAX + 1];
-    __shared__ double d0[CQ_MAX], rd[CQ_MAX];
+    __shared__ double d0[CQ_MAX], pd[CQ_MAX], rd[CQ_MAX];
     __shared__ int s_bad;
     slot_begin(slot);
     const int tid = threadIdx.x;
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
         const bool ok = p > 1e-10 * dj && p <= 4.0 * dj && dj < INFINITY;
         if (!ok) p = (dj > 0.0 && dj < INFINITY) ? dj : 1.0;   // keep going; the flag discards the result
         if (tid == 0) {
-            rd[j] = sqrt(p);
+            pd[j] = p;   // square roots after the sweep, off the barrier chain
             if (!ok) s_bad = 1;
         }
         if (l < c) {
@@ -74,6 +74,8 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
         }
         __syncthreads();
     }
+    for (int j = tid; j < c; j += CQ_T) rd[j] = sqrt(pd[j]);
+    __syncthreads();
     for (int e = tid; e < c * c; e += CQ_T) {
         const int cl = e / c, j = e - cl * c;
         const double v = cl > j ? A[j][cl] / rd[j] : (cl == j ? rd[j] : 0.0);
@@ -82,14 +84,22 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
         Ri[j + (int64_t)cl * c] = j <= cl ? (j == cl ? 1.0 : A[cl][j]) / rd[cl] : 0.0;
     }
     if (R1 != nullptr) {
+        // R1 (upper, diagonal included) replaces W in the lower triangle as
+        // R1^T: A[l][t] = R1[t][l], t <= l; the diagonal of A is not read again
+        __syncthreads();
+        for (int e = tid; e < c * c; e += CQ_T) {
+            const int cl = e / c, t = e - cl * c;
+            if (t <= cl) A[cl][t] = R1[t + (int64_t)cl * c];
+        }
+        __syncthreads();
         // (R2 R1)[i][l] = sum_{t=i..l} R2[i][t] R1[t][l], R2[i][t] = A[i][t] / rd[i] (t > i)
         for (int e = tid; e < c * c; e += CQ_T) {
             const int cl = e / c, i = e - cl * c;
             double v = 0.0;
             if (i <= cl) {
                 double acc = 0.0;
-                for (int t = i + 1; t <= cl; ++t) acc += A[i][t] * R1[t + (int64_t)cl * c];
-                v = rd[i] * R1[i + (int64_t)cl * c] + acc / rd[i];
+                for (int t = i + 1; t <= cl; ++t) acc += A[i][t] * A[cl][t];
+                v = rd[i] * A[cl][i] + acc / rd[i];
             }
             Rp[i + (int64_t)cl * c] = v;
             if (RT != nullptr) RT[cl + (int64_t)i * c] = v;

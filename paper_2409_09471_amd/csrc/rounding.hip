@@ -5,6 +5,7 @@
 // exact new sizes.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 
 #include "tt_ops.h"
@@ -158,13 +159,16 @@ void upload_perm(const std::vector<int>& perm, const std::vector<double>& fac, i
 }  // namespace
 
 size_t tt_svd_extra_bytes(int d, const int* n, const int* r) {
-    size_t sum = 0, mx = 0;
+    size_t sum = 0, mx = 0, rmax = 1;
     for (int mu = 0; mu < d; ++mu) {
         const size_t e = (size_t)r[mu] * n[mu] * r[mu + 1];
         sum += e;
         mx = std::max(mx, e);
+        rmax = std::max(rmax, (size_t)std::max(r[mu], r[mu + 1]));
     }
-    return (sum + 2 * mx + 6 * 64 * 64 + 256) * sizeof(double) + (size_t)(d + 1) * 64;
+    // + the host read-back block (squared norm, flags, per-bond singular values)
+    return (sum + 2 * mx + 6 * 64 * 64 + 256) * sizeof(double) + (size_t)(d + 1) * 64 +
+           (4 + (rmax + 1) * d) * sizeof(double) + 256;
 }
 
 double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vector<double*>& w,
@@ -185,16 +189,24 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
     double* tau = ar.get<double>(maxr);
     double* sig = ar.get<double>(maxr);
     double* part = ar.get<double>(1024);
-    double* scal = ar.get<double>(2);
     int* perm_dev = ar.get<int>(maxr);
     double* fac_dev = ar.get<double>(maxr);
+    // Values the host reads back, packed so that each synchronization point
+    // costs one copy: [squared norm, spare, right-to-left CholQR flag] and,
+    // per left-to-right bond, [singular values (maxr), CholQR flag].
+    const int64_t sbk = maxr + 1;
+    double* rb = ar.get<double>(4 + sbk * d);
+    fill(4 + sbk * d, 0.0, rb, st);   // clears every flag
+    double* scal = rb;
+    int* flags = reinterpret_cast<int*>(rb + 2);
+    auto bond_blk = [&](int mu) { return rb + 4 + sbk * mu; };
+    auto bond_flag = [&](int mu) { return reinterpret_cast<int*>(bond_blk(mu) + maxr); };
+    std::vector<double> hb(4 + sbk);
 
     // 1) right-to-left QR orthogonalization.  Bonds whose unfolding fits
     // CholQR2 use it (matrix-core Gram products); if any of them reports an
     // untrustworthy factorization, the cores are restored from a snapshot and
     // the sweep is redone with Householder QR.
-    int* flags = ar.get<int>(d + 1);
-    zero_flags(d + 1, flags, st);
     std::vector<int> r_in = r;
     bool any_chol = false;
     for (int mu = d - 1; mu >= 1; --mu) any_chol = any_chol || cholqr_fits(n[mu] * r[mu + 1], r[mu]);
@@ -236,19 +248,22 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
         }
     };
     orthogonalize(true);
-    if (any_chol) {
-        int hflag = 0;
-        TTSG_HIP(hipMemcpyAsync(&hflag, flags, sizeof(int), hipMemcpyDeviceToHost, st));
-        TTSG_HIP(hipStreamSynchronize(st));
-        if (hflag != 0) {
-            stats_event(TTSG_ST_QR_REDO);
-            r = r_in;
-            for (int mu = 0; mu < d; ++mu) copy_f64((int64_t)r[mu] * n[mu] * r[mu + 1], snap[mu], w[mu], st);
-            orthogonalize(false);
-        }
-    }
+    // squared norm and flag in one read
     sumsq((int64_t)r[0] * n[0] * r[1], w[0], part, scal, st);
-    const double nrm = std::sqrt(read_scalar(scal, st));
+    TTSG_HIP(hipMemcpyAsync(hb.data(), rb, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    TTSG_HIP(hipStreamSynchronize(st));
+    double nrm2 = hb[0];
+    int hflag0 = 0;
+    std::memcpy(&hflag0, &hb[2], sizeof(int));
+    if (any_chol && hflag0 != 0) {
+        stats_event(TTSG_ST_QR_REDO);
+        r = r_in;
+        for (int mu = 0; mu < d; ++mu) copy_f64((int64_t)r[mu] * n[mu] * r[mu + 1], snap[mu], w[mu], st);
+        orthogonalize(false);
+        sumsq((int64_t)r[0] * n[0] * r[1], w[0], part, scal, st);
+        nrm2 = read_scalar(scal, st);
+    }
+    const double nrm = std::sqrt(nrm2);
     if (norm_before) *norm_before = nrm;
     if (nrm == 0.0 || d == 1) {
         ar.release(mark);
@@ -291,16 +306,17 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
                 // R = V' S U'^T, i.e. U_R = V' and S V_R^T = (U' S)^T.  Relative
                 // orthogonality 1e-11 is far below every rounding tolerance used.
                 if (!have_rt) transpose2d(c, c, Rm, c, QV, c, st);   // QV = R^T (column-major)
-                svd_small(c, QV, V, sig, st, 1e-11);
-                hsig.assign(c, 0.0);
-                TTSG_HIP(hipMemcpyAsync(hsig.data(), sig, c * sizeof(double), hipMemcpyDeviceToHost, st));
+                svd_small(c, QV, V, bond_blk(mu), st, 1e-11);
+                // singular values and the CholQR flag in one read
+                TTSG_HIP(hipMemcpyAsync(hb.data(), bond_blk(mu), sbk * sizeof(double), hipMemcpyDeviceToHost, st));
+                TTSG_HIP(hipStreamSynchronize(st));
+                hsig.assign(hb.begin(), hb.begin() + c);
             };
             if (chol) {
-                cholqr2(m, c, w[mu], c, 1, Q, c, 1, Rm, flags + 1 + mu, ar, st, QV);   // QV = R^T
+                cholqr2(m, c, w[mu], c, 1, Q, c, 1, Rm, bond_flag(mu), ar, st, QV);   // QV = R^T
                 small_svd(true);
                 int hflag = 0;
-                TTSG_HIP(hipMemcpyAsync(&hflag, flags + 1 + mu, sizeof(int), hipMemcpyDeviceToHost, st));
-                TTSG_HIP(hipStreamSynchronize(st));
+                std::memcpy(&hflag, &hb[maxr], sizeof(int));
                 if (hflag != 0) {
                     stats_event(TTSG_ST_QR_REDO);
                     chol = false;
@@ -309,7 +325,6 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             if (!chol) {
                 householder();
                 small_svd(false);
-                TTSG_HIP(hipStreamSynchronize(st));
             }
             perm = argsort_desc(hsig);
             std::vector<double> sd(c);
@@ -422,8 +437,20 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
     // sweeps that Jacobi on Omega itself needs): R^T W = U_B S gives
     // Omega = (Q W) S U_B^T, so Omega^+ = U_B S^-1 (Q W)^T.
     std::vector<double*> Ab(d), Rt(d), Wb(d), Sb(d), Gb(d), Vk(d), Wk(d), Qb(d);
-    std::vector<int*> permb(d);
-    std::vector<double*> facb(d);
+    std::vector<int*> permb(d, nullptr);
+    std::vector<double*> facb(d, nullptr);
+    // singular values of all bonds side by side: one read-back
+    int64_t s_tot = 0;
+    std::vector<int64_t> s_off(d, 0);
+    for (int b = 1; b <= d - 1; ++b) {
+        s_off[b] = s_tot;
+        s_tot += rx[b];
+    }
+    double* Sall = ar.get<double>(std::max<int64_t>(s_tot, 1));
+    // gather tables of all bonds (factors, then indices), one upload
+    int64_t u_tot = 0;
+    for (int b = 1; b <= d - 1; ++b) u_tot += rx[b] + (rx[b] + 1) / 2;
+    double* Uall = ar.get<double>(std::max<int64_t>(u_tot, 1));
     std::vector<TsqrPlan> plans(d);
     std::vector<bool> use_tsqr(d, false), use_small(d, false);
     std::vector<double*> Rsm(d, nullptr);
@@ -436,12 +463,10 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         Ab[b] = ar.get<double>((int64_t)m * c);
         Rt[b] = ar.get<double>((int64_t)c * c);
         Wb[b] = ar.get<double>((int64_t)c * c);
-        Sb[b] = ar.get<double>(c);
+        Sb[b] = Sall + s_off[b];
         Gb[b] = ar.get<double>((int64_t)m * c);
         Vk[b] = ar.get<double>((int64_t)c * c);
         Wk[b] = ar.get<double>((int64_t)c * c);
-        permb[b] = ar.get<int>(c);
-        facb[b] = ar.get<double>(2 * (int64_t)c);
         transpose2d(m, c, Omega[b - 1], c, Ab[b], m, st);        // column-major m x c
         use_small[b] = qr_small_fits(m, c);
         use_tsqr[b] = !use_small[b] && tsqr_fits(m, c);
@@ -488,14 +513,16 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
     for (int b = 1; b <= d - 1; ++b) maxT = std::max<int64_t>(maxT, (int64_t)rho[b] * rx[b]);
     double* T = ar.get<double>(maxT);
     std::vector<std::vector<double>> hs(d);
-    for (int b = 1; b <= d - 1; ++b) {
-        hs[b].assign(rx[b], 0.0);
-        TTSG_HIP(hipMemcpyAsync(hs[b].data(), Sb[b], rx[b] * sizeof(double), hipMemcpyDeviceToHost, st));
-    }
+    std::vector<double> hall(std::max<int64_t>(s_tot, 1));
+    TTSG_HIP(hipMemcpyAsync(hall.data(), Sall, s_tot * sizeof(double), hipMemcpyDeviceToHost, st));
     TTSG_HIP(hipStreamSynchronize(st));
     std::vector<std::vector<int>> keep(d);
     std::vector<std::vector<double>> facs(d);
+    // host image of the gather tables; alive until the final synchronization
+    std::vector<double> hup(std::max<int64_t>(u_tot, 1), 0.0);
+    int64_t u_off = 0;
     for (int b = 1; b <= d - 1; ++b) {
+        hs[b].assign(hall.begin() + s_off[b], hall.begin() + s_off[b] + rx[b]);
         std::vector<int> p = argsort_desc(hs[b]);
         const double smax = hs[b][p[0]];
         int k = 0;
@@ -508,8 +535,15 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
             facs[b][t] = sv > 0.0 ? 1.0 / sv : 0.0;
         }
         r_out[b] = k;
-        TTSG_HIP(hipMemcpyAsync(permb[b], keep[b].data(), k * sizeof(int), hipMemcpyHostToDevice, st));
-        TTSG_HIP(hipMemcpyAsync(facb[b], facs[b].data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+        facb[b] = Uall + u_off;
+        permb[b] = reinterpret_cast<int*>(Uall + u_off + k);
+        std::memcpy(hup.data() + u_off, facs[b].data(), k * sizeof(double));
+        std::memcpy(hup.data() + u_off + k, keep[b].data(), k * sizeof(int));
+        u_off += k + (k + 1) / 2;
+    }
+    TTSG_HIP(hipMemcpyAsync(Uall, hup.data(), u_off * sizeof(double), hipMemcpyHostToDevice, st));
+    for (int b = 1; b <= d - 1; ++b) {
+        const int k = r_out[b];
         const int m = rho[b], c = rx[b];
         // V'_b (column-major rx x k) = U_B[:, keep] = (U_B S)[:, keep] / s
         if (pivb[b] != nullptr) {
