@@ -15,16 +15,13 @@
 #include <algorithm>
 
 #include "ttsg_internal.h"
+#include "xlane.h"
 
 namespace ttsg {
 namespace {
 
 constexpr int LA_THREADS = 512;
 
-__device__ __forceinline__ double wsum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 __global__ __launch_bounds__(LA_THREADS) void k_qr(int m, int c, double* __restrict__ A, int lda, int64_t sA,
                                                     double* __restrict__ tau, int64_t sT, DevSlot* slot) {
@@ -39,7 +36,7 @@ __global__ __launch_bounds__(LA_THREADS) void k_qr(int m, int c, double* __restr
         if (wave == 0) {
             double s = 0.0;
             for (int i = j + 1 + lane; i < m; i += 64) s += col[i] * col[i];
-            s = wsum(s);
+            s = wave_sum64(s);
             if (lane == 0) {
                 double alpha = col[j];
                 if (s == 0.0) {
@@ -66,7 +63,7 @@ __global__ __launch_bounds__(LA_THREADS) void k_qr(int m, int c, double* __restr
                 double* cl = A + (int64_t)l * lda;
                 double w = 0.0;
                 for (int i = j + 1 + lane; i < m; i += 64) w += col[i] * cl[i];
-                w = wsum(w);
+                w = wave_sum64(w);
                 w = t * (w + cl[j]);
                 if (lane == 0) cl[j] -= w;
                 for (int i = j + 1 + lane; i < m; i += 64) cl[i] -= w * col[i];
@@ -97,7 +94,7 @@ __global__ __launch_bounds__(LA_THREADS) void k_form_q(int m, int c, const doubl
                 double* ql = Q + (int64_t)l * ldq;
                 double w = 0.0;
                 for (int i = j + 1 + lane; i < m; i += 64) w += v[i] * ql[i];
-                w = wsum(w);
+                w = wave_sum64(w);
                 w = t * (w + ql[j]);
                 if (lane == 0) ql[j] -= w;
                 for (int i = j + 1 + lane; i < m; i += 64) ql[i] -= w * v[i];

@@ -17,6 +17,7 @@
 #include <mutex>
 
 #include "tt_ops.h"
+#include "xlane.h"
 
 namespace ttsg {
 namespace {
@@ -25,10 +26,6 @@ constexpr int JT = 512;    // threads of the Jacobi workgroup (32 lane groups of
 constexpr int QT = 1024;   // threads of the QR leaf workgroups
 constexpr int LEAF = 256;  // maximum rows of a TSQR leaf
 
-__device__ __forceinline__ double wsum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 struct JacobiBatch {
     int count;
@@ -47,12 +44,6 @@ __device__ __forceinline__ void tab_partial_add(double* dst, double v, bool firs
     atomicAdd(dst, v);
 }
 
-// Sum over the G lanes of a lane group (G a power of two dividing 64).
-template <int G> __device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-    return v;
-}
 
 // One-sided Jacobi with one lane group of JG lanes per column pair: the group
 // forms the pair's three dot products over its strided rows, reduces them in
@@ -60,24 +51,6 @@ template <int G> __device__ __forceinline__ double gsum(double v) {
 // a single barrier.  The pairs of every round come from a table built once.
 constexpr int JG = 16;
 constexpr int JROWS = 8;   // rows of a column held per lane: m <= JG * JROWS (kernel JR <= JROWS)
-
-// Data-parallel-primitive move of a double within a row of 16 lanes.
-template <int CTRL> __device__ __forceinline__ double dpp_mov(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-// Sum over the 16 lanes of a row: quad swaps (xor 1, xor 2), then the half-row
-// and row mirrors.  Every step adds two partial sums in commuted order on the
-// two lanes involved, so all 16 lanes end with bit-identical totals.
-__device__ __forceinline__ double row_sum16(double v) {
-    v += dpp_mov<0xB1>(v);    // quad_perm [1, 0, 3, 2]
-    v += dpp_mov<0x4E>(v);    // quad_perm [2, 3, 0, 1]
-    v += dpp_mov<0x141>(v);   // row_half_mirror
-    v += dpp_mov<0x140>(v);   // row_mirror
-    return v;
-}
 
 // 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
 // each (the estimates carry about half the double mantissa; each step doubles
@@ -139,7 +112,7 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
             int j = e / m, i = e - j * m;
             f += A[j * ldm + i] * A[j * ldm + i];
         }
-        f = wsum(f);
+        f = wave_sum64(f);
         if ((tid & 63) == 0) tab_partial_add(&s_fro, f, tid == 0);
     }
     __syncthreads();
@@ -293,6 +266,7 @@ __device__ __forceinline__ void leaf_rows(int m, int nleaves, int i, int& r0, in
 // reflector of column j; then every trailing column is owned by a lane group
 // of QG lanes that reduces v^T a_l in registers and updates its own rows.
 constexpr int QG = 16;
+static_assert(QG == 16, "lane groups are DPP rows");
 __global__ __launch_bounds__(QT) void k_qr_leaf(int m, int c, const double* __restrict__ A, int lda,
                                                  int nleaves, double* __restrict__ refl, int ldr,
                                                  double* __restrict__ tau, double* __restrict__ Rs, int ldrs,
@@ -319,7 +293,7 @@ __global__ __launch_bounds__(QT) void k_qr_leaf(int m, int c, const double* __re
         if (wave == 0) {
             double sacc = 0.0;
             for (int r = j + 1 + lane; r < rows; r += 64) sacc += col[r] * col[r];
-            sacc = wsum(sacc);
+            sacc = wave_sum64(sacc);
             const double alpha = col[j];
             double tt = 0.0, sc = 0.0, beta = alpha;
             if (sacc != 0.0) {
@@ -342,7 +316,7 @@ __global__ __launch_bounds__(QT) void k_qr_leaf(int m, int c, const double* __re
                 double* cl = T + l * ldt;
                 double w = 0.0;
                 for (int r = j + 1 + lt; r < rows; r += QG) w += col[r] * cl[r];
-                w = gsum<QG>(w);
+                w = row_sum16(w);
                 w = t * (w + cl[j]);
                 if (lt == 0) cl[j] -= w;
                 for (int r = j + 1 + lt; r < rows; r += QG) cl[r] -= w * col[r];
@@ -395,7 +369,7 @@ __global__ __launch_bounds__(QT) void k_qr_apply_leaf(int m, int c, int k, const
             double* xt = X + t * ldx;
             double w = 0.0;
             for (int r = j + 1 + lt; r < rows; r += QG) w += v[r] * xt[r];
-            w = gsum<QG>(w);
+            w = row_sum16(w);
             w = tj * (w + xt[j]);
             if (lt == 0) xt[j] -= w;
             for (int r = j + 1 + lt; r < rows; r += QG) xt[r] -= w * v[r];
@@ -452,7 +426,7 @@ __global__ __launch_bounds__(QT) void k_qr_small(QrBatch jb, DevSlot* slot) {
         for (int l = grp; l < c; l += ngrp) {
             double s2 = 0.0;
             for (int r = lt; r < rows; r += QG) s2 += T[l * ldt + r] * T[l * ldt + r];
-            s2 = gsum<QG>(s2);
+            s2 = row_sum16(s2);
             if (lt == 0) s_cn[l] = s2;
         }
         for (int l = tid; l < c; l += blockDim.x) s_perm[l] = l;
@@ -464,16 +438,7 @@ __global__ __launch_bounds__(QT) void k_qr_small(QrBatch jb, DevSlot* slot) {
         if (pivot) {
             // column pivoting: bring the column with the largest remaining norm to j
             if (wave == 0) {
-                double v = (lane >= j && lane < c) ? s_cn[lane] : -1.0;
-                int idx = lane;
-                for (int o = 32; o > 0; o >>= 1) {
-                    const double v2 = __shfl_xor(v, o, 64);
-                    const int i2 = __shfl_xor(idx, o, 64);
-                    if (v2 > v || (v2 == v && i2 < idx)) {
-                        v = v2;
-                        idx = i2;
-                    }
-                }
+                const int idx = wave_argmax64((lane >= j && lane < c) ? s_cn[lane] : -1.0, lane);
                 if (lane == 0) s_piv = idx;
             }
             __syncthreads();
@@ -499,7 +464,7 @@ __global__ __launch_bounds__(QT) void k_qr_small(QrBatch jb, DevSlot* slot) {
         if (wave == 0) {
             double sacc = 0.0;
             for (int r = j + 1 + lane; r < rows; r += 64) sacc += col[r] * col[r];
-            sacc = wsum(sacc);
+            sacc = wave_sum64(sacc);
             const double alpha = col[j];
             double tt = 0.0, sc = 0.0, beta = alpha;
             if (sacc != 0.0) {
@@ -520,7 +485,7 @@ __global__ __launch_bounds__(QT) void k_qr_small(QrBatch jb, DevSlot* slot) {
             if (t != 0.0) {
                 double w = 0.0;
                 for (int r = j + 1 + lt; r < rows; r += QG) w += col[r] * cl[r];
-                w = gsum<QG>(w);
+                w = row_sum16(w);
                 w = t * (w + cl[j]);
                 if (lt == 0) cl[j] -= w;
                 for (int r = j + 1 + lt; r < rows; r += QG) cl[r] -= w * col[r];
@@ -529,7 +494,7 @@ __global__ __launch_bounds__(QT) void k_qr_small(QrBatch jb, DevSlot* slot) {
                 // norm of the rows below j, recomputed (no downdating)
                 double s2 = 0.0;
                 for (int r = j + 1 + lt; r < rows; r += QG) s2 += cl[r] * cl[r];
-                s2 = gsum<QG>(s2);
+                s2 = row_sum16(s2);
                 if (lt == 0) s_cn[l] = s2;
             }
         }
@@ -544,7 +509,7 @@ __global__ __launch_bounds__(QT) void k_qr_small(QrBatch jb, DevSlot* slot) {
                 double* xl = X + l * ldt;
                 double w = 0.0;
                 for (int r = j + 1 + lt; r < rows; r += QG) w += v[r] * xl[r];
-                w = gsum<QG>(w);
+                w = row_sum16(w);
                 w = tj * (w + xl[j]);
                 if (lt == 0) xl[j] -= w;
                 for (int r = j + 1 + lt; r < rows; r += QG) xl[r] -= w * v[r];

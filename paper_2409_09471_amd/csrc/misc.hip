@@ -1,5 +1,6 @@
 // Element-wise and reduction kernels used between the contractions.
 #include "ttsg_internal.h"
+#include "xlane.h"
 
 namespace ttsg {
 namespace {
@@ -72,17 +73,13 @@ __global__ void k_lin_comb(int64_t n, int32_t nt, Ptrs8 xs, const double* __rest
     }
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 __global__ void k_sumsq_part(int64_t n, const double* __restrict__ x, double* __restrict__ part) {
     __shared__ double red[TPB / 64];
     double acc = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         acc += x[i] * x[i];
-    acc = wave_sum(acc);
+    acc = wave_sum64(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -96,7 +93,7 @@ __global__ void k_sum_final(int32_t np, const double* __restrict__ part, double*
     __shared__ double red[TPB / 64];
     double acc = 0.0;
     for (int i = threadIdx.x; i < np; i += blockDim.x) acc += part[i];
-    acc = wave_sum(acc);
+    acc = wave_sum64(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -17,19 +17,16 @@
 #include <cmath>
 
 #include "tt_ops.h"
+#include "xlane.h"
 
 namespace ttsg {
 namespace {
 
 constexpr int LS_THREADS = 1024;
 
-__device__ __forceinline__ double wsum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 __device__ double block_sum(double v, double* red) {
-    v = wsum(v);
+    v = wave_sum64(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     __syncthreads();
     if (lane == 0) red[wave] = v;
@@ -62,7 +59,7 @@ __global__ __launch_bounds__(LS_THREADS) void k_ls_append(int s, int k, int ld, 
             const double* qi = Q + (int64_t)i * s;
             double a = 0.0;
             for (int j = lane; j < s; j += 64) a += qi[j] * qk[j];
-            a = wsum(a);
+            a = wave_sum64(a);
             if (lane == 0) {
                 rk[i] += a;
                 res[2 + i] = a;  // this pass's coefficients
@@ -107,7 +104,7 @@ __global__ void k_ls_solve(int k, int ld, const double* __restrict__ Rm, const d
     for (int i = k - 1; i >= 0; --i) {
         double a = 0.0;
         for (int j = i + 1 + lane; j < k; j += 64) a += Rm[(int64_t)j * ld + i] * y[j];
-        a = wsum(a);
+        a = wave_sum64(a);
         if (lane == 0) {
             const double rii = Rm[(int64_t)i * ld + i];
             y[i] = rii != 0.0 ? (c[i] - a) / rii : 0.0;
