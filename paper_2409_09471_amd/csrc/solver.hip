@@ -187,7 +187,7 @@ class SgmresSolver {
         Arena ar;
         ar.measure();
         carve(ar);
-        return ar.used() + 3 * scratch_bytes() + (64u << 20);
+        return ar.used() + 4 * scratch_bytes() + (64u << 20);
     }
 
     int run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info, void* ws, size_t ws_bytes);
@@ -228,6 +228,7 @@ class SgmresSolver {
     Arena scratch_;    // main stream
     Arena scratchK_;   // side stream K: Khatri-Rao column + least squares
     Arena scratchH_;   // side stream H: sketch of v_k + coefficients h
+    Arena scratchR_;   // side stream R: right sweep and Omega of the sketch of A v_k
 
     size_t scratch_bytes() const;
     void carve(Arena& ar);
@@ -254,7 +255,12 @@ size_t SgmresSolver::scratch_bytes() const {
         big = std::max<int64_t>(big, (int64_t)in_.s * Rm * rl * nn);
         big = std::max<int64_t>(big, (rl * Rm + in_.rb[mu] + rl) * nn * (rr * Rm + in_.rb[mu + 1] + rr));
     }
-    return (size_t)(12 * big + 8 * (int64_t)in_.s * Rm * 512) * 8;
+    // + the kept intermediates of the two-stream STTA sketch (every mode's T2
+    // and left environment at the slot capacities)
+    int64_t kept = 0;
+    for (int mu = 0; mu < d; ++mu)
+        kept += (int64_t)in_.rho[mu] * in_.n[mu] * Rm * in_.rx[mu + 1] + (int64_t)in_.rho[mu] * Rm * in_.rx[mu] + 64;
+    return (size_t)(12 * big + 8 * (int64_t)in_.s * Rm * 512 + kept) * 8;
 }
 
 void SgmresSolver::carve(Arena& ar) {
@@ -379,32 +385,49 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     carve(meas);
     const size_t fixed = meas.used();
     const size_t scr = scratch_bytes();
-    Workspace wsp(ws, ws_bytes, fixed + 3 * scr + 3 * 4096, st_);
+    Workspace wsp(ws, ws_bytes, fixed + 4 * scr + 4 * 4096, st_);
     carve(wsp.arena);
     scratch_.reset(wsp.arena.get<char>(scr), scr);
     scratchK_.reset(wsp.arena.get<char>(scr), scr);
     scratchH_.reset(wsp.arena.get<char>(scr), scr);
+    scratchR_.reset(wsp.arena.get<char>(scr), scr);
 
     // Within an iteration the Khatri-Rao column of A v_k (with the least-squares
     // update) and the sketch of v_k plus the coefficients h do not depend on the
     // STTA sketch of A v_k: they run on two side streams (default priority)
     // while the main stream sketches A v_k, each with its own scratch.
+    // The STTA sketch of A v_k itself runs on two streams: its right sweep and
+    // Omega sketches on side stream R, its left sweep and Psi sketches here.
     struct SideStreams {
-        hipStream_t k = nullptr, h = nullptr;
+        hipStream_t k = nullptr, h = nullptr, r = nullptr;
         hipEvent_t v = nullptr, hd = nullptr;
+        hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
         ~SideStreams() {
             if (k) (void)hipStreamSynchronize(k);
             if (h) (void)hipStreamSynchronize(h);
+            if (r) (void)hipStreamSynchronize(r);
             if (v) (void)hipEventDestroy(v);
             if (hd) (void)hipEventDestroy(hd);
+            for (hipEvent_t e : ev)
+                if (e) (void)hipEventDestroy(e);
             if (k) (void)hipStreamDestroy(k);
             if (h) (void)hipStreamDestroy(h);
+            if (r) (void)hipStreamDestroy(r);
         }
     } side;
     TTSG_HIP(hipStreamCreateWithFlags(&side.k, hipStreamNonBlocking));
     TTSG_HIP(hipStreamCreateWithFlags(&side.h, hipStreamNonBlocking));
+    TTSG_HIP(hipStreamCreateWithFlags(&side.r, hipStreamNonBlocking));
     TTSG_HIP(hipEventCreateWithFlags(&side.v, hipEventDisableTiming));
     TTSG_HIP(hipEventCreateWithFlags(&side.hd, hipEventDisableTiming));
+    for (hipEvent_t& e : side.ev) TTSG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    SketchSide sk_side;
+    sk_side.st = side.r;
+    sk_side.ar = &scratchR_;
+    sk_side.in = side.ev[0];
+    sk_side.right = side.ev[1];
+    sk_side.left = side.ev[2];
+    sk_side.done = side.ev[3];
 
     const bool timing = info && info->phase_seconds;
     auto now = [&]() {
@@ -412,6 +435,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             TTSG_HIP(hipStreamSynchronize(st_));
             TTSG_HIP(hipStreamSynchronize(side.k));
             TTSG_HIP(hipStreamSynchronize(side.h));
+            TTSG_HIP(hipStreamSynchronize(side.r));
         }
         return clock::now();
     };
@@ -657,7 +681,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             {
                 std::vector<double*> psi, om;
                 sk_ptrs(skA_, psi, om);
-                stta_sketch(so_op, slot_r_[vk], slot_ops(vk), psi.data(), om.data(), scratch_, st_);
+                stta_sketch(so_op, slot_r_[vk], slot_ops(vk), psi.data(), om.data(), scratch_, st_, &sk_side);
                 TTSG_HIP(hipStreamWaitEvent(st_, side.hd, 0));
                 // window entry t holds basis index (k - nw + 1 + t) of this cycle
                 std::vector<const double*> xs(1 + nw);

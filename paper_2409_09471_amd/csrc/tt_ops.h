@@ -75,9 +75,20 @@ struct SketchOperands {
     std::vector<const void*> D;               // d, element type of p, or empty
 };
 
-// x cores (element type of p), ranks r.
+// A second stream for stta_sketch: the right-environment sweep and the Omega
+// sketches run on it while the calling stream runs the left sweep and the Psi
+// sketches (the two sweeps are independent; Psi_mu and Omega_b need one
+// environment of each).  The events belong to the caller (created once).
+struct SketchSide {
+    hipStream_t st = nullptr;
+    Arena* ar = nullptr;   // scratch used only by st
+    hipEvent_t in = nullptr, right = nullptr, left = nullptr, done = nullptr;
+};
+// x cores (element type of p), ranks r.  With side, every output is complete
+// in stream order on st when the call returns (st waits for the side stream).
 void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::vector<const void*>& x,
-                 double* const* Psi, double* const* Omega, Arena& ar, hipStream_t st);
+                 double* const* Psi, double* const* Omega, Arena& ar, hipStream_t st,
+                 const SketchSide* side = nullptr);
 
 // Khatri-Rao sketch w = S x or S A x.  SA: d precomputed S_mu D_mu (or S_mu)
 // of element type p; w: float64 output of length s.

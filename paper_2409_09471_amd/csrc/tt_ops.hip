@@ -289,8 +289,111 @@ inline char* adv(const void* p, int64_t elems, Prec pr) {
 }
 }  // namespace
 
+namespace {
+
+// Two-stream form of the STTA sketch: the side stream computes the right
+// environments F_b (right-to-left) and then Omega_b = E_b F_b; the calling
+// stream computes the left environments E_mu with their T2 intermediates
+// (left-to-right, all kept) and then Psi_mu = T2_mu F_{mu+1}.
+void stta_sketch_two_streams(const SketchOperands& o, const std::vector<int>& r, const std::vector<const void*>& x,
+                             double* const* Psi, double* const* Omega, Arena& ar, hipStream_t st,
+                             const SketchSide& sd) {
+    const int d = o.d;
+    const int* n = o.n;
+    const Prec p = o.p;
+    const size_t es = elem_size(p);
+    const bool op = !o.D.empty();
+    auto Rk = [&](int b) { return op ? o.R[b] : 1; };
+    Arena& ar2 = *sd.ar;
+    const size_t mark = ar.mark(), mark2 = ar2.mark();
+    // side stream scratch: right-step intermediates and its conversion buffer
+    int64_t u1 = 1, u2 = 1, om_mx = 1, psi_mx = 1, t1 = 1;
+    for (int mu = 0; mu < d; ++mu) {
+        const int rl = r[mu], rr = r[mu + 1], nn = n[mu];
+        u1 = std::max<int64_t>(u1, (int64_t)rl * nn * Rk(mu + 1) * o.rx[mu + 1]);
+        u2 = std::max<int64_t>(u2, (int64_t)rl * Rk(mu) * nn * o.rx[mu + 1]);
+        t1 = std::max<int64_t>(t1, (int64_t)o.rho[mu] * Rk(mu) * nn * rr);
+        om_mx = std::max<int64_t>(om_mx, (int64_t)o.rho[mu] * o.rx[mu]);
+        psi_mx = std::max<int64_t>(psi_mx, (int64_t)o.rho[mu] * nn * o.rx[mu + 1]);
+    }
+    void* U1 = ar2.get<char>(u1 * es);
+    void* U2 = ar2.get<char>(u2 * es);
+    void* tmp_om = p != Prec::F64 ? ar2.get<char>(om_mx * es) : nullptr;
+    // main stream scratch: T1, the kept T2 of every mode, all left
+    // environments, the right environments (written by the side stream)
+    void* T1 = ar.get<char>(t1 * es);
+    std::vector<void*> T2(d, nullptr), E(d, nullptr), F(d + 1, nullptr);
+    for (int mu = 0; mu < d; ++mu) {
+        const int64_t t2 = (int64_t)o.rho[mu] * n[mu] * Rk(mu + 1) * r[mu + 1];
+        T2[mu] = ar.get<char>((op ? t2 : (int64_t)o.rho[mu] * Rk(mu) * n[mu] * r[mu + 1]) * es);
+        E[mu] = ar.get<char>(std::max<int64_t>((int64_t)o.rho[mu] * Rk(mu) * r[mu], 2) * es);
+    }
+    for (int b = 1; b <= d; ++b) F[b] = ar.get<char>((int64_t)r[b] * Rk(b) * o.rx[b] * es);
+    void* tmp_psi = p != Prec::F64 ? ar.get<char>(psi_mx * es) : nullptr;
+
+    // side: right sweep
+    TTSG_HIP(hipEventRecord(sd.in, st));
+    TTSG_HIP(hipStreamWaitEvent(sd.st, sd.in, 0));
+    set_one(p, F[d], sd.st);
+    for (int mu = d - 1; mu >= 1; --mu) {
+        LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rx[mu], o.rx[mu + 1]};
+        right_step(p, s, F[mu + 1], x[mu], op ? o.D[mu] : nullptr, o.X[mu - 1], U1, U2, F[mu], sd.st, &ar2);
+    }
+    TTSG_HIP(hipEventRecord(sd.right, sd.st));
+    // main: left sweep, keeping T2 and E of every mode
+    set_one(p, E[0], st);
+    for (int mu = 0; mu < d; ++mu) {
+        LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rho[mu], mu + 1 < d ? o.rho[mu + 1] : 1};
+        // without an operator the first stage's output is the intermediate
+        left_step(p, s, E[mu], x[mu], op ? o.D[mu] : nullptr, nullptr, op ? T1 : T2[mu], op ? T2[mu] : nullptr,
+                  nullptr, st, &ar);
+        if (mu + 1 < d) {
+            ContractDesc dd = cdesc(o.rho[mu + 1], Rk(mu + 1) * r[mu + 1], o.rho[mu] * n[mu]);
+            dd.am = idx1(1);
+            dd.ak = idx1(o.rho[mu + 1]);
+            dd.bk = idx1((int64_t)Rk(mu + 1) * r[mu + 1]);
+            dd.bn = idx1(1);
+            dd.cm = idx1((int64_t)Rk(mu + 1) * r[mu + 1]);
+            dd.cn = idx1(1);
+            contract(p, dd, o.Y[mu], T2[mu], E[mu + 1], st, &ar);
+        }
+    }
+    TTSG_HIP(hipEventRecord(sd.left, st));
+    // side: Omega_b = E_b F_b once the left sweep is done
+    TTSG_HIP(hipStreamWaitEvent(sd.st, sd.left, 0));
+    for (int b = 1; b <= d - 1; ++b) {
+        if (p == Prec::F64) {
+            omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], E[b], F[b], Omega[b - 1], sd.st, &ar2);
+        } else {
+            omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], E[b], F[b], tmp_om, sd.st, &ar2);
+            to_f64(p, (int64_t)o.rho[b] * o.rx[b], tmp_om, Omega[b - 1], sd.st);
+        }
+    }
+    TTSG_HIP(hipEventRecord(sd.done, sd.st));
+    // main: Psi_mu = T2_mu F_{mu+1} once the right sweep is done
+    TTSG_HIP(hipStreamWaitEvent(st, sd.right, 0));
+    for (int mu = 0; mu < d; ++mu) {
+        if (p == Prec::F64) {
+            psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2[mu], F[mu + 1], Psi[mu], st, &ar);
+        } else {
+            psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2[mu], F[mu + 1], tmp_psi, st, &ar);
+            to_f64(p, (int64_t)o.rho[mu] * n[mu] * o.rx[mu + 1], tmp_psi, Psi[mu], st);
+        }
+    }
+    // everything (and the side stream's use of this scratch) ends before st goes on
+    TTSG_HIP(hipStreamWaitEvent(st, sd.done, 0));
+    ar2.release(mark2);
+    ar.release(mark);
+}
+
+}  // namespace
+
 void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::vector<const void*>& x,
-                 double* const* Psi, double* const* Omega, Arena& ar, hipStream_t st) {
+                 double* const* Psi, double* const* Omega, Arena& ar, hipStream_t st, const SketchSide* side) {
+    if (side != nullptr && side->st != nullptr && o.d >= 2) {
+        stta_sketch_two_streams(o, r, x, Psi, Omega, ar, st, *side);
+        return;
+    }
     const int d = o.d;
     const int* n = o.n;
     const Prec p = o.p;
