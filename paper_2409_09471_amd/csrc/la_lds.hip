@@ -31,6 +31,7 @@ struct JacobiBatch {
     int count;
     int m[32], c[32], lda[32];
     double tol[32];
+    double drop_abs2[32], drop_rel2[32];
     double* A[32];
     double* V[32];
     double* sig[32];
@@ -120,8 +121,25 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
     // rank-deficient matrix); their mutual dot products never look orthogonal,
     // so they are treated as converged
     const double nz = 2.0 * m * 2.220446049250313e-16;
-    const double tiny = nz * nz * s_fro;
+    const double tiny0 = nz * nz * s_fro;
     const double tol2 = tol * tol;
+    // columns that the caller discards anyway take part in no rotation
+    double drop2 = jb.drop_abs2[bi];
+    if (jb.drop_rel2[bi] > 0.0) {
+        __shared__ unsigned long long s_cmax;
+        if (tid == 0) s_cmax = 0ull;
+        __syncthreads();
+        for (int l = grp; l < c; l += ngrp) {
+            double s2 = 0.0;
+            for (int i = lt; i < m; i += JG) s2 += A[l * ldm + i] * A[l * ldm + i];
+            s2 = row_sum16(s2);
+            // non-negative doubles order like their bit patterns
+            if (lt == 0) atomicMax(&s_cmax, (unsigned long long)__double_as_longlong(s2));
+        }
+        __syncthreads();
+        drop2 = fmax(drop2, jb.drop_rel2[bi] * __longlong_as_double((long long)s_cmax));
+    }
+    const double tiny = fmax(tiny0, drop2);
     for (int sweep = 0; sweep < maxsweeps && cp > 1; ++sweep) {
         int rotated = 0;
         double mo2 = 0.0;   // largest squared |cos| between a pair's columns met in this sweep
@@ -576,6 +594,8 @@ void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st) {
             jb.sig[cnt] = j.sig;
             // below m eps a computed dot product is rounding noise
             jb.tol[cnt] = j.tol > 0.0 ? j.tol : 4.0 * j.m * 2.220446049250313e-16;
+            jb.drop_abs2[cnt] = j.drop_abs2;
+            jb.drop_rel2[cnt] = j.drop_rel2;
             lds = std::max(lds, jacobi_lds_bytes(j.m, j.c));
             mmax = std::max(mmax, j.m);
             flops += 0.5 * j.c * (j.c - 1.0) * (12.0 * j.m + 6.0 * j.c);

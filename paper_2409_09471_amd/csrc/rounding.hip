@@ -64,9 +64,9 @@ void eye(int c, double* I, hipStream_t st) {
 }
 
 // SVD of a c x c column-major matrix in place (LDS kernel when it fits).
-void svd_small(int c, double* A, double* V, double* sig, hipStream_t st, double tol = 0.0) {
+void svd_small(int c, double* A, double* V, double* sig, hipStream_t st, double tol = 0.0, double drop_abs2 = 0.0) {
     if (jacobi_lds_fits(c, c)) {
-        svd_jacobi_batched({JacobiJob{c, c, c, A, V, sig, tol}}, st);
+        svd_jacobi_batched({JacobiJob{c, c, c, A, V, sig, tol, drop_abs2, 0.0}}, st);
     } else {
         svd_jacobi(1, c, c, A, c, 0, V, c, 0, sig, 0, st);
     }
@@ -305,8 +305,12 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
                 // graded unfolding converge in few sweeps): R^T V' = U' S gives
                 // R = V' S U'^T, i.e. U_R = V' and S V_R^T = (U' S)^T.  Relative
                 // orthogonality 1e-11 is far below every rounding tolerance used.
+                // Columns of norm below delta / (4 sqrt(c)) hold at most delta^2 / 16
+                // together, so the truncation drops all of them: they are not
+                // rotated any more (the error of the truncation stays exactly the
+                // norm of the dropped columns).
                 if (!have_rt) transpose2d(c, c, Rm, c, QV, c, st);   // QV = R^T (column-major)
-                svd_small(c, QV, V, bond_blk(mu), st, 1e-11);
+                svd_small(c, QV, V, bond_blk(mu), st, 1e-11, delta * delta / (16.0 * c));
                 // singular values and the CholQR flag in one read
                 TTSG_HIP(hipMemcpyAsync(hb.data(), bond_blk(mu), sbk * sizeof(double), hipMemcpyDeviceToHost, st));
                 TTSG_HIP(hipStreamSynchronize(st));
@@ -502,8 +506,11 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
             // singular values below rcond * s_max are dropped, so rotations
             // that leave 1e-3 rcond of non-orthogonality change nothing kept
             const double jt = std::max(4.0 * rx[b] * 2.220446049250313e-16, 1e-3 * rcond);
+            // singular values below rcond s_max are dropped: columns shorter
+            // than rcond / 16 times the longest one are not rotated any more
             if (jacobi_lds_fits(rx[b], rx[b]))
-                jobs.push_back(JacobiJob{rx[b], rx[b], rx[b], Rt[b], Wb[b], Sb[b], jt});
+                jobs.push_back(JacobiJob{rx[b], rx[b], rx[b], Rt[b], Wb[b], Sb[b], jt, 0.0,
+                                         (rcond / 16.0) * (rcond / 16.0)});
             else
                 svd_jacobi(1, rx[b], rx[b], Rt[b], rx[b], 0, Wb[b], rx[b], 0, Sb[b], 0, st);
         }

@@ -111,6 +111,15 @@ struct JacobiJob {
     double* V;            // out: c x c right singular vectors (column-major, ld c)
     double* sig;          // out: c singular values (unsorted)
     double tol = 0.0;     // stop when every |a_p.a_q| <= tol ||a_p|| ||a_q|| (0: 4 m eps)
+    // A column whose squared norm is at most max(drop_abs2, drop_rel2 *
+    // (largest initial squared column norm)) takes part in no further rotation,
+    // like the columns at rounding-noise level.  For callers that discard every
+    // such column afterwards: with A V = B for the accumulated orthogonal V,
+    // keeping any set of columns of B leaves an error of exactly the norm of
+    // the dropped ones, whatever the angles between kept and dropped columns,
+    // and the kept columns are still orthogonalized among themselves.
+    double drop_abs2 = 0.0;
+    double drop_rel2 = 0.0;
 };
 bool jacobi_lds_fits(int m, int c);
 // One launch for up to 32 matrices (more are split into several launches).
