@@ -293,7 +293,8 @@ int ttsg_autotune_clear(void);
 /* its first workgroup started and its last one ended (one small device slot */
 /* per launch); ttsg_stats_read synchronizes the device and returns, per     */
 /* class, the launch count, the algorithmic flops (2*M*N*K*batch per         */
-/* contraction; the textbook counts for QR and one Jacobi sweep), the operand */
+/* contraction; the textbook counts for QR; for a Jacobi launch one sweep's  */
+/* rotations times the sweeps it ran, its slowest matrix's count), the operand */
 /* bytes (A + B + C, an operand shared across a batch counted once) and the  */
 /* summed kernel durations.  It is meant for benchmarking: each launch pays  */
 /* two extra atomics per workgroup.                                           */

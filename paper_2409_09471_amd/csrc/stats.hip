@@ -118,7 +118,8 @@ int ttsg_stats_read(ttsg_stats* out) {
                          r.shp[4], sec, r.flops, (unsigned long long)s.aux);
         const int c = r.cls;
         out->launches[c] += 1;
-        out->flops[c] += r.flops;
+        // a Jacobi launch records one sweep's rotations; it ran aux sweeps
+        out->flops[c] += (c == TTSG_ST_SVD && s.aux > 0) ? r.flops * (double)s.aux : r.flops;
         out->bytes[c] += r.bytes;
         out->seconds[c] += sec;
         if (c == TTSG_ST_SVD && s.aux > (unsigned long long)out->flops[7]) out->flops[7] = (double)s.aux;
