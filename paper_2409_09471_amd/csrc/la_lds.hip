@@ -411,6 +411,7 @@ struct QrBatch {
     double* Q[32];
     double* R[32];
     int* perm[32];   // nullptr: no column pivoting
+    int flags[32];   // bit 0: A row-major; bit 1: write R^T
 };
 
 // Householder QR of one small matrix per workgroup with the explicit Q:
@@ -434,9 +435,18 @@ __global__ __launch_bounds__(QT) void k_qr_small(QrBatch jb, DevSlot* slot) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int grp = tid / QG, lt = tid - grp * QG, ngrp = QT / QG;
+    const bool a_rm = (jb.flags[bi] & 1) != 0, r_tr = (jb.flags[bi] & 2) != 0;
+    for (int e = tid; e < rows * c; e += blockDim.x) {
+        if (a_rm) {
+            const int r = e / c, j = e - r * c;   // consecutive threads read consecutive entries of a row
+            T[j * ldt + r] = Ag[(int64_t)r * lda + j];
+        } else {
+            const int j = e / rows, r = e - j * rows;
+            T[j * ldt + r] = Ag[(int64_t)j * lda + r];
+        }
+    }
     for (int e = tid; e < rows * c; e += blockDim.x) {
         const int j = e / rows, r = e - j * rows;
-        T[j * ldt + r] = Ag[(int64_t)j * lda + r];
         X[j * ldt + r] = (r == j) ? 1.0 : 0.0;
     }
     __syncthreads();
@@ -543,7 +553,7 @@ __global__ __launch_bounds__(QT) void k_qr_small(QrBatch jb, DevSlot* slot) {
     }
     for (int e = tid; e < c * c; e += blockDim.x) {
         const int j = e / c, r = e - j * c;
-        Rg[(int64_t)j * c + r] = (r <= j && r < kk) ? T[j * ldt + r] : 0.0;
+        Rg[r_tr ? (int64_t)r * c + j : (int64_t)j * c + r] = (r <= j && r < kk) ? T[j * ldt + r] : 0.0;
     }
     if (pivot)
         for (int l = tid; l < c; l += blockDim.x) jb.perm[bi][l] = s_perm[l];
@@ -639,10 +649,12 @@ void qr_small_batched(const std::vector<QrJob>& jobs, hipStream_t st) {
             jb.Q[cnt] = j.Q;
             jb.R[cnt] = j.R;
             jb.perm[cnt] = j.perm;
+            jb.flags[cnt] = (j.a_rowmajor ? 1 : 0) | (j.r_transposed ? 2 : 0);
             lds = std::max(lds, qr_small_lds_bytes(j.m, j.c));
             flops += 4.0 * j.m * j.c * (double)j.c - 4.0 / 3.0 * j.c * (double)j.c * j.c;
             if (bounds_checking()) {
-                check_range(j.A, ((int64_t)(j.c - 1) * j.lda + j.m) * 8, "qr_small A");
+                check_range(j.A, (j.a_rowmajor ? (int64_t)(j.m - 1) * j.lda + j.c : (int64_t)(j.c - 1) * j.lda + j.m) * 8,
+                            "qr_small A");
                 check_range(j.Q, (int64_t)j.m * j.c * 8, "qr_small Q");
                 check_range(j.R, (int64_t)j.c * j.c * 8, "qr_small R");
             }

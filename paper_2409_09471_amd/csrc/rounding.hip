@@ -457,7 +457,6 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
     double* Uall = ar.get<double>(std::max<int64_t>(u_tot, 1));
     std::vector<TsqrPlan> plans(d);
     std::vector<bool> use_tsqr(d, false), use_small(d, false);
-    std::vector<double*> Rsm(d, nullptr);
     std::vector<int*> pivb(d, nullptr);
     std::vector<QrJob> qjobs;
     int64_t maxT = 1;
@@ -471,17 +470,22 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         Gb[b] = ar.get<double>((int64_t)m * c);
         Vk[b] = ar.get<double>((int64_t)c * c);
         Wk[b] = ar.get<double>((int64_t)c * c);
-        transpose2d(m, c, Omega[b - 1], c, Ab[b], m, st);        // column-major m x c
         use_small[b] = qr_small_fits(m, c);
         use_tsqr[b] = !use_small[b] && tsqr_fits(m, c);
         if (use_small[b]) {
             // column-pivoted: R^T is then graded and the Jacobi SVD below
-            // converges in fewer sweeps
+            // converges in fewer sweeps; Omega is read row-major as it is and
+            // R^T written directly
             Qb[b] = ar.get<double>((int64_t)m * c);
-            Rsm[b] = ar.get<double>((int64_t)c * c);
             pivb[b] = ar.get<int>(c);
-            qjobs.push_back(QrJob{m, c, m, Ab[b], Qb[b], Rsm[b], pivb[b]});
-        } else if (use_tsqr[b]) {
+            QrJob qj{m, c, c, Omega[b - 1], Qb[b], Rt[b], pivb[b]};
+            qj.a_rowmajor = true;
+            qj.r_transposed = true;
+            qjobs.push_back(qj);
+            continue;
+        }
+        transpose2d(m, c, Omega[b - 1], c, Ab[b], m, st);        // column-major m x c
+        if (use_tsqr[b]) {
             plans[b].factor(m, c, Ab[b], m, ar, st);
             transpose2d(c, c, plans[b].R, c, Rt[b], c, st);       // R (column-major) -> R^T
         } else {
@@ -495,11 +499,7 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         }
     }
     // all small QRs of the bonds in one launch
-    if (!qjobs.empty()) {
-        qr_small_batched(qjobs, st);
-        for (int b = 1; b <= d - 1; ++b)
-            if (use_small[b]) transpose2d(rx[b], rx[b], Rsm[b], rx[b], Rt[b], rx[b], st);
-    }
+    if (!qjobs.empty()) qr_small_batched(qjobs, st);
     {
         std::vector<JacobiJob> jobs;
         for (int b = 1; b <= d - 1; ++b) {

@@ -136,6 +136,8 @@ struct QrJob {
     double* Q;
     double* R;
     int* perm = nullptr;
+    bool a_rowmajor = false;   // A(i, j) at A[i * lda + j] instead of A[j * lda + i]
+    bool r_transposed = false; // write R^T (column-major c x c) instead of R
 };
 bool qr_small_fits(int m, int c);
 void qr_small_batched(const std::vector<QrJob>& jobs, hipStream_t st);
