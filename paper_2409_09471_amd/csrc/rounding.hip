@@ -216,25 +216,29 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             snap[mu] = ar.get<double>((int64_t)r[mu] * n[mu] * r[mu + 1]);
             copy_f64((int64_t)r[mu] * n[mu] * r[mu + 1], w[mu], snap[mu], st);
         }
+    // The core that a bond factors is read from X: w[mu] for the first bond,
+    // then T, where the previous bond left the core times its R factor (no
+    // copy back into w per bond; the last such product is copied once).
     auto orthogonalize = [&](bool allow_chol) {
+        const double* X = w[d - 1];
         for (int mu = d - 1; mu >= 1; --mu) {
             const int rl = r[mu], rr = r[mu + 1], m = n[mu] * rr, c = rl;
             const int k = std::min(m, c);
             if (allow_chol && cholqr_fits(m, c)) {
                 // the row-major core is the column-major m x c matrix C^T; Q^T
-                // overwrites it as the new row-major core
-                cholqr2(m, c, w[mu], 1, m, w[mu], 1, m, Rm, flags, ar, st);
+                // is the new row-major core
+                cholqr2(m, c, X, 1, m, w[mu], 1, m, Rm, flags, ar, st);
             } else if (tsqr_fits(m, c)) {
                 const size_t mk = ar.mark();
                 TsqrPlan plan;
-                plan.factor(m, c, w[mu], m, ar, st);
+                plan.factor(m, c, X, m, ar, st);
                 double* I = ar.get<double>((int64_t)c * c);
                 eye(c, I, st);
                 copy_f64((int64_t)c * c, plan.R, Rm, st);          // R: c x c, ld c (k == c)
                 plan.apply(c, I, c, w[mu], m, false, ar, st);      // Q^T as the new row-major core
                 ar.release(mk);
             } else {
-                copy_f64((int64_t)m * c, w[mu], A, st);            // column-major m x c == row-major core
+                copy_f64((int64_t)m * c, X, A, st);                // column-major m x c == row-major core
                 qr_householder(1, m, c, A, m, 0, tau, 0, st);
                 qr_form_q(1, m, c, A, m, 0, tau, 0, w[mu], m, 0, st);  // Q^T as the new row-major core
                 extract_r(k, c, A, m, Rm, k, st);
@@ -243,9 +247,10 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             // T (rll*nl x k) = W_{mu-1} (rll*nl x rl) * R^T
             // B[l][kk] = R[kk][l] = Rm[l*k + kk]: the column-major R read row-major
             gemm_rm_rm(rll * nl, k, rl, w[mu - 1], rl, Rm, k, T, k, st, &ar);
-            copy_f64((int64_t)rll * nl * k, T, w[mu - 1], st);
+            X = T;
             r[mu] = k;
         }
+        if (d >= 2) copy_f64((int64_t)r[0] * n[0] * r[1], T, w[0], st);
     };
     orthogonalize(true);
     // squared norm and flag in one read
@@ -276,6 +281,9 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
     std::vector<double> hsig;
     std::vector<std::vector<int>> hold_i;
     std::vector<std::vector<double>> hold_d;
+    // X: the unfolding of the current core (w[0], then T where the previous
+    // bond left S V^T times the next core; T is scratch again once X is read)
+    const double* X = w[0];
     for (int mu = 0; mu <= d - 2; ++mu) {
         const int rl = r[mu], rr = r[mu + 1], m = rl * n[mu], c = rr;
         const int r2 = r[mu + 2], n2 = n[mu + 1];
@@ -290,7 +298,7 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             TsqrPlan plan;
             const size_t mk = ar.mark();
             auto householder = [&]() {
-                transpose2d(m, c, w[mu], c, A, m, st);           // column-major m x c
+                transpose2d(m, c, X, c, A, m, st);               // column-major m x c
                 if (tsqr) {
                     plan.factor(m, c, A, m, ar, st);
                     copy_f64((int64_t)c * c, plan.R, Rm, st);
@@ -317,7 +325,7 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
                 hsig.assign(hb.begin(), hb.begin() + c);
             };
             if (chol) {
-                cholqr2(m, c, w[mu], c, 1, Q, c, 1, Rm, bond_flag(mu), ar, st, QV);   // QV = R^T
+                cholqr2(m, c, X, c, 1, Q, c, 1, Rm, bond_flag(mu), ar, st, QV);   // QV = R^T
                 small_svd(true);
                 int hflag = 0;
                 std::memcpy(&hflag, &hb[maxr], sizeof(int));
@@ -372,7 +380,7 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             }
         } else {
             // wide unfolding: M^T (c x m) is the row-major core read column-major
-            copy_f64((int64_t)m * c, w[mu], A, st);
+            copy_f64((int64_t)m * c, X, A, st);
             qr_householder(1, c, m, A, c, 0, tau, 0, st);
             qr_form_q(1, c, m, A, c, 0, tau, 0, Q, c, 0, st);   // Q2: c x m
             extract_r(m, m, A, c, Rm, m, st);                    // R2: m x m (column-major)
@@ -416,11 +424,12 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             dd.cm = idx1((int64_t)n2 * r2);
             dd.cn = idx1(1);
             contract(Prec::F64, dd, QV, w[mu + 1], T, st, &ar);
-            copy_f64((int64_t)k * n2 * r2, T, w[mu + 1], st);
+            X = T;
         }
         r[mu + 1] = k;
         (void)cap_elems;
     }
+    copy_f64((int64_t)r[d - 1] * n[d - 1] * r[d], T, w[d - 1], st);
     sumsq((int64_t)r[d - 1] * n[d - 1], w[d - 1], part, scal, st);
     const double nout = std::sqrt(read_scalar(scal, st));
     ar.release(mark);
