@@ -253,6 +253,9 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
 
     const out_t alpha = (out_t)d.alpha;
     const out_t beta = (out_t)d.beta;
+    // float32 arithmetic may write a float64 output (its strides count doubles)
+    const bool wide = sizeof(out_t) == 4 && d.c_f64 != 0;
+    double* Cw = reinterpret_cast<double*>(C) + idx_off(d.cb, bidx);
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -264,6 +267,11 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
                 if (row < d.M && col < d.N) {
                     if (part != nullptr) {
                         part[(((int64_t)split * d.batch + bidx) * d.M + row) * d.N + col] = (out_t)acc[i][j][r];
+                    } else if (wide) {
+                        int64_t off = idx_off(d.cm, row) + idx_off(d.cn, col);
+                        double v = d.alpha * (double)acc[i][j][r];
+                        if (d.beta != 0.0) v += d.beta * Cw[off];
+                        Cw[off] = v;
                     } else {
                         int64_t off = idx_off(d.cm, row) + idx_off(d.cn, col);
                         out_t v = alpha * (out_t)acc[i][j][r];
@@ -296,9 +304,16 @@ __global__ __launch_bounds__(256) void reduce_splits(ContractDesc d, int splits,
             const int64_t mn = e - (int64_t)b * per;
             const int m = (int)(mn / d.N), n = (int)(mn - (int64_t)m * d.N);
             const int64_t off = idx_off(d.cb, b) + idx_off(d.cm, m) + idx_off(d.cn, n);
-            O v = alpha * acc;
-            if (beta != O(0)) v += beta * C[off];
-            C[off] = v;
+            if (sizeof(O) == 4 && d.c_f64 != 0) {
+                double* Cw = reinterpret_cast<double*>(C);
+                double v = d.alpha * (double)acc;
+                if (d.beta != 0.0) v += d.beta * Cw[off];
+                Cw[off] = v;
+            } else {
+                O v = alpha * acc;
+                if (beta != O(0)) v += beta * C[off];
+                C[off] = v;
+            }
         }
     }
 }
@@ -412,6 +427,7 @@ int tune(const TuneKey& key, const ContractDesc& d, const void* A, const void* B
     using out_t = typename Traits<T>::out_t;
     ContractDesc dc = d;
     dc.beta = 0.0;
+    dc.c_f64 = 0;   // timed into a scratch of the arithmetic's type
     dc.cb = idx1((int64_t)d.M * d.N);
     dc.cm = idx1(d.N);
     dc.cn = idx1(1);
@@ -447,6 +463,8 @@ int tune(const TuneKey& key, const ContractDesc& d, const void* A, const void* B
 template <typename T>
 void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStream_t st, Arena* ar) {
     if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
+    TTSG_CHECK(d.c_f64 == 0 || sizeof(typename Traits<T>::out_t) == 4, TTSG_ERR_ARG,
+               "contraction: a float64 output needs float32 arithmetic");
     using in_t = typename Traits<T>::in_t;
     if (bounds_checking()) {
         using out_t = typename Traits<T>::out_t;
@@ -455,7 +473,7 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         const int64_t ec = idx_max(d.cb, d.batch) + idx_max(d.cm, d.M) + idx_max(d.cn, d.N) + 1;
         check_range(A, ea * sizeof(in_t), "contract A");
         check_range(B, eb * sizeof(in_t), "contract B");
-        check_range(C, ec * sizeof(out_t), "contract C");
+        check_range(C, ec * (d.c_f64 ? sizeof(double) : sizeof(out_t)), "contract C");
     }
     const int cls = sizeof(typename Traits<T>::lds_t) == 8
                         ? TTSG_ST_CONTRACT_F64
@@ -468,7 +486,7 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         const double ua = (double)d.M * d.K * (d.ab.s0 == 0 ? 1.0 : nb);
         const double ub = (double)d.K * d.N * (d.bb.s0 == 0 ? 1.0 : nb);
         const double uc = (double)d.M * d.N * nb * (d.beta != 0.0 ? 2.0 : 1.0);
-        bytes = (ua + ub) * sizeof(in_t) + uc * sizeof(out_t);
+        bytes = (ua + ub) * sizeof(in_t) + uc * (d.c_f64 ? sizeof(double) : sizeof(out_t));
     }
     StatScope scope(cls, flops, bytes, st);
     using out_t = typename Traits<T>::out_t;

@@ -25,10 +25,11 @@ void left_step(Prec p, const LeftDims& s, const void* E, const void* C, const vo
 // F (rr x Rr x pr) -> Fout (rl x Rl x pl).  U1: rl*n*Rr*pr, U2: rl*Rl*n*pr.
 void right_step(Prec p, const LeftDims& s, const void* F, const void* C, const void* D, const void* Z, void* U1,
                 void* U2, void* Fout, hipStream_t st, Arena* ar = nullptr);
+// out_f64: float32 arithmetic (p != F64) writes a float64 Psi / Om.
 void psi_step(Prec p, int pl, int n, int Rr, int rr, int qr, const void* T2, const void* F, void* Psi,
-              hipStream_t st, Arena* ar = nullptr);
+              hipStream_t st, Arena* ar = nullptr, bool out_f64 = false);
 void omega_step(Prec p, int pl, int Rr, int rr, int qr, const void* E, const void* F, void* Om, hipStream_t st,
-                Arena* ar = nullptr);
+                Arena* ar = nullptr, bool out_f64 = false);
 
 void kr_precompute(Prec p, int s, int n, int Rl, int Rr, const void* S, const void* D, void* SA, hipStream_t st);
 // P (s x Rl x rl) -> Pout (s x Rr x rr); Xbuf holds s*Rr*rl*n elements.

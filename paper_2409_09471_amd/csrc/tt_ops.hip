@@ -144,7 +144,7 @@ void right_step(Prec p, const LeftDims& s, const void* F, const void* C, const v
 }
 
 void psi_step(Prec p, int pl, int n, int Rr, int rr, int qr, const void* T2, const void* F, void* Psi,
-              hipStream_t st, Arena* ar) {
+              hipStream_t st, Arena* ar, bool out_f64) {
     // Psi[p'][i][q] = sum_{(be,b)} T2[p'][i][be][b] F[b][be][q]
     ContractDesc d = cdesc(pl * n, qr, Rr * rr);
     d.am = idx1((int64_t)Rr * rr);
@@ -153,11 +153,12 @@ void psi_step(Prec p, int pl, int n, int Rr, int rr, int qr, const void* T2, con
     d.bn = idx1(1);
     d.cm = idx1(qr);
     d.cn = idx1(1);
+    d.c_f64 = out_f64 && p != Prec::F64 ? 1 : 0;
     contract(p, d, T2, F, Psi, st, ar);
 }
 
 void omega_step(Prec p, int pl, int Rr, int rr, int qr, const void* E, const void* F, void* Om, hipStream_t st,
-                Arena* ar) {
+                Arena* ar, bool out_f64) {
     // Om[p][q] = sum_{(be,b)} E[p][be][b] F[b][be][q]
     ContractDesc d = cdesc(pl, qr, Rr * rr);
     d.am = idx1((int64_t)Rr * rr);
@@ -166,6 +167,7 @@ void omega_step(Prec p, int pl, int Rr, int rr, int qr, const void* E, const voi
     d.bn = idx1(1);
     d.cm = idx1(qr);
     d.cn = idx1(1);
+    d.c_f64 = out_f64 && p != Prec::F64 ? 1 : 0;
     contract(p, d, E, F, Om, st, ar);
 }
 
@@ -306,19 +308,16 @@ void stta_sketch_two_streams(const SketchOperands& o, const std::vector<int>& r,
     auto Rk = [&](int b) { return op ? o.R[b] : 1; };
     Arena& ar2 = *sd.ar;
     const size_t mark = ar.mark(), mark2 = ar2.mark();
-    // side stream scratch: right-step intermediates and its conversion buffer
-    int64_t u1 = 1, u2 = 1, om_mx = 1, psi_mx = 1, t1 = 1;
+    // side stream scratch: right-step intermediates
+    int64_t u1 = 1, u2 = 1, t1 = 1;
     for (int mu = 0; mu < d; ++mu) {
         const int rl = r[mu], rr = r[mu + 1], nn = n[mu];
         u1 = std::max<int64_t>(u1, (int64_t)rl * nn * Rk(mu + 1) * o.rx[mu + 1]);
         u2 = std::max<int64_t>(u2, (int64_t)rl * Rk(mu) * nn * o.rx[mu + 1]);
         t1 = std::max<int64_t>(t1, (int64_t)o.rho[mu] * Rk(mu) * nn * rr);
-        om_mx = std::max<int64_t>(om_mx, (int64_t)o.rho[mu] * o.rx[mu]);
-        psi_mx = std::max<int64_t>(psi_mx, (int64_t)o.rho[mu] * nn * o.rx[mu + 1]);
     }
     void* U1 = ar2.get<char>(u1 * es);
     void* U2 = ar2.get<char>(u2 * es);
-    void* tmp_om = p != Prec::F64 ? ar2.get<char>(om_mx * es) : nullptr;
     // main stream scratch: T1, the kept T2 of every mode, all left
     // environments, the right environments (written by the side stream)
     void* T1 = ar.get<char>(t1 * es);
@@ -329,7 +328,6 @@ void stta_sketch_two_streams(const SketchOperands& o, const std::vector<int>& r,
         E[mu] = ar.get<char>(std::max<int64_t>((int64_t)o.rho[mu] * Rk(mu) * r[mu], 2) * es);
     }
     for (int b = 1; b <= d; ++b) F[b] = ar.get<char>((int64_t)r[b] * Rk(b) * o.rx[b] * es);
-    void* tmp_psi = p != Prec::F64 ? ar.get<char>(psi_mx * es) : nullptr;
 
     // side: right sweep
     TTSG_HIP(hipEventRecord(sd.in, st));
@@ -361,25 +359,13 @@ void stta_sketch_two_streams(const SketchOperands& o, const std::vector<int>& r,
     TTSG_HIP(hipEventRecord(sd.left, st));
     // side: Omega_b = E_b F_b once the left sweep is done
     TTSG_HIP(hipStreamWaitEvent(sd.st, sd.left, 0));
-    for (int b = 1; b <= d - 1; ++b) {
-        if (p == Prec::F64) {
-            omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], E[b], F[b], Omega[b - 1], sd.st, &ar2);
-        } else {
-            omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], E[b], F[b], tmp_om, sd.st, &ar2);
-            to_f64(p, (int64_t)o.rho[b] * o.rx[b], tmp_om, Omega[b - 1], sd.st);
-        }
-    }
+    for (int b = 1; b <= d - 1; ++b)
+        omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], E[b], F[b], Omega[b - 1], sd.st, &ar2, true);
     TTSG_HIP(hipEventRecord(sd.done, sd.st));
     // main: Psi_mu = T2_mu F_{mu+1} once the right sweep is done
     TTSG_HIP(hipStreamWaitEvent(st, sd.right, 0));
-    for (int mu = 0; mu < d; ++mu) {
-        if (p == Prec::F64) {
-            psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2[mu], F[mu + 1], Psi[mu], st, &ar);
-        } else {
-            psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2[mu], F[mu + 1], tmp_psi, st, &ar);
-            to_f64(p, (int64_t)o.rho[mu] * n[mu] * o.rx[mu + 1], tmp_psi, Psi[mu], st);
-        }
-    }
+    for (int mu = 0; mu < d; ++mu)
+        psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2[mu], F[mu + 1], Psi[mu], st, &ar, true);
     // everything (and the side stream's use of this scratch) ends before st goes on
     TTSG_HIP(hipStreamWaitEvent(st, sd.done, 0));
     ar2.release(mark2);
@@ -421,12 +407,6 @@ void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::
     // right environments F_b for b = d..1 (F_d = 1)
     std::vector<void*> F(d + 1, nullptr);
     for (int b = 1; b <= d; ++b) F[b] = ar.get<char>((int64_t)r[b] * Rk(b) * o.rx[b] * es);
-    void* tmp_out = nullptr;
-    if (p != Prec::F64) {
-        int64_t mx = 1;
-        for (int mu = 0; mu < d; ++mu) mx = std::max<int64_t>(mx, (int64_t)o.rho[mu] * n[mu] * o.rx[mu + 1]);
-        tmp_out = ar.get<char>(mx * es);
-    }
     set_one(p, F[d], st);
     for (int mu = d - 1; mu >= 1; --mu) {
         LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rx[mu], o.rx[mu + 1]};
@@ -441,13 +421,7 @@ void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::
         const bool last = (mu == d - 1);
         left_step(p, s, E, x[mu], op ? o.D[mu] : nullptr, nullptr, T1, T2, nullptr, st, &ar);
         const void* T2r = op ? T2 : T1;
-        const int64_t npsi = (int64_t)o.rho[mu] * n[mu] * o.rx[mu + 1];
-        if (p == Prec::F64) {
-            psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2r, F[mu + 1], Psi[mu], st, &ar);
-        } else {
-            psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2r, F[mu + 1], tmp_out, st, &ar);
-            to_f64(p, npsi, tmp_out, Psi[mu], st);
-        }
+        psi_step(p, o.rho[mu], n[mu], Rk(mu + 1), r[mu + 1], o.rx[mu + 1], T2r, F[mu + 1], Psi[mu], st, &ar, true);
         if (!last) {
             // E_{mu+1} = Y_mu contracted with T2
             ContractDesc dd = cdesc(o.rho[mu + 1], Rk(mu + 1) * r[mu + 1], o.rho[mu] * n[mu]);
@@ -459,12 +433,7 @@ void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::
             dd.cn = idx1(1);
             contract(p, dd, o.Y[mu], T2r, En, st, &ar);
             const int b = mu + 1;
-            if (p == Prec::F64) {
-                omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], En, F[b], Omega[b - 1], st, &ar);
-            } else {
-                omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], En, F[b], tmp_out, st, &ar);
-                to_f64(p, (int64_t)o.rho[b] * o.rx[b], tmp_out, Omega[b - 1], st);
-            }
+            omega_step(p, o.rho[b], Rk(b), r[b], o.rx[b], En, F[b], Omega[b - 1], st, &ar, true);
             std::swap(E, En);
         }
     }

@@ -122,6 +122,7 @@ struct ContractDesc {
     Idx2 am, ak, bk, bn, cm, cn;
     Idx2 ab, bb, cb;
     double alpha, beta;
+    int32_t c_f64;   // F32/BF16 arithmetic writing a float64 C (strides in its elements)
 };
 
 // Arithmetic of the contraction kernels.  F32 and BF16 share float32
