@@ -574,8 +574,24 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         double hb[2];
         TTSG_HIP(hipMemcpyAsync(hb, scal_ + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, st_));
         TTSG_HIP(hipStreamSynchronize(st_));
-        double r2 = nb * nb - 2.0 * hb[0] + hb[1];
-        return std::sqrt(std::max(r2, 0.0)) / nb;
+        const double r2 = nb * nb - 2.0 * hb[0] + hb[1];
+        // The three terms cancel: below about 64 eps (||b||^2 + ||A x||^2) the
+        // difference is rounding, not residual.  Then r = b - A x is formed as
+        // a block TT and measured by orthogonalization, which does not cancel.
+        const double noise2 = 64.0 * 2.220446049250313e-16 * (nb * nb + hb[1]);
+        if (r2 > noise2) return std::sqrt(r2) / nb;
+        const size_t mk = scratch_.mark();
+        std::vector<double*> rc(d);
+        for (int mu = 0; mu < d; ++mu)
+            rc[mu] = scratch_.get<double>((int64_t)(in_.rb[mu] + gr[mu]) * n[mu] * (in_.rb[mu + 1] + gr[mu + 1]));
+        std::vector<double*> bw(d);
+        for (int mu = 0; mu < d; ++mu) bw[mu] = const_cast<double*>(in_.b[mu]);   // read only
+        std::vector<const double*> gc(G.begin(), G.end());
+        std::vector<int> rr;
+        tt_add_block(d, n, in_.rb, bw, gr, gc, -1.0, rc, rr, st_);
+        const double nr = tt_norm_orth(d, n, rr, rc, scratch_, st_);
+        scratch_.release(mk);
+        return nr / nb;
     };
 
     // ---- cycles ------------------------------------------------------------
