@@ -94,9 +94,6 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
         int j = e / c, i = e - j * c;
         V[j * ldv + i] = (i == j) ? 1.0 : 0.0;
     }
-    const int cp = c + (c & 1);
-    const int npair = cp / 2;
-    const int nround = cp - 1;
     const int grp = tid / JG, lt = tid - grp * JG;
     const int ngrp = JT / JG;
     __shared__ double s_fro;
@@ -124,22 +121,57 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
     const double tiny0 = nz * nz * s_fro;
     const double tol2 = tol * tol;
     // columns that the caller discards anyway take part in no rotation
-    double drop2 = jb.drop_abs2[bi];
-    if (jb.drop_rel2[bi] > 0.0) {
-        __shared__ unsigned long long s_cmax;
-        if (tid == 0) s_cmax = 0ull;
-        __syncthreads();
-        for (int l = grp; l < c; l += ngrp) {
-            double s2 = 0.0;
-            for (int i = lt; i < m; i += JG) s2 += A[l * ldm + i] * A[l * ldm + i];
-            s2 = row_sum16(s2);
+    __shared__ double s_cn[64];
+    __shared__ unsigned long long s_cmax;
+    __shared__ int s_perm[64];
+    __shared__ int s_cact;
+    if (tid == 0) s_cmax = 0ull;
+    __syncthreads();
+    for (int l = grp; l < c; l += ngrp) {
+        double s2 = 0.0;
+        for (int i = lt; i < m; i += JG) s2 += A[l * ldm + i] * A[l * ldm + i];
+        s2 = row_sum16(s2);
+        if (lt == 0) {
+            s_cn[l] = s2;
             // non-negative doubles order like their bit patterns
-            if (lt == 0) atomicMax(&s_cmax, (unsigned long long)__double_as_longlong(s2));
+            atomicMax(&s_cmax, (unsigned long long)__double_as_longlong(s2));
+        }
+    }
+    __syncthreads();
+    double drop2 = jb.drop_abs2[bi];
+    if (jb.drop_rel2[bi] > 0.0) drop2 = fmax(drop2, jb.drop_rel2[bi] * __longlong_as_double((long long)s_cmax));
+    const double tiny = fmax(tiny0, drop2);
+    // The columns that can rotate go first (in index order), the ones at or
+    // below the threshold after them: the rounds then run over the active
+    // columns only.  V starts as the permutation, so A V = B still holds.
+    if (tid < 64) {
+        const bool on = tid < c && s_cn[tid] > tiny;
+        const unsigned long long act = __ballot(on);
+        const unsigned long long below = (1ull << tid) - 1ull;
+        const int nact = __popcll(act);
+        if (tid < c) {
+            const unsigned long long valid = c >= 64 ? ~0ull : ((1ull << c) - 1ull);
+            const int pos = on ? __popcll(act & below) : nact + __popcll(~act & valid & below);
+            s_perm[pos] = tid;
+        }
+        if (tid == 0) s_cact = nact;
+    }
+    __syncthreads();
+    const int c_act = s_cact;
+    if (c_act < c) {
+        for (int e = tid; e < m * c; e += blockDim.x) {
+            const int j = e / m, i = e - j * m;
+            A[j * ldm + i] = Ag[(int64_t)s_perm[j] * lda + i];
+        }
+        for (int e = tid; e < c * c; e += blockDim.x) {
+            const int j = e / c, i = e - j * c;
+            V[j * ldv + i] = (i == s_perm[j]) ? 1.0 : 0.0;
         }
         __syncthreads();
-        drop2 = fmax(drop2, jb.drop_rel2[bi] * __longlong_as_double((long long)s_cmax));
     }
-    const double tiny = fmax(tiny0, drop2);
+    const int cp = c_act + (c_act & 1);
+    const int npair = cp / 2;
+    const int nround = cp - 1;
     for (int sweep = 0; sweep < maxsweeps && cp > 1; ++sweep) {
         int rotated = 0;
         double mo2 = 0.0;   // largest squared |cos| between a pair's columns met in this sweep
@@ -149,7 +181,7 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
         // (r + k, r - k) mod cp-1; both indices advance by one per round
         int p = grp == 0 ? cp - 1 : grp, q = grp == 0 ? 0 : cp - 1 - grp;
         for (int r = 0; r < nround; ++r) {
-            if (grp < npair && p < c && q < c) {
+            if (grp < npair && p < c_act && q < c_act) {
                 double* ap = A + p * ldm;
                 double* aq = A + q * ldm;
                 double* vp = V + p * ldv;
