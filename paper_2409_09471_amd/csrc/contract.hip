@@ -503,7 +503,7 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         int want = (int)std::min<int64_t>((512 + wgs - 1) / wgs, d.K / (4 * BK));
         want = std::min(want, 64);
         want = std::min<int64_t>(want, 65535 / std::max(d.batch, 1));
-        if (want >= 2) {
+        if (want >= 5) {   // two to four splits of an already wide grid cost more in the extra reduction than they save
             kchunk = ((d.K + want - 1) / want + BK - 1) / BK * BK;
             splits = (d.K + kchunk - 1) / kchunk;
         }
