@@ -31,15 +31,27 @@ __global__ void k_gather_cols(int rows, int k, const double* __restrict__ src, i
     }
 }
 
-// Column t, row i of dst = fac[t] * src[perm[t]][i], written to row rowperm[i]
-// (the row permutation of a column-pivoted QR).
-__global__ void k_gather_cols_rows(int rows, int k, const double* __restrict__ src, int lds,
-                                   double* __restrict__ dst, int ldd, const int* __restrict__ perm,
-                                   const double* __restrict__ fac, const int* __restrict__ rowperm) {
-    int total = rows * k;
+// Several column gathers in one launch (blockIdx.y = job): column t, row i of
+// dst = fac[t] * src[perm[t]][i], written to row rowperm[i] when rowperm is set.
+struct GatherJob {
+    int rows, k, lds, ldd;
+    const double* src;
+    double* dst;
+    const int* perm;
+    const double* fac;
+    const int* rowperm;
+};
+struct GatherBatch {
+    int count;
+    GatherJob j[32];
+};
+__global__ void k_gather_batched(GatherBatch gb) {
+    const GatherJob g = gb.j[blockIdx.y];
+    const int total = g.rows * g.k;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-        int t = e / rows, i = e - t * rows;
-        dst[(int64_t)t * ldd + rowperm[i]] = fac[t] * src[(int64_t)perm[t] * lds + i];
+        const int t = e / g.rows, i = e - t * g.rows;
+        const int oi = g.rowperm != nullptr ? g.rowperm[i] : i;
+        g.dst[(int64_t)t * g.ldd + oi] = g.fac[t] * g.src[(int64_t)g.perm[t] * g.lds + i];
     }
 }
 
@@ -558,20 +570,32 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         u_off += k + (k + 1) / 2;
     }
     TTSG_HIP(hipMemcpyAsync(Uall, hup.data(), u_off * sizeof(double), hipMemcpyHostToDevice, st));
+    // the gathers of every bond, batched:
+    //   V'_b (column-major rx x k) = U_B[:, keep] = (U_B S)[:, keep] / s; with
+    //   Omega P = Q R the right factor is P U_B, rows of U_B scattered by P;
+    //   W[:, keep] / s for G_b (row-major k x rho == column-major rho x k) = Q W[:, keep] / s
+    {
+        std::vector<GatherJob> gj;
+        for (int b = 1; b <= d - 1; ++b) {
+            const int k = r_out[b], c = rx[b];
+            gj.push_back(GatherJob{c, k, c, c, Rt[b], Vk[b], permb[b], facb[b], pivb[b]});
+            gj.push_back(GatherJob{c, k, c, c, Wb[b], Wk[b], permb[b], facb[b], nullptr});
+        }
+        for (size_t j0 = 0; j0 < gj.size(); j0 += 32) {
+            GatherBatch gb{};
+            gb.count = (int)std::min<size_t>(32, gj.size() - j0);
+            int64_t mx = 1;
+            for (int t = 0; t < gb.count; ++t) {
+                gb.j[t] = gj[j0 + t];
+                mx = std::max<int64_t>(mx, (int64_t)gb.j[t].rows * gb.j[t].k);
+            }
+            hipLaunchKernelGGL(k_gather_batched, dim3(nb(mx), gb.count), dim3(256), 0, st, gb);
+            TTSG_HIP(hipGetLastError());
+        }
+    }
     for (int b = 1; b <= d - 1; ++b) {
         const int k = r_out[b];
         const int m = rho[b], c = rx[b];
-        // V'_b (column-major rx x k) = U_B[:, keep] = (U_B S)[:, keep] / s
-        if (pivb[b] != nullptr) {
-            // Omega P = Q R: the right factor is P U_B, rows of U_B scattered by P
-            hipLaunchKernelGGL(k_gather_cols_rows, dim3(nb((int64_t)c * k)), dim3(256), 0, st, c, k, Rt[b], c,
-                               Vk[b], c, permb[b], facb[b], pivb[b]);
-            TTSG_HIP(hipGetLastError());
-        } else {
-            gather_cols(c, k, Rt[b], c, Vk[b], c, permb[b], facb[b], st);
-        }
-        // G_b (row-major k x rho == column-major rho x k) = Q W[:, keep] / s
-        gather_cols(c, k, Wb[b], c, Wk[b], c, permb[b], facb[b], st);
         if (use_small[b]) {
             // G_b (column-major m x k) = Q (column-major m x c) * W[:, keep] / s
             ContractDesc dg = cdesc(m, k, c);
