@@ -136,6 +136,37 @@ void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_
     hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(TPB), 0, st, n, a, x, b, y);
     TTSG_HIP(hipGetLastError());
 }
+namespace {
+struct HostStage {
+    double* p = nullptr;
+    bool tried = false;
+    ~HostStage() {
+        if (p != nullptr) (void)hipHostFree(p);
+    }
+};
+}  // namespace
+
+double* host_stage(int region) {
+    thread_local HostStage s;
+    if (!s.tried) {
+        s.tried = true;
+        if (hipHostMalloc(reinterpret_cast<void**>(&s.p), 2 * kStageDoubles * sizeof(double), hipHostMallocDefault) !=
+            hipSuccess) {
+            s.p = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    return s.p != nullptr ? s.p + (region != 0 ? kStageDoubles : 0) : nullptr;
+}
+
+const void* read_back(const void* dev, size_t bytes, void* fallback, hipStream_t st) {
+    double* stage = bytes <= kStageDoubles * sizeof(double) ? host_stage(0) : nullptr;
+    void* dst = stage != nullptr ? static_cast<void*>(stage) : fallback;
+    TTSG_HIP(hipMemcpyAsync(dst, dev, bytes, hipMemcpyDeviceToHost, st));
+    TTSG_HIP(hipStreamSynchronize(st));
+    return dst;
+}
+
 void fill(int64_t n, double v, double* y, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(TPB), 0, st, n, v, y);

@@ -156,9 +156,7 @@ std::vector<int> argsort_desc(const std::vector<double>& s) {
 
 double read_scalar(const double* dev, hipStream_t st) {
     double h = 0.0;
-    TTSG_HIP(hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, st));
-    TTSG_HIP(hipStreamSynchronize(st));
-    return h;
+    return *static_cast<const double*>(read_back(dev, sizeof(double), &h, st));
 }
 
 // Upload perm (ints) and factors (doubles) into device buffers.
@@ -267,11 +265,10 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
     orthogonalize(true);
     // squared norm and flag in one read
     sumsq((int64_t)r[0] * n[0] * r[1], w[0], part, scal, st);
-    TTSG_HIP(hipMemcpyAsync(hb.data(), rb, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-    TTSG_HIP(hipStreamSynchronize(st));
-    double nrm2 = hb[0];
+    const double* h3 = static_cast<const double*>(read_back(rb, 3 * sizeof(double), hb.data(), st));
+    double nrm2 = h3[0];
     int hflag0 = 0;
-    std::memcpy(&hflag0, &hb[2], sizeof(int));
+    std::memcpy(&hflag0, &h3[2], sizeof(int));
     if (any_chol && hflag0 != 0) {
         stats_event(TTSG_ST_QR_REDO);
         r = r_in;
@@ -332,8 +329,9 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
                 if (!have_rt) transpose2d(c, c, Rm, c, QV, c, st);   // QV = R^T (column-major)
                 svd_small(c, QV, V, bond_blk(mu), st, 1e-11, delta * delta / (16.0 * c));
                 // singular values and the CholQR flag in one read
-                TTSG_HIP(hipMemcpyAsync(hb.data(), bond_blk(mu), sbk * sizeof(double), hipMemcpyDeviceToHost, st));
-                TTSG_HIP(hipStreamSynchronize(st));
+                const double* hr =
+                    static_cast<const double*>(read_back(bond_blk(mu), sbk * sizeof(double), hb.data(), st));
+                std::copy(hr, hr + sbk, hb.begin());
                 hsig.assign(hb.begin(), hb.begin() + c);
             };
             if (chol) {
@@ -542,8 +540,10 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
     double* T = ar.get<double>(maxT);
     std::vector<std::vector<double>> hs(d);
     std::vector<double> hall(std::max<int64_t>(s_tot, 1));
-    TTSG_HIP(hipMemcpyAsync(hall.data(), Sall, s_tot * sizeof(double), hipMemcpyDeviceToHost, st));
-    TTSG_HIP(hipStreamSynchronize(st));
+    {
+        const double* hr = static_cast<const double*>(read_back(Sall, s_tot * sizeof(double), hall.data(), st));
+        if (hr != hall.data()) std::copy(hr, hr + s_tot, hall.begin());
+    }
     std::vector<std::vector<int>> keep(d);
     std::vector<std::vector<double>> facs(d);
     // host image of the gather tables; alive until the final synchronization
@@ -569,7 +569,13 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         std::memcpy(hup.data() + u_off + k, keep[b].data(), k * sizeof(int));
         u_off += k + (k + 1) / 2;
     }
-    TTSG_HIP(hipMemcpyAsync(Uall, hup.data(), u_off * sizeof(double), hipMemcpyHostToDevice, st));
+    {
+        // from pinned memory when it fits (kept untouched until the final synchronization below)
+        double* up = (size_t)u_off <= kStageDoubles ? host_stage(1) : nullptr;
+        if (up != nullptr) std::copy(hup.begin(), hup.begin() + u_off, up);
+        TTSG_HIP(hipMemcpyAsync(Uall, up != nullptr ? up : hup.data(), u_off * sizeof(double), hipMemcpyHostToDevice,
+                                st));
+    }
     // the gathers of every bond, batched:
     //   V'_b (column-major rx x k) = U_B[:, keep] = (U_B S)[:, keep] / s; with
     //   Omega P = Q R the right factor is P U_B, rows of U_B scattered by P;

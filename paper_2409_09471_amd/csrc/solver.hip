@@ -514,9 +514,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     };
     auto read = [&](const double* dev) {
         double h = 0.0;
-        TTSG_HIP(hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, st_));
-        TTSG_HIP(hipStreamSynchronize(st_));
-        return h;
+        return *static_cast<const double*>(read_back(dev, sizeof(double), &h, st_));
     };
     auto cvec = [](const std::vector<double*>& v) { return std::vector<const double*>(v.begin(), v.end()); };
 
@@ -571,9 +569,8 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         std::vector<const void*> gv(G.begin(), G.end()), bv(in_.b.begin(), in_.b.end());
         inner_run(Prec::F64, d, n, R1, {}, gr, gv, in_.rb, bv, scal_ + 1, scratch_, st_);
         inner_run(Prec::F64, d, n, R1, {}, gr, gv, gr, gv, scal_ + 2, scratch_, st_);
-        double hb[2];
-        TTSG_HIP(hipMemcpyAsync(hb, scal_ + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, st_));
-        TTSG_HIP(hipStreamSynchronize(st_));
+        double hbuf[2];
+        const double* hb = static_cast<const double*>(read_back(scal_ + 1, 2 * sizeof(double), hbuf, st_));
         const double r2 = nb * nb - 2.0 * hb[0] + hb[1];
         // The three terms cancel: below about 64 eps (||b||^2 + ||A x||^2) the
         // difference is rounding, not residual.  Then r = b - A x is formed as
@@ -738,8 +735,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             // 5) least-squares residual (stream K finished long ago)
             t1 = now();
             double sres = 0.0;
-            TTSG_HIP(hipMemcpyAsync(&sres, lsres_, sizeof(double), hipMemcpyDeviceToHost, side.k));
-            TTSG_HIP(hipStreamSynchronize(side.k));
+            sres = *static_cast<const double*>(read_back(lsres_, sizeof(double), &sres, side.k));
             add_phase(TTSG_PH_LS, t1);
             TTSG_CHECK(std::isfinite(sres), TTSG_ERR_NONFINITE, "non-finite sketched residual");
             kk = k + 1;
