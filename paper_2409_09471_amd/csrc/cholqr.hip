@@ -42,6 +42,7 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
                                                     double* __restrict__ Rp, double* __restrict__ RT,
                                                     DevSlot* slot) {
     __shared__ double A[CQ_MAX][CQ_MAX + 1];
+    __shared__ double B[CQ_MAX][CQ_MAX + 1];   // second pass: R1, row-major
     __shared__ double d0[CQ_MAX], pd[CQ_MAX], rd[CQ_MAX];
     __shared__ int s_bad;
     slot_begin(slot);
@@ -84,22 +85,32 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
         Ri[j + (int64_t)cl * c] = j <= cl ? (j == cl ? 1.0 : A[cl][j]) / rd[cl] : 0.0;
     }
     if (R1 != nullptr) {
-        // R1 (upper, diagonal included) replaces W in the lower triangle as
-        // R1^T: A[l][t] = R1[t][l], t <= l; the diagonal of A is not read again
+        // R1 (upper, diagonal included) staged row-major: B[t][l] = R1[t][l]
         __syncthreads();
         for (int e = tid; e < c * c; e += CQ_T) {
             const int cl = e / c, t = e - cl * c;
-            if (t <= cl) A[cl][t] = R1[t + (int64_t)cl * c];
+            B[t][cl] = t <= cl ? R1[e] : 0.0;
         }
         __syncthreads();
-        // (R2 R1)[i][l] = sum_{t=i..l} R2[i][t] R1[t][l], R2[i][t] = A[i][t] / rd[i] (t > i)
+        // (R2 R1)[i][l] = sum_{t=i..l} R2[i][t] R1[t][l], R2[i][t] = A[i][t] / rd[i]
+        // (t > i); lanes run along l, so R1 is read along its rows and R2's
+        // entries are shared by the lanes of one row i
         for (int e = tid; e < c * c; e += CQ_T) {
-            const int cl = e / c, i = e - cl * c;
+            const int i = e / c, cl = e - i * c;
             double v = 0.0;
             if (i <= cl) {
-                double acc = 0.0;
-                for (int t = i + 1; t <= cl; ++t) acc += A[i][t] * A[cl][t];
-                v = rd[i] * A[cl][i] + acc / rd[i];
+                // four independent partial sums: each group of eight LDS reads
+                // is issued before any of them is waited for
+                double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+                int t = i + 1;
+                for (; t + 3 <= cl; t += 4) {
+                    acc0 += A[i][t] * B[t][cl];
+                    acc1 += A[i][t + 1] * B[t + 1][cl];
+                    acc2 += A[i][t + 2] * B[t + 2][cl];
+                    acc3 += A[i][t + 3] * B[t + 3][cl];
+                }
+                for (; t <= cl; ++t) acc0 += A[i][t] * B[t][cl];
+                v = rd[i] * B[i][cl] + ((acc0 + acc1) + (acc2 + acc3)) / rd[i];
             }
             Rp[i + (int64_t)cl * c] = v;
             if (RT != nullptr) RT[cl + (int64_t)i * c] = v;
