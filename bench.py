@@ -122,23 +122,33 @@ def rounding_gflops(w, t):
     return dict(seconds=el, gflop=fl / 1e9, gflops_per_s=fl / el / 1e9)
 
 
-COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "contract_kernel_hbm_counters_convdiff_d10_n64.md")
+# HBM counter summaries per kernel class: (file under profiles/, kernel source
+# whose SHA-256 the summary records)
+COUNTER_SUMMARIES = {
+    "contract_f64": ("contract_kernel_f64_hbm_counters_convdiff_d10_n64.md", "contract.hip"),
+    "contract_f32": ("contract_kernel_f32_hbm_counters_convdiff_d10_n64.md", "contract.hip"),
+    "svd_jacobi": ("k_jacobi_lds_hbm_counters_convdiff_d10_n64.md", "la_lds.hip"),
+}
 TILE_TABLE = os.path.join(ROOT, "paper_2409_09471_amd", "tiles_gfx950.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2409_09471_amd", "csrc", "contract.hip")
 
 
 def counter_traffic(cls):
-    """HBM bytes per launch of the contraction class `cls` from the committed
-    FETCH_SIZE / WRITE_SIZE summary, or None when that summary was taken on a
-    different version of the kernel source (or is missing)."""
-    if not os.path.exists(COUNTER_SUMMARY):
+    """HBM bytes per launch of the kernel class `cls` from its committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when there is none for the class or
+    it was taken on a different version of the kernel's source."""
+    ent = COUNTER_SUMMARIES.get(cls)
+    if ent is None:
+        return None
+    path = os.path.join(ROOT, "profiles", ent[0])
+    if not os.path.exists(path):
         return None
     fields = {}
-    for line in open(COUNTER_SUMMARY):
+    for line in open(path):
         m = re.match(r"^- (\w+): (\S+)", line.strip())
         if m:
             fields[m.group(1)] = m.group(2)
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    src = os.path.join(ROOT, "paper_2409_09471_amd", "csrc", ent[1])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if fields.get("kernel_source_sha256") != sha or fields.get("class") != cls:
         return None
     try:
@@ -245,7 +255,7 @@ def main():
         else:
             # single-workgroup FP64 factorizations: vector ALU work
             name = {"svd_jacobi": "k_jacobi_lds", "qr": "k_chol_inv + k_qr_small"}.get(cls, cls)
-            bound, peak, traffic = "alu", PEAK_F64_VECTOR, None
+            bound, peak, traffic = "alu", PEAK_F64_VECTOR, counter_traffic(cls)
         return {"kernel": name, "bound": bound, "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": ach / peak, "traffic": traffic, "flop_per_launch": v["flops"] / v["launches"],
                 "avg_launch_us": v["seconds"] / v["launches"] * 1e6}

@@ -648,7 +648,10 @@ void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st) {
             }
         }
         jb.count = cnt;
+        int cmax = 0;
+        for (int t = 0; t < cnt; ++t) cmax = std::max(cmax, jb.c[t]);
         StatScope scope(TTSG_ST_SVD, flops, 0.0, st);
+        scope.shape(cnt, mmax, cmax, 0, 0);
         // four register rows per lane cover every matrix of up to 64 rows
         if (mmax <= 4 * JG) {
             allow_lds(reinterpret_cast<const void*>(&k_jacobi_lds<4>), lds, g_lds_jacobi4);
