@@ -122,12 +122,6 @@ def expsum_full(sol) -> np.ndarray:
     return sum(wq * full(c) for wq, c in sol)
 
 
-def expsum_dot(sol, y) -> float:
-    """<x*, y> for a TT y."""
-    from .tt import dot
-    return float(sum(wq * dot(c, y) for wq, c in sol))
-
-
 def expsum_round(sol, tol: float = 1e-12, maxrank=None):
     """x* as one TT: the terms are summed in chunks with TT-SVD rounding in between."""
     from .tt import add, round_svd, scale

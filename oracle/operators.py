@@ -80,3 +80,50 @@ def dense_from_tt_matrix(A: List[np.ndarray]) -> np.ndarray:
         M = np.einsum('ijx,xaby->iajby', M, D).reshape(rows * m, cols * n, Rr)
         rows, cols = rows * m, cols * n
     return M[:, :, 0]
+
+
+def tt_markov(Q: List[np.ndarray], J: np.ndarray, P: np.ndarray, rate: float) -> List[np.ndarray]:
+    """TT-matrix of the synchronized Markov chain of Sec. 5.1.2:
+        A = sum_k Q_k  +  rate sum_{k<d-1} (J_k x J_{k+1})  -  rate sum_{k<d-1} (P_k x P_{k+1})
+    (each term acting on the named modes, identity elsewhere): the independent
+    walks Q = (+)_k Q_k, the joint transitions W of neighbouring systems and the
+    row-sum correction D = diag(W 1).  Four states per bond: 0 = nothing placed,
+    1 = one term complete, 2 = a J of a pair placed, 3 = a P of a pair placed;
+    a pair opened at mode k must close at mode k+1.  The bond rank is 4 for
+    every d (the paper's remark that the rank grows with d describes a
+    representation that adds the terms one by one)."""
+    d = len(Q)
+    n = Q[0].shape[0]
+    I = np.eye(n)
+    cores = []
+    for k in range(d):
+        D = np.zeros((4, n, n, 4))
+        D[0, :, :, 0] = I
+        D[1, :, :, 1] = I
+        D[0, :, :, 1] = Q[k]
+        D[0, :, :, 2] = rate * J
+        D[0, :, :, 3] = -rate * P
+        D[2, :, :, 1] = J
+        D[3, :, :, 1] = P
+        if k == 0:
+            D = D[0:1]
+        if k == d - 1:
+            D = D[:, :, :, 1:2]
+        cores.append(np.ascontiguousarray(D))
+    return cores
+
+
+def dense_markov(Q: List[np.ndarray], J: np.ndarray, P: np.ndarray, rate: float) -> np.ndarray:
+    """Explicit matrix of tt_markov by Kronecker products (mode 0 slowest); tiny sizes."""
+    d = len(Q)
+    n = Q[0].shape[0]
+
+    def place(mats):
+        M = np.ones((1, 1))
+        for k in range(d):
+            M = np.kron(M, mats.get(k, np.eye(n)))
+        return M
+    A = sum(place({k: Q[k]}) for k in range(d))
+    for k in range(d - 1):
+        A = A + rate * place({k: J, k + 1: J}) - rate * place({k: P, k + 1: P})
+    return A

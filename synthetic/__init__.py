@@ -70,6 +70,62 @@ def potential_1d(n: int) -> np.ndarray:
     return np.diag(np.sin(np.pi * x))
 
 
+def convdiff_1d(n: int, K: float = 1e-2, w: float = 1e-2, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Mode matrix of the convection-diffusion problem of Sec. 5.1.1 on [lo, hi]
+    with h = (hi - lo)/(n+1), written for the SPD-signed system A x = f:
+    K/h^2 tridiag(-1, 2, -1) + w/h (I - superdiagonal), i.e. minus the paper's
+    L + D_i (its equation reads (sum_i (L + D_i)) x + f = 0)."""
+    h = (hi - lo) / (n + 1.0)
+    A = np.zeros((n, n))
+    idx = np.arange(n)
+    A[idx, idx] = 2.0 * K / h ** 2 + w / h
+    A[idx[:-1], idx[:-1] + 1] = -K / h ** 2 - w / h
+    A[idx[1:], idx[1:] - 1] = -K / h ** 2
+    return A
+
+
+def gauss_source_1d(n: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """exp(-10 x_i^2) at the interior grid points x_i = lo + i h, i = 1..n: one
+    factor of the rank-1 source f(x) = exp(-10 ||x||^2) of Sec. 5.1.1."""
+    h = (hi - lo) / (n + 1.0)
+    x = lo + h * np.arange(1, n + 1)
+    return np.exp(-10.0 * x ** 2)
+
+
+def markov_rates(rng: np.random.Generator, d: int, n: int):
+    """Forward and backward rates of the d random walks of Sec. 5.1.2, each drawn
+    independently from U[1, 2]: eta[k][i] from state i to i+1, mu[k][i] from
+    state i to i-1 (0-based states 0..n-1)."""
+    eta = [rng.uniform(1.0, 2.0, size=n) for _ in range(d)]
+    mu = [rng.uniform(1.0, 2.0, size=n) for _ in range(d)]
+    return eta, mu
+
+
+def markov_walk_1d(eta: np.ndarray, mu: np.ndarray) -> np.ndarray:
+    """Generator block Q_i of one random walk, row = source state, column =
+    target state: Q[i, i+1] = eta[i], Q[i, i-1] = mu[i], Q[i, i] = -(eta[i] +
+    mu[i]).  The walk's boundary moves (eta of the last state, mu of the first)
+    leave the chain, so -Q_i is a nonsingular M-matrix."""
+    n = len(eta)
+    Q = np.zeros((n, n))
+    idx = np.arange(n)
+    Q[idx, idx] = -(eta + mu)
+    Q[idx[:-1], idx[:-1] + 1] = eta[:-1]
+    Q[idx[1:], idx[1:] - 1] = mu[1:]
+    return Q
+
+
+def markov_sync_1d(n: int):
+    """The two one-entry factors of a synchronized joint failure of Sec. 5.1.2:
+    J moves a system from state n-2 to state n-1 (0-based), P = e_{n-2} e_{n-2}^T
+    is the matching diagonal entry of the row-sum correction D."""
+    J = np.zeros((n, n))
+    J[n - 2, n - 1] = 1.0
+    P = np.zeros((n, n))
+    P[n - 2, n - 2] = 1.0
+    return J, P
+
+
 # ----------------------------------------------------------------------------
 # Random TT data
 # ----------------------------------------------------------------------------
@@ -268,3 +324,20 @@ def config_c5(d: int = 20, n: int = 128, s: int = 2000, maxit: int = 1000) -> Wo
     Y = tt_drm(rng, ns, rho, 0, d - 1)
     return Workload(f"potential_d{d}_n{n}", d, ns, [[L] * d, [V] * d], 3, b, S, X, Y, rx, rho, 128,
                     s, 1, maxit, 0, 1e-6, 1e-7, 0.1)
+
+
+def markov_chain(d: int, n: int, *, config_index: int = 5, rate: float = 0.1, s: int = 200,
+                 cap: int = 64, oversample: int = 20, stream: int = 0) -> dict:
+    """Synchronized Markov chain of Sec. 5.1.2: d random walks with n states and
+    U[1, 2] rates, neighbouring systems failing together at `rate`; right-hand
+    side e (all ones, rank 1).  Returns the problem data (per-mode generator
+    blocks Q_k, the one-entry factors J and P) and the sketches of the method."""
+    rng = rng_for(config_index, stream)
+    ns = [n] * d
+    eta, mu = markov_rates(rng, d, n)
+    Q = [markov_walk_1d(e, m) for e, m in zip(eta, mu)]
+    J, P = markov_sync_1d(n)
+    b = [np.ones((1, n, 1)) for _ in range(d)]
+    S, X, Y, rx, rho = _sketches(rng, ns, s, cap, oversample)
+    return dict(d=d, n=n, ns=ns, Q=Q, J=J, P=P, rate=rate, b=b, S=S, X=X, Y=Y, rx=rx, rho=rho, s=s,
+                cap=cap)
