@@ -50,11 +50,22 @@ enum {
     TTSG_OK = 0,
     TTSG_NOT_CONVERGED = 1, /* iteration budget spent before the true residual met tol */
     TTSG_BREAKDOWN = 2,     /* h_{k+1,k} = 0: the Krylov space is invariant, solution exact */
+    TTSG_RANK_CAPPED = 3,   /* converged, but a basis rounding was limited by the rank cap
+                               (maxrank of Sec. 4.2) rather than by its tolerance */
     TTSG_ERR_ARG = 1,       /* returned negated: bad sizes, ranks or pointers */
     TTSG_ERR_CAPACITY = 2,  /* an output capacity is smaller than required */
     TTSG_ERR_WS = 3,        /* workspace too small */
-    TTSG_ERR_NONFINITE = 4, /* a NaN/Inf appeared in the iteration */
-    TTSG_ERR_HIP = 5        /* a HIP runtime call failed (see ttsg_last_error) */
+    TTSG_ERR_NONFINITE = 4, /* a NaN/Inf appeared in the inputs or the iteration */
+    TTSG_ERR_HIP = 5,       /* a HIP runtime call failed (see ttsg_last_error) */
+    TTSG_ERR_DTYPE = 6      /* unknown precision / arithmetic mode */
+};
+
+/* Least-squares form of the sketched problem (Sec. 3.4). */
+enum {
+    TTSG_LS_PINV = 0,   /* y = (S A V_k)^+ S r0 (eq. pseudo_inv): W_k = S A V_k is formed */
+    TTSG_LS_WHITEN = 1  /* whitening: skinny QR of S V_{k+1} and the sketched Arnoldi
+                           relation (eq. sketchedArnoldi); y from eq. sketched_argmin2,
+                           the residual from eq. sketched_residualnorm.  W_k is not formed */
 };
 
 /* Arithmetic of the contraction kernels. */
@@ -136,6 +147,17 @@ int ttsg_round_rand(int32_t d, const int32_t* n,
                     double* const* out, int32_t* out_r, int32_t precision,
                     void* ws, size_t ws_bytes, ttsg_stream_t stream);
 
+/* Workspace bytes of ttsg_kr_sketch / ttsg_stta_sketch / ttsg_round_rand for
+ * these shapes (R may be NULL: no operator).  A workspace of at least this
+ * size, passed as (ws, ws_bytes), makes the call allocate no device memory.
+ * Returns 0 and writes *bytes, or a negative error. */
+int ttsg_kr_sketch_workspace_size(int32_t d, const int32_t* n, int32_t s, const int32_t* R, const int32_t* r,
+                                  int32_t precision, size_t* bytes);
+int ttsg_stta_sketch_workspace_size(int32_t d, const int32_t* n, const int32_t* rho, const int32_t* rx,
+                                    const int32_t* R, const int32_t* r, int32_t precision, size_t* bytes);
+int ttsg_round_rand_workspace_size(int32_t d, const int32_t* n, const int32_t* r, const int32_t* rho,
+                                   const int32_t* rx, int32_t precision, size_t* bytes);
+
 /* Deterministic TT-SVD rounding (Sec. 2.2) of x at relative tolerance tol,
  * ranks capped at maxrank (0 = none).  out cores have capacity r[k] x n[k] x
  * r[k+1] (rounding never increases ranks).  Synchronizes `stream`. */
@@ -181,7 +203,8 @@ typedef struct {
 enum { TTSG_PH_KR = 0, TTSG_PH_INNER = 1, TTSG_PH_STTA = 2, TTSG_PH_RECOVER = 3,
        TTSG_PH_TTSVD = 4, TTSG_PH_LS = 5, TTSG_PH_FINAL = 6, TTSG_PH_OTHER = 7 };
 
-/* Solve A x = b with x_0 = 0.  The sketches S (s rows), Y and X are supplied
+/* Solve A x = b with x_0 = 0 (ttsg_sgmres_solve_ex adds an initial guess, a
+ * right preconditioner and the whitened least squares).  The sketches S (s rows), Y and X are supplied
  * by the caller.  x: d DEVICE pointers with capacity rx[k] x n[k] x rx[k+1];
  * x_r: HOST int32[d+1] receives the solution ranks.  Returns TTSG_OK when the
  * FP64 true residual is <= tol, TTSG_NOT_CONVERGED when the budget ran out
@@ -229,6 +252,77 @@ typedef struct {
 
 int ttsg_sgmres_solve_batched(int32_t count, ttsg_system* systems, int32_t concurrency,
                               ttsg_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* TT-sPGMRES (Alg. 5) and the other solve options                            */
+/* ------------------------------------------------------------------------- */
+/* Exponential-sum right preconditioner (Sec. 4.1):
+ *   P^{-1} = sum_{j<zeta} alpha_j (x)_k exp(-beta_j M_k)  ~  (M_1 (+) .. (+) M_d)^{-1}.
+ * With it the iteration runs on A P^{-1} (Alg. 5): A P^{-1} v_k is never formed;
+ * its Khatri-Rao sketch, STTA sketch and inner products are sums over the zeta
+ * terms alpha_j A ((x)_k exp(-beta_j M_k) v_k), each an operator-fused sweep
+ * over v_k with its modes multiplied (ranks unchanged).  A cycle's recovered
+ * correction u enters the solution as x += P^{-1} u, formed by the same STTA
+ * streaming sum and rounded at final_tol.  The mode factors are computed once
+ * per solve on the GPU (scaling and squaring, FP64 matrix cores). */
+typedef struct {
+    /* initial guess x0 (x0 == NULL: x0 = 0): d DEVICE pointers, HOST ranks
+       x0_r[d+1], each rank <= rx; r0 = b - A x0 and the solution is x0 plus
+       the corrections (for Alg. 5, x0 guesses x itself, not P x). */
+    const int32_t* x0_r;
+    const double* const* x0;
+    /* preconditioner (zeta == 0: none).  alpha, beta: HOST arrays of zeta
+       values, beta ascending and >= 0 (ttsg_expsum gives both); M: d DEVICE
+       pointers to the n[k] x n[k] row-major mode matrices of the Kronecker
+       sum.  Signs of alpha are free (e.g. alpha < 0 preconditions -M). */
+    int32_t zeta;
+    const double* alpha;
+    const double* beta;
+    const double* const* M;
+    /* least-squares form: TTSG_LS_PINV (default) or TTSG_LS_WHITEN */
+    int32_t ls_mode;
+} ttsg_sgmres_ext;
+
+/* ttsg_sgmres_solve with the options above (ext == NULL: plain Alg. 4).
+ * Same arguments, ownership, synchronization and return values. */
+int ttsg_sgmres_solve_ex(int32_t d, const int32_t* n,
+                         const int32_t* R, const double* const* A,
+                         const int32_t* rb, const double* const* b,
+                         int32_t s, const double* const* S,
+                         const int32_t* rho, const double* const* Y,
+                         const int32_t* rx, const double* const* X,
+                         const ttsg_sgmres_opts* opts, const ttsg_sgmres_ext* ext,
+                         double* const* x, int32_t* x_r,
+                         ttsg_sgmres_info* info,
+                         void* ws, size_t ws_bytes, ttsg_stream_t stream);
+
+/* Bytes of workspace ttsg_sgmres_solve_ex needs for these shapes and options
+ * (the pointers may be NULL: only sizes are read).  Passing a workspace of at
+ * least this size makes the solve allocate no device memory.  Returns 0 and
+ * writes *bytes, or a negative error. */
+int ttsg_sgmres_workspace_size(int32_t d, const int32_t* n, const int32_t* R, const int32_t* rb, int32_t s,
+                               const int32_t* rho, const int32_t* rx, const ttsg_sgmres_opts* opts,
+                               const ttsg_sgmres_ext* ext, size_t* bytes);
+
+/* Exponential-sum coefficients (Sec. 4.1) with |z E(z) - 1| <= tol for every
+ * z in [zmin, zmax] (0 < zmin <= zmax, 0 < tol < 1), from the trapezoid rule
+ * on 1/z = int_R exp(u - e^u z) du (beta_j = e^{u_j}, alpha_j = h e^{u_j}).
+ * alpha, beta: HOST arrays of max_terms values.  Returns zeta (the number of
+ * terms written), -TTSG_ERR_CAPACITY when max_terms is too small, or
+ * -TTSG_ERR_ARG.  Pure host arithmetic; no GPU call. */
+int ttsg_expsum(double zmin, double zmax, double tol, int32_t max_terms, double* alpha, double* beta);
+
+/* P^{-1} x for the preconditioner above, rounded by the randomized streaming
+ * sum of Sec. 3.3: the STTA sketches of the zeta TTs alpha_j (x)_k
+ * exp(-beta_j M_k) x are summed, recovered (pseudo-inverse cutoff rcond) and
+ * TT-SVD rounded at relative tol with ranks capped at maxrank (0 = rx only).
+ * Shapes as ttsg_round_rand; out cores have capacity rx[k] x n[k] x rx[k+1];
+ * out_r: HOST int32[d+1].  Synchronizes `stream`. */
+int ttsg_precond_round(int32_t d, const int32_t* n, int32_t zeta, const double* alpha, const double* beta,
+                       const double* const* M, const int32_t* r, const double* const* x,
+                       const int32_t* rho, const double* const* Y, const int32_t* rx, const double* const* X,
+                       double tol, int32_t maxrank, double rcond, double* const* out, int32_t* out_r,
+                       void* ws, size_t ws_bytes, ttsg_stream_t stream);
 
 /* FP64 true residual ||b - A x|| / ||b|| through TT arithmetic on the GPU
  * (b - A x formed as a TT, its norm taken after QR orthogonalization).

@@ -61,7 +61,7 @@ hipStream_t S(ttsg_stream_t s) { return static_cast<hipStream_t>(s); }
 
 ttsg::Prec prec_of(int32_t precision) {
     TTSG_CHECK(precision == TTSG_PREC_F64 || precision == TTSG_PREC_MIXED || precision == TTSG_PREC_BF16,
-               TTSG_ERR_ARG, "unknown precision");
+               TTSG_ERR_DTYPE, "unknown precision");
     return precision == TTSG_PREC_F64 ? ttsg::Prec::F64
                                       : (precision == TTSG_PREC_MIXED ? ttsg::Prec::F32 : ttsg::Prec::BF16);
 }
@@ -92,6 +92,19 @@ int ttsg_matvec(int32_t d, const int32_t* n, const int32_t* R, const double* con
     });
 }
 
+static size_t kr_ws(int32_t d, const int32_t* n, int32_t s, const int32_t* R, const int32_t* r) {
+    size_t need = 0;
+    for (int mu = 0; mu < d; ++mu) {
+        const size_t Rl = R ? R[mu] : 1, Rr = R ? R[mu + 1] : 1;
+        need += ((size_t)s * Rl * n[mu] * Rr * 8 + 256);              // S A (or S) and its f32 copy
+        need += ((size_t)r[mu] * n[mu] * r[mu + 1] * 4 + 256);        // x in f32
+        need += ((size_t)s * Rr * r[mu] * n[mu] * 8 + 256);           // X buffer
+        need += 2 * ((size_t)s * Rr * r[mu + 1] * 8 + 256);           // P buffers
+    }
+    need += (size_t)s * 8 * 4 + 4096;
+    return need * 2 + kSplitSlack;
+}
+
 int ttsg_kr_sketch(int32_t d, const int32_t* n, int32_t s, const double* const* Sf, const int32_t* R,
                    const double* const* A, const int32_t* r, const double* const* x, double* w, int32_t precision,
                    void* ws, size_t ws_bytes, ttsg_stream_t stream) {
@@ -110,15 +123,7 @@ int ttsg_kr_sketch(int32_t d, const int32_t* n, int32_t s, const double* const* 
         const ttsg::Prec p = prec_of(precision);
         std::vector<int> RR(d + 1, 1);
         if (op) RR = vec(R, d + 1);
-        size_t need = 0;
-        for (int mu = 0; mu < d; ++mu) {
-            need += ((size_t)s * RR[mu] * n[mu] * RR[mu + 1] * 8 + 256);           // SA
-            need += ((size_t)r[mu] * n[mu] * r[mu + 1] * 4 + 256);                  // x in f32
-            need += ((size_t)s * RR[mu + 1] * r[mu] * n[mu] * 8 + 256);             // X buffer
-            need += 2 * ((size_t)s * RR[mu + 1] * r[mu + 1] * 8 + 256);             // P buffers
-        }
-        need += (size_t)s * 8 * 4 + 4096;
-        ttsg::Workspace W(ws, ws_bytes, (need * 2) + kSplitSlack, S(stream));
+        ttsg::Workspace W(ws, ws_bytes, kr_ws(d, n, s, op ? R : nullptr, r), S(stream));
         ttsg::Arena& ar = W.arena;
         std::vector<const void*> SA(d), xs(d);
         for (int mu = 0; mu < d; ++mu) {
@@ -143,7 +148,6 @@ int ttsg_kr_sketch(int32_t d, const int32_t* n, int32_t s, const double* const* 
             }
         }
         ttsg::kr_sketch_run(p, d, n, s, RR, SA, vec(r, d + 1), xs, w, ar, S(stream));
-        TTSG_HIP(hipStreamSynchronize(S(stream)));
         return 0;
     });
 }
@@ -215,9 +219,21 @@ int ttsg_stta_sketch(int32_t d, const int32_t* n, const int32_t* rho, const doub
         }
         ttsg::Workspace W(ws, ws_bytes, (stta_ws(d, n, rho, rx, A ? R : nullptr, r)) + kSplitSlack, S(stream));
         stta_common(d, n, rho, Y, rx, X, A ? R : nullptr, A, r, x, Psi, Omega, precision, W.arena, S(stream));
-        TTSG_HIP(hipStreamSynchronize(S(stream)));
         return 0;
     });
+}
+
+static size_t round_rand_ws(int32_t d, const int32_t* n, const int32_t* r, const int32_t* rho, const int32_t* rx) {
+    size_t sk = 0;
+    for (int mu = 0; mu < d; ++mu) sk += (size_t)rho[mu] * n[mu] * rx[mu + 1] + (size_t)rho[mu] * rx[mu] + 64;
+    size_t core = 0, rmax = 1;
+    for (int mu = 0; mu < d; ++mu) {
+        core = std::max(core, (size_t)rx[mu] * n[mu] * rx[mu + 1]);
+        rmax = std::max(rmax, (size_t)std::max(rho[mu], rx[mu]));
+    }
+    const size_t need = stta_ws(d, n, rho, rx, nullptr, r) + sk * 8 + (8 * core + 12 * rmax * rmax) * 8 +
+                        (size_t)d * 16 * rmax * rmax * 8 + (4 << 20) + ttsg::tt_svd_extra_bytes(d, n, rx);
+    return need + kSplitSlack;
 }
 
 int ttsg_round_rand(int32_t d, const int32_t* n, const int32_t* r, const double* const* x, const int32_t* rho,
@@ -236,16 +252,7 @@ int ttsg_round_rand(int32_t d, const int32_t* n, const int32_t* r, const double*
         check_ptrs(d, (const void* const*)x, "round_rand x");
         check_ptrs(d, (const void* const*)out, "round_rand out");
         TTSG_CHECK(out_r != nullptr, TTSG_ERR_ARG, "round_rand: null out_r");
-        size_t sk = 0;
-        for (int mu = 0; mu < d; ++mu) sk += (size_t)rho[mu] * n[mu] * rx[mu + 1] + (size_t)rho[mu] * rx[mu] + 64;
-        size_t core = 0, rmax = 1;
-        for (int mu = 0; mu < d; ++mu) {
-            core = std::max(core, (size_t)rx[mu] * n[mu] * rx[mu + 1]);
-            rmax = std::max(rmax, (size_t)std::max(rho[mu], rx[mu]));
-        }
-        const size_t need = stta_ws(d, n, rho, rx, nullptr, r) + sk * 8 + (8 * core + 12 * rmax * rmax) * 8 +
-                            (size_t)d * 16 * rmax * rmax * 8 + (4 << 20) + ttsg::tt_svd_extra_bytes(d, n, rx);
-        ttsg::Workspace W(ws, ws_bytes, (need) + kSplitSlack, S(stream));
+        ttsg::Workspace W(ws, ws_bytes, round_rand_ws(d, n, r, rho, rx), S(stream));
         ttsg::Arena& ar = W.arena;
         std::vector<double*> psi(d), om(d - 1);
         for (int mu = 0; mu < d; ++mu) psi[mu] = ar.get<double>((int64_t)rho[mu] * n[mu] * rx[mu + 1]);
@@ -259,6 +266,45 @@ int ttsg_round_rand(int32_t d, const int32_t* n, const int32_t* r, const double*
         ttsg::tt_svd_inplace(d, n, rr, o, caps, tol, maxrank, ar, S(stream), nullptr);
         for (int k = 0; k <= d; ++k) out_r[k] = rr[k];
         TTSG_HIP(hipStreamSynchronize(S(stream)));
+        return 0;
+    });
+}
+
+int ttsg_kr_sketch_workspace_size(int32_t d, const int32_t* n, int32_t s, const int32_t* R, const int32_t* r,
+                                  int32_t precision, size_t* bytes) {
+    return guarded([&]() {
+        check_shape(d, n, r, "kr_sketch x");
+        TTSG_CHECK(s >= 1 && bytes != nullptr, TTSG_ERR_ARG, "kr_sketch_workspace_size: bad arguments");
+        (void)prec_of(precision);
+        if (R) check_shape(d, n, R, "kr_sketch A");
+        *bytes = kr_ws(d, n, s, R, r);
+        return 0;
+    });
+}
+
+int ttsg_stta_sketch_workspace_size(int32_t d, const int32_t* n, const int32_t* rho, const int32_t* rx,
+                                    const int32_t* R, const int32_t* r, int32_t precision, size_t* bytes) {
+    return guarded([&]() {
+        check_shape(d, n, r, "stta x");
+        check_shape(d, n, rho, "stta rho");
+        check_shape(d, n, rx, "stta rx");
+        TTSG_CHECK(bytes != nullptr, TTSG_ERR_ARG, "stta_sketch_workspace_size: null output");
+        (void)prec_of(precision);
+        if (R) check_shape(d, n, R, "stta A");
+        *bytes = stta_ws(d, n, rho, rx, R, r) + kSplitSlack;
+        return 0;
+    });
+}
+
+int ttsg_round_rand_workspace_size(int32_t d, const int32_t* n, const int32_t* r, const int32_t* rho,
+                                   const int32_t* rx, int32_t precision, size_t* bytes) {
+    return guarded([&]() {
+        check_shape(d, n, r, "round_rand x");
+        check_shape(d, n, rho, "round_rand rho");
+        check_shape(d, n, rx, "round_rand rx");
+        TTSG_CHECK(bytes != nullptr, TTSG_ERR_ARG, "round_rand_workspace_size: null output");
+        (void)prec_of(precision);
+        *bytes = round_rand_ws(d, n, r, rho, rx);
         return 0;
     });
 }
@@ -408,50 +454,223 @@ int ttsg_tt_axpby(int32_t d, const int32_t* n, double alpha, const int32_t* rx, 
     });
 }
 
-int ttsg_sgmres_solve(int32_t d, const int32_t* n, const int32_t* R, const double* const* A, const int32_t* rb,
-                      const double* const* b, int32_t s, const double* const* Sf, const int32_t* rho,
-                      const double* const* Y, const int32_t* rx, const double* const* X,
-                      const ttsg_sgmres_opts* opts, double* const* x, int32_t* x_r, ttsg_sgmres_info* info, void* ws,
-                      size_t ws_bytes, ttsg_stream_t stream) {
-    return guarded([&]() {
-        check_shape(d, n, R, "sgmres A");
-        check_shape(d, n, rb, "sgmres b");
-        check_shape(d, n, rho, "sgmres rho");
-        check_shape(d, n, rx, "sgmres rx");
-        TTSG_CHECK(d >= 2, TTSG_ERR_ARG, "sgmres: d must be >= 2");
-        TTSG_CHECK(opts != nullptr, TTSG_ERR_ARG, "sgmres: null options");
-        TTSG_CHECK(opts->maxit >= 1, TTSG_ERR_ARG, "sgmres: maxit < 1");
-        TTSG_CHECK(opts->tol > 0.0 && opts->round_tol >= 0.0, TTSG_ERR_ARG, "sgmres: bad tolerance");
-        TTSG_CHECK(opts->q >= 1 && opts->q <= 7, TTSG_ERR_ARG, "sgmres: q must be in 1..7");
-        (void)prec_of(opts->precision);
-        TTSG_CHECK(s >= 1, TTSG_ERR_ARG, "sgmres: s < 1");
-        for (int b2 = 1; b2 < d; ++b2) TTSG_CHECK(rho[b2] >= rx[b2], TTSG_ERR_ARG, "sgmres: rho_b < rx_b");
+}  // extern "C"
+
+namespace {
+
+// Validate the arguments of a solve and collect them; pointer arrays may be
+// NULL when only sizes are needed (workspace query).
+ttsg::SolverInputs solver_inputs(int32_t d, const int32_t* n, const int32_t* R, const double* const* A,
+                                 const int32_t* rb, const double* const* b, int32_t s, const double* const* Sf,
+                                 const int32_t* rho, const double* const* Y, const int32_t* rx,
+                                 const double* const* X, const ttsg_sgmres_opts* opts, const ttsg_sgmres_ext* ext,
+                                 bool sizes_only) {
+    check_shape(d, n, R, "sgmres A");
+    check_shape(d, n, rb, "sgmres b");
+    check_shape(d, n, rho, "sgmres rho");
+    check_shape(d, n, rx, "sgmres rx");
+    TTSG_CHECK(d >= 2, TTSG_ERR_ARG, "sgmres: d must be >= 2");
+    TTSG_CHECK(opts != nullptr, TTSG_ERR_ARG, "sgmres: null options");
+    TTSG_CHECK(opts->maxit >= 1, TTSG_ERR_ARG, "sgmres: maxit < 1");
+    TTSG_CHECK(opts->tol > 0.0 && opts->round_tol >= 0.0, TTSG_ERR_ARG, "sgmres: bad tolerance");
+    TTSG_CHECK(opts->q >= 1 && opts->q <= 7, TTSG_ERR_ARG, "sgmres: q must be in 1..7");
+    (void)prec_of(opts->precision);
+    TTSG_CHECK(s >= 1, TTSG_ERR_ARG, "sgmres: s < 1");
+    for (int b2 = 1; b2 < d; ++b2) TTSG_CHECK(rho[b2] >= rx[b2], TTSG_ERR_ARG, "sgmres: rho_b < rx_b");
+    for (int b2 = 0; b2 <= d; ++b2)
+        TTSG_CHECK(rb[b2] <= rx[b2], TTSG_ERR_CAPACITY, "sgmres: rank of b exceeds the STTA target ranks");
+    if (!sizes_only) {
         check_ptrs(d, (const void* const*)A, "sgmres A");
         check_ptrs(d, (const void* const*)b, "sgmres b");
         check_ptrs(d, (const void* const*)Sf, "sgmres S");
         check_ptrs(d - 1, (const void* const*)Y, "sgmres Y");
         check_ptrs(d - 1, (const void* const*)X, "sgmres X");
-        check_ptrs(d, (const void* const*)x, "sgmres x");
-        TTSG_CHECK(x_r != nullptr, TTSG_ERR_ARG, "sgmres: null x_r");
-        for (int b2 = 0; b2 <= d; ++b2)
-            TTSG_CHECK(rb[b2] <= rx[b2], TTSG_ERR_CAPACITY, "sgmres: rank of b exceeds the STTA target ranks");
-        ttsg::SolverInputs in;
-        in.d = d;
-        in.n = n;
-        in.R = vec(R, d + 1);
+    }
+    ttsg::SolverInputs in;
+    in.d = d;
+    in.n = n;
+    in.R = vec(R, d + 1);
+    in.rb = vec(rb, d + 1);
+    in.s = s;
+    in.rho = vec(rho, d + 1);
+    in.rx = vec(rx, d + 1);
+    if (!sizes_only) {
         in.A.assign(A, A + d);
-        in.rb = vec(rb, d + 1);
         in.b.assign(b, b + d);
-        in.s = s;
         in.S.assign(Sf, Sf + d);
-        in.rho = vec(rho, d + 1);
-        in.rx = vec(rx, d + 1);
         in.Y.assign(Y, Y + d - 1);
         in.X.assign(X, X + d - 1);
-        in.o = *opts;
-        if (in.o.rcond <= 0.0) in.o.rcond = 1e-12;
-        if (in.o.stop_safety <= 0.0) in.o.stop_safety = 1.0;
+    }
+    in.o = *opts;
+    if (in.o.rcond <= 0.0) in.o.rcond = 1e-12;
+    if (in.o.stop_safety <= 0.0) in.o.stop_safety = 1.0;
+    if (ext != nullptr) {
+        TTSG_CHECK(ext->ls_mode == TTSG_LS_PINV || ext->ls_mode == TTSG_LS_WHITEN, TTSG_ERR_ARG,
+                   "sgmres: unknown least-squares mode");
+        in.ls_mode = ext->ls_mode;
+        if (ext->x0 != nullptr || ext->x0_r != nullptr) {
+            TTSG_CHECK(ext->x0 != nullptr && ext->x0_r != nullptr, TTSG_ERR_ARG, "sgmres: x0 needs cores and ranks");
+            check_shape(d, n, ext->x0_r, "sgmres x0");
+            for (int b2 = 0; b2 <= d; ++b2)
+                TTSG_CHECK(ext->x0_r[b2] <= rx[b2], TTSG_ERR_CAPACITY, "sgmres: rank of x0 exceeds the STTA target ranks");
+            in.x0_r = vec(ext->x0_r, d + 1);
+            if (!sizes_only) {
+                check_ptrs(d, (const void* const*)ext->x0, "sgmres x0");
+                in.x0.assign(ext->x0, ext->x0 + d);
+            }
+        }
+        TTSG_CHECK(ext->zeta >= 0 && ext->zeta <= 4096, TTSG_ERR_ARG, "sgmres: zeta out of range");
+        if (ext->zeta > 0) {
+            TTSG_CHECK(ext->alpha != nullptr && ext->beta != nullptr, TTSG_ERR_ARG,
+                       "sgmres: preconditioner needs alpha and beta");
+            in.zeta = ext->zeta;
+            in.alpha.assign(ext->alpha, ext->alpha + ext->zeta);
+            in.beta.assign(ext->beta, ext->beta + ext->zeta);
+            for (int j = 0; j < ext->zeta; ++j) {
+                TTSG_CHECK(std::isfinite(in.alpha[j]) && std::isfinite(in.beta[j]) && in.beta[j] >= 0.0,
+                           TTSG_ERR_ARG, "sgmres: preconditioner coefficients must be finite, beta >= 0");
+                TTSG_CHECK(j == 0 || in.beta[j] >= in.beta[j - 1], TTSG_ERR_ARG,
+                           "sgmres: preconditioner beta must be ascending");
+            }
+            if (!sizes_only) {
+                check_ptrs(d, (const void* const*)ext->M, "sgmres preconditioner M");
+                in.M.assign(ext->M, ext->M + d);
+            }
+        }
+    }
+    return in;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ttsg_sgmres_solve_ex(int32_t d, const int32_t* n, const int32_t* R, const double* const* A, const int32_t* rb,
+                         const double* const* b, int32_t s, const double* const* Sf, const int32_t* rho,
+                         const double* const* Y, const int32_t* rx, const double* const* X,
+                         const ttsg_sgmres_opts* opts, const ttsg_sgmres_ext* ext, double* const* x, int32_t* x_r,
+                         ttsg_sgmres_info* info, void* ws, size_t ws_bytes, ttsg_stream_t stream) {
+    return guarded([&]() {
+        ttsg::SolverInputs in = solver_inputs(d, n, R, A, rb, b, s, Sf, rho, Y, rx, X, opts, ext, false);
+        check_ptrs(d, (const void* const*)x, "sgmres x");
+        TTSG_CHECK(x_r != nullptr, TTSG_ERR_ARG, "sgmres: null x_r");
         return ttsg::sgmres_solve(in, x, x_r, info, ws, ws_bytes, S(stream));
+    });
+}
+
+int ttsg_sgmres_solve(int32_t d, const int32_t* n, const int32_t* R, const double* const* A, const int32_t* rb,
+                      const double* const* b, int32_t s, const double* const* Sf, const int32_t* rho,
+                      const double* const* Y, const int32_t* rx, const double* const* X,
+                      const ttsg_sgmres_opts* opts, double* const* x, int32_t* x_r, ttsg_sgmres_info* info, void* ws,
+                      size_t ws_bytes, ttsg_stream_t stream) {
+    return ttsg_sgmres_solve_ex(d, n, R, A, rb, b, s, Sf, rho, Y, rx, X, opts, nullptr, x, x_r, info, ws, ws_bytes,
+                                stream);
+}
+
+int ttsg_sgmres_workspace_size(int32_t d, const int32_t* n, const int32_t* R, const int32_t* rb, int32_t s,
+                               const int32_t* rho, const int32_t* rx, const ttsg_sgmres_opts* opts,
+                               const ttsg_sgmres_ext* ext, size_t* bytes) {
+    return guarded([&]() {
+        TTSG_CHECK(bytes != nullptr, TTSG_ERR_ARG, "workspace_size: null output");
+        ttsg::SolverInputs in = solver_inputs(d, n, R, nullptr, rb, nullptr, s, nullptr, rho, nullptr, rx, nullptr,
+                                              opts, ext, true);
+        *bytes = ttsg::sgmres_workspace(in);
+        return 0;
+    });
+}
+
+int ttsg_expsum(double zmin, double zmax, double tol, int32_t max_terms, double* alpha, double* beta) {
+    return guarded([&]() {
+        TTSG_CHECK(alpha != nullptr && beta != nullptr && max_terms >= 1, TTSG_ERR_ARG, "expsum: bad output arrays");
+        const int z = ttsg::expsum_coefficients(zmin, zmax, tol, max_terms, alpha, beta);
+        TTSG_CHECK(z != -1, TTSG_ERR_ARG, "expsum: need 0 < zmin <= zmax and 0 < tol < 1");
+        TTSG_CHECK(z > 0, TTSG_ERR_CAPACITY, "expsum: more terms needed than max_terms");
+        return z;
+    });
+}
+
+int ttsg_precond_round(int32_t d, const int32_t* n, int32_t zeta, const double* alpha, const double* beta,
+                       const double* const* M, const int32_t* r, const double* const* x, const int32_t* rho,
+                       const double* const* Y, const int32_t* rx, const double* const* X, double tol, int32_t maxrank,
+                       double rcond, double* const* out, int32_t* out_r, void* ws, size_t ws_bytes,
+                       ttsg_stream_t stream) {
+    return guarded([&]() {
+        check_shape(d, n, r, "precond_round x");
+        check_shape(d, n, rho, "precond_round rho");
+        check_shape(d, n, rx, "precond_round rx");
+        TTSG_CHECK(d >= 2, TTSG_ERR_ARG, "precond_round: d must be >= 2");
+        TTSG_CHECK(zeta >= 1 && alpha != nullptr && beta != nullptr, TTSG_ERR_ARG, "precond_round: no terms");
+        TTSG_CHECK(tol >= 0.0 && rcond >= 0.0, TTSG_ERR_ARG, "precond_round: negative tolerance");
+        for (int b2 = 1; b2 < d; ++b2) TTSG_CHECK(rho[b2] >= rx[b2], TTSG_ERR_ARG, "precond_round: rho_b < rx_b");
+        check_ptrs(d, (const void* const*)M, "precond_round M");
+        check_ptrs(d, (const void* const*)x, "precond_round x");
+        check_ptrs(d - 1, (const void* const*)Y, "precond_round Y");
+        check_ptrs(d - 1, (const void* const*)X, "precond_round X");
+        check_ptrs(d, (const void* const*)out, "precond_round out");
+        TTSG_CHECK(out_r != nullptr, TTSG_ERR_ARG, "precond_round: null out_r");
+        for (int j = 0; j < zeta; ++j)
+            TTSG_CHECK(std::isfinite(alpha[j]) && std::isfinite(beta[j]) && beta[j] >= 0.0 &&
+                           (j == 0 || beta[j] >= beta[j - 1]),
+                       TTSG_ERR_ARG, "precond_round: beta must be finite, >= 0 and ascending");
+        size_t sk = 0, core = 0, rmax = 1, ee = 0;
+        for (int mu = 0; mu < d; ++mu) {
+            sk += (size_t)rho[mu] * n[mu] * rx[mu + 1] + (size_t)rho[mu] * rx[mu] + 64;
+            core = std::max(core, (size_t)std::max(rx[mu], r[mu]) * n[mu] * std::max(rx[mu + 1], r[mu + 1]));
+            rmax = std::max(rmax, (size_t)std::max(rho[mu], rx[mu]));
+            ee += (size_t)zeta * n[mu] * n[mu] * 3 + 64;
+        }
+        size_t zc = 0;
+        for (int mu = 0; mu < d; ++mu) zc += (size_t)r[mu] * n[mu] * r[mu + 1] + 64;
+        const size_t need = stta_ws(d, n, rho, rx, nullptr, r) + 2 * sk * 8 + ee * 8 + zc * 8 +
+                            (8 * core + 12 * rmax * rmax) * 8 + (size_t)d * 16 * rmax * rmax * 8 + (4 << 20) +
+                            ttsg::tt_svd_extra_bytes(d, n, rx);
+        ttsg::Workspace W(ws, ws_bytes, need + kSplitSlack, S(stream));
+        ttsg::Arena& ar = W.arena;
+        std::vector<double*> Eb(d), z(d);
+        for (int mu = 0; mu < d; ++mu) Eb[mu] = ar.get<double>((int64_t)zeta * n[mu] * n[mu]);
+        for (int mu = 0; mu < d; ++mu) z[mu] = ar.get<double>((int64_t)r[mu] * n[mu] * r[mu + 1]);
+        std::vector<double*> psi(d), om(d - 1), pt(d), ot(d - 1);
+        for (int mu = 0; mu < d; ++mu) psi[mu] = ar.get<double>((int64_t)rho[mu] * n[mu] * rx[mu + 1]);
+        for (int b2 = 1; b2 < d; ++b2) om[b2 - 1] = ar.get<double>((int64_t)rho[b2] * rx[b2]);
+        for (int mu = 0; mu < d; ++mu) pt[mu] = ar.get<double>((int64_t)rho[mu] * n[mu] * rx[mu + 1]);
+        for (int b2 = 1; b2 < d; ++b2) ot[b2 - 1] = ar.get<double>((int64_t)rho[b2] * rx[b2]);
+        std::vector<const double*> Mv(M, M + d);
+        ttsg::mode_exponentials(zeta, beta, d, n, Mv, Eb, ar, S(stream));
+        ttsg::SketchOperands o;
+        o.p = ttsg::Prec::F64;
+        o.n = n;
+        o.d = d;
+        o.rho = vec(rho, d + 1);
+        o.rx = vec(rx, d + 1);
+        o.R.assign(d + 1, 1);
+        for (int k = 0; k < d - 1; ++k) {
+            o.Y.push_back(Y[k]);
+            o.X.push_back(X[k]);
+        }
+        const std::vector<int> rv = vec(r, d + 1);
+        std::vector<const double*> xv(x, x + d);
+        std::vector<const void*> zv(z.begin(), z.end());
+        for (int j = 0; j < zeta; ++j) {
+            std::vector<const double*> Ej(d);
+            for (int mu = 0; mu < d; ++mu) Ej[mu] = Eb[mu] + (int64_t)j * n[mu] * n[mu];
+            ttsg::mode_product_tt(d, n, rv, xv, Ej, alpha[j], z, S(stream), &ar);
+            ttsg::stta_sketch(o, rv, zv, (j == 0 ? psi : pt).data(), (j == 0 ? om : ot).data(), ar, S(stream));
+            if (j > 0) {
+                for (int mu = 0; mu < d; ++mu)
+                    ttsg::axpby((int64_t)rho[mu] * n[mu] * rx[mu + 1], 1.0, pt[mu], 1.0, psi[mu], S(stream));
+                for (int b2 = 1; b2 < d; ++b2)
+                    ttsg::axpby((int64_t)rho[b2] * rx[b2], 1.0, ot[b2 - 1], 1.0, om[b2 - 1], S(stream));
+            }
+        }
+        std::vector<const double*> cp(psi.begin(), psi.end()), co(om.begin(), om.end());
+        std::vector<int> rr;
+        std::vector<double*> o2(out, out + d);
+        ttsg::stta_recover(d, n, vec(rho, d + 1), vec(rx, d + 1), cp, co, rcond, o2, rr, ar, S(stream));
+        std::vector<int64_t> caps(d);
+        ttsg::tt_svd_inplace(d, n, rr, o2, caps, tol, maxrank, ar, S(stream), nullptr);
+        for (int k = 0; k <= d; ++k) out_r[k] = rr[k];
+        TTSG_HIP(hipStreamSynchronize(S(stream)));
+        return 0;
     });
 }
 

@@ -131,6 +131,9 @@ void gemm_cm_cm(int M, int N, int K, const double* A, int lda, const double* B, 
     contract(Prec::F64, d, A, B, C, st, ar);
 }
 
+// Bonds whose rank the cap (not the tolerance) decided, per host thread.
+thread_local int t_cap_events = 0;
+
 // Smallest k whose discarded tail is <= delta; at least 1; capped at maxrank.
 int trunc_rank(const std::vector<double>& s_desc, double delta, int maxrank) {
     int m = (int)s_desc.size();
@@ -143,7 +146,10 @@ int trunc_rank(const std::vector<double>& s_desc, double delta, int maxrank) {
             break;
         }
     k = std::max(k, 1);
-    if (maxrank > 0) k = std::min(k, maxrank);
+    if (maxrank > 0 && k > maxrank) {
+        k = maxrank;
+        ++t_cap_events;
+    }
     return k;
 }
 
@@ -681,6 +687,12 @@ double tt_norm_orth(int d, const int* n, std::vector<int>& r, const std::vector<
     double nrm = std::sqrt(read_scalar(scal, st));
     ar.release(mark);
     return nrm;
+}
+
+int take_rank_cap_events() {
+    const int v = t_cap_events;
+    t_cap_events = 0;
+    return v;
 }
 
 }  // namespace ttsg

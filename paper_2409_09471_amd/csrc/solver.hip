@@ -128,6 +128,64 @@ __global__ void k_nonfinite(int64_t n, const double* __restrict__ x, int* __rest
         if (!isfinite(x[i])) *flag = 1;
 }
 
+// out[t] = sum_j part[t * zeta + j] in order (the window coefficients h_{i,k}
+// of a preconditioned step are sums over the zeta terms of A P^{-1} v_k).
+__global__ void k_sum_terms(int nw, int zeta, const double* __restrict__ part, double* __restrict__ out) {
+    const int t = threadIdx.x;
+    if (t < nw) {
+        double a = 0.0;
+        for (int j = 0; j < zeta; ++j) a += part[t * zeta + j];
+        out[t] = a;
+    }
+}
+
+// Whitened least squares (Sec. 3.4).  T is the triangular factor of the QR of
+// S V (column-major, leading dimension ld; T(r, i) = T[i * ld + r]); the
+// sketched Arnoldi relation gives S A V_k = Q_{k+1} (T_{k+1} H_k), so y solves
+// min || T_{k+1} H_k y - beta e_1 || (eq. sketched_argmin2 with z = T_k y).
+// T_{k+1} H_k is upper Hessenberg: it is reduced by Givens rotations one column
+// per iteration, as in GMRES, and |g[k+1]| is the residual of
+// eq. sketched_residualnorm.
+__global__ void k_whiten_init(int len, const double* __restrict__ zz, double* __restrict__ g) {
+    for (int i = threadIdx.x; i < len; i += blockDim.x) g[i] = (i == 0) ? sqrt(zz[0]) : 0.0;
+}
+
+// Column k (0-based) of H: h[t] for basis indices k - nw + 1 + t (t < nw),
+// h_{k+1,k} = hk (has_next = 0 after a breakdown: no row k + 1).
+__global__ void k_whiten_step(int k, int ld, int nw, const double* __restrict__ T, const double* __restrict__ h,
+                              double hk, int has_next, double* __restrict__ Gr, double* __restrict__ cs,
+                              double* __restrict__ sn, double* __restrict__ g, double* __restrict__ res) {
+    if (threadIdx.x != 0) return;
+    double* col = Gr + (int64_t)k * ld;
+    const int lo = k - nw + 1;
+    double extra = 0.0;
+    for (int r = 0; r <= k + 1; ++r) {
+        double a = 0.0;
+        for (int t = 0; t < nw; ++t) {
+            const int i = lo + t;
+            if (r <= i) a += T[(int64_t)i * ld + r] * h[t];
+        }
+        if (has_next) a += T[(int64_t)(k + 1) * ld + r] * hk;
+        if (r <= k) col[r] = a;
+        else extra = a;
+    }
+    for (int j = 0; j < k; ++j) {
+        const double a = col[j], b = col[j + 1];
+        col[j] = cs[j] * a + sn[j] * b;
+        col[j + 1] = -sn[j] * a + cs[j] * b;
+    }
+    const double a = col[k], b = extra;
+    const double rr = hypot(a, b);
+    const double c = rr > 0.0 ? a / rr : 1.0, sg = rr > 0.0 ? b / rr : 0.0;
+    cs[k] = c;
+    sn[k] = sg;
+    col[k] = rr;
+    const double gk = g[k];
+    g[k] = c * gk;
+    g[k + 1] = -sg * gk;
+    res[0] = fabs(g[k + 1]);
+}
+
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384)); }
 
 // Block core of a sum of two TTs (Sec. 2.2 addition): for mode mu of d,
@@ -225,6 +283,29 @@ class SgmresSolver {
     std::vector<int> xcur_r_;
     double* scal_ = nullptr;
     int* flag_ = nullptr;
+    // preconditioner (Alg. 5): mode factors [zeta][n][n] per mode, the TT of
+    // one term alpha_j (x)_k E_jk v, its sketches and partial coefficients
+    bool pre_ = false;
+    std::vector<double*> Eblk_;
+    std::vector<double*> zbuf_;
+    std::vector<void*> zlp_;
+    double* skT_ = nullptr;
+    double* wtmp_ = nullptr;
+    double* htmp_ = nullptr;
+    // whitened least squares (Sec. 3.4): S V, its CGS2 QR and the Givens
+    // factorization of T H
+    bool white_ = false;
+    int ldw_ = 0;
+    double* SV_ = nullptr;
+    double* Q2_ = nullptr;
+    double* T2_ = nullptr;
+    double* c2_ = nullptr;
+    double* z2_ = nullptr;
+    double* res2_ = nullptr;
+    double* Gr_ = nullptr;
+    double* cs_ = nullptr;
+    double* sn_ = nullptr;
+    double* g_ = nullptr;
     Arena scratch_;    // main stream
     Arena scratchK_;   // side stream K: Khatri-Rao column + least squares
     Arena scratchH_;   // side stream H: sketch of v_k + coefficients h
@@ -323,7 +404,7 @@ void SgmresSolver::carve(Arena& ar) {
     Rls_ = ar.get<double>((int64_t)(m_ + 1) * (m_ + 1));
     cls_ = ar.get<double>(m_ + 1);
     z_ = ar.get<double>(in_.s);
-    lsres_ = ar.get<double>(m_ + 8);
+    lsres_ = ar.get<double>(std::max(m_ + 8, 1024));
     hco_ = ar.get<double>(16);
     y_ = ar.get<double>(m_ + 1);
     xsum_.assign(d, nullptr);
@@ -334,6 +415,34 @@ void SgmresSolver::carve(Arena& ar) {
     }
     scal_ = ar.get<double>(8);
     flag_ = ar.get<int>(8);
+    pre_ = in_.zeta > 0;
+    white_ = in_.ls_mode == TTSG_LS_WHITEN;
+    Eblk_.assign(d, nullptr);
+    zbuf_.assign(d, nullptr);
+    zlp_.assign(d, nullptr);
+    if (pre_) {
+        for (int mu = 0; mu < d; ++mu) {
+            Eblk_[mu] = ar.get<double>((int64_t)in_.zeta * in_.n[mu] * in_.n[mu]);
+            zbuf_[mu] = ar.get<double>(cap_[mu]);
+            if (p_ != Prec::F64) zlp_[mu] = ar.get<char>(cap_[mu] * es);
+        }
+        skT_ = ar.get<double>(sk_len_);
+        wtmp_ = ar.get<double>(in_.s);
+        htmp_ = ar.get<double>((int64_t)q_ * in_.zeta + 8);
+    }
+    if (white_) {
+        ldw_ = m_ + 2;
+        SV_ = ar.get<double>((int64_t)in_.s * ldw_);
+        Q2_ = ar.get<double>((int64_t)in_.s * ldw_);
+        T2_ = ar.get<double>((int64_t)ldw_ * ldw_);
+        c2_ = ar.get<double>(ldw_);
+        z2_ = ar.get<double>(in_.s);
+        res2_ = ar.get<double>(ldw_ + 8);
+        Gr_ = ar.get<double>((int64_t)ldw_ * ldw_);
+        cs_ = ar.get<double>(ldw_);
+        sn_ = ar.get<double>(ldw_);
+        g_ = ar.get<double>(ldw_ + 1);
+    }
 }
 
 }  // namespace ttsg
@@ -477,6 +586,13 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             Xv[k] = Xp_[k];
         }
     }
+    // Preconditioner (Alg. 5): the factors E_jk = exp(-beta_j M_k), once per solve
+    if (pre_) mode_exponentials(in_.zeta, in_.beta.data(), d, n, in_.M, Eblk_, scratch_, st_);
+    auto Eterm = [&](int j) {
+        std::vector<const double*> e(d);
+        for (int mu = 0; mu < d; ++mu) e[mu] = Eblk_[mu] + (int64_t)j * n[mu] * n[mu];
+        return e;
+    };
     // Precision map: the Khatri-Rao column w_k, S r0, ||S b|| and the stored
     // STTA sketches of the basis vectors (which build the final solution) are
     // FP64; the STTA sketch of A v_k and the coefficients h (which only shape
@@ -591,9 +707,68 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         return nr / nb;
     };
 
+    // One preconditioned step (Alg. 5): the Khatri-Rao column, the window
+    // coefficients h_{i,k} and the STTA sketch of A P^{-1} v_k, each a sum over
+    // the zeta terms alpha_j A ((x)_k E_jk v_k) in term order; the sketch of
+    // v_k itself (kept for the final solution) runs on stream H meanwhile.
+    // The combination with the window sketches follows as in Alg. 4.
+    auto precond_step = [&](int k, int vk, const std::vector<int>& window) {
+        const int nw = (int)window.size();
+        TTSG_HIP(hipStreamWaitEvent(side.h, side.v, 0));
+        sketch_slot(vk, sketches_ + (int64_t)k * sk_len_, scratchH_, side.h);
+        fill(1, 1.0, hco_, side.h);
+        TTSG_HIP(hipEventRecord(side.hd, side.h));
+        std::vector<const void*> z64(zbuf_.begin(), zbuf_.end());
+        std::vector<const void*> zop(d);
+        for (int mu = 0; mu < d; ++mu) zop[mu] = p_ == Prec::F64 ? static_cast<const void*>(zbuf_[mu]) : zlp_[mu];
+        std::vector<double*> pa, oa, pt, ot;
+        sk_ptrs(skA_, pa, oa);
+        sk_ptrs(skT_, pt, ot);
+        std::vector<const void*> SA64(SA64_.begin(), SA64_.end());
+        double* wcol = W_ + (int64_t)k * s;
+        for (int j = 0; j < in_.zeta; ++j) {
+            mode_product_tt(d, n, slot_r_[vk], cvec(slots_[vk]), Eterm(j), in_.alpha[j], zbuf_, st_, &scratch_);
+            if (p_ != Prec::F64)
+                for (int mu = 0; mu < d; ++mu)
+                    convert_f64_f32((int64_t)slot_r_[vk][mu] * n[mu] * slot_r_[vk][mu + 1], zbuf_[mu],
+                                    static_cast<float*>(zlp_[mu]), st_);
+            if (!white_) {
+                kr_sketch_run(Prec::F64, d, n, s, in_.R, SA64, slot_r_[vk], z64, j == 0 ? wcol : wtmp_, scratch_, st_);
+                if (j > 0) axpby(s, 1.0, wtmp_, 1.0, wcol, st_);
+            }
+            for (int t = 0; t < nw; ++t)
+                inner_run(p_, d, n, in_.R, Dv, slot_r_[vk], zop, slot_r_[window[t]], slot_ops(window[t]),
+                          htmp_ + t * in_.zeta + j, scratch_, st_);
+            stta_sketch(so_op, slot_r_[vk], zop, (j == 0 ? pa : pt).data(), (j == 0 ? oa : ot).data(), scratch_, st_,
+                        &sk_side);
+            if (j > 0) axpby(sk_len_, 1.0, skT_, 1.0, skA_, st_);
+        }
+        hipLaunchKernelGGL(k_sum_terms, dim3(1), dim3(64), 0, st_, nw, in_.zeta, htmp_, hco_ + 1);
+        TTSG_HIP(hipGetLastError());
+        if (!white_) {
+            hipLaunchKernelGGL(k_ls_append, dim3(1), dim3(LS_THREADS), 0, st_, s, k, m_ + 1, W_, Q_, Rls_, cls_, z_,
+                               lsres_);
+            TTSG_HIP(hipGetLastError());
+        }
+        TTSG_HIP(hipStreamWaitEvent(st_, side.hd, 0));
+        std::vector<const double*> xs(1 + nw);
+        std::vector<double> sg(1 + nw, -1.0);
+        xs[0] = skA_;
+        sg[0] = 1.0;
+        for (int t = 0; t < nw; ++t) xs[1 + t] = sketches_ + (int64_t)(k - nw + 1 + t) * sk_len_;
+        lin_comb_dev(sk_len_, 1 + nw, xs.data(), hco_, sg.data(), skC_, st_);
+    };
+
     // ---- cycles ------------------------------------------------------------
-    int total = 0, cycles = 0, status = TTSG_NOT_CONVERGED, max_rank = 0;
+    int total = 0, cycles = 0, status = TTSG_NOT_CONVERGED, max_rank = 0, cap_events = 0;
     bool have_x = false;
+    if (!in_.x0_r.empty()) {
+        // initial guess: the first cycle starts from r0 = b - A x0, like a restart
+        for (int mu = 0; mu < d; ++mu)
+            copy_f64((int64_t)in_.x0_r[mu] * n[mu] * in_.x0_r[mu + 1], in_.x0[mu], xcur_[mu], st_);
+        xcur_r_ = in_.x0_r;
+        have_x = true;
+    }
     double last_sres = 1.0, last_true = 1.0;
     const int max_cycles = o.max_cycles > 0 ? o.max_cycles : 50;
     const double final_tol = o.final_tol > 0.0 ? o.final_tol : o.round_tol;
@@ -651,7 +826,20 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             std::vector<const void*> S64(in_.S.begin(), in_.S.end()), c64(slots_[s0].begin(), slots_[s0].end());
             kr_sketch_run(Prec::F64, d, n, s, R1, S64, slot_r_[s0], c64, z_, scratch_, st_);
         }
+        if (white_) {
+            // S v_1 opens the QR of S V; ||S r0|| = beta ||S v_1|| starts the rotated rhs
+            copy_f64(s, z_, SV_, st_);
+            fill(s, 0.0, z2_, st_);
+            hipLaunchKernelGGL(k_ls_append, dim3(1), dim3(LS_THREADS), 0, st_, s, 0, ldw_, SV_, Q2_, T2_, c2_, z2_,
+                               res2_);
+            TTSG_HIP(hipGetLastError());
+        }
         scale_f64(s, beta, z_, st_);
+        if (white_) {
+            sumsq(s, z_, lsres_, scal_ + 3, st_);
+            hipLaunchKernelGGL(k_whiten_init, dim3(1), dim3(64), 0, st_, ldw_ + 1, scal_ + 3, g_);
+            TTSG_HIP(hipGetLastError());
+        }
         window.push_back(s0);
         add_phase(TTSG_PH_OTHER, t0);
 
@@ -660,9 +848,15 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         std::vector<double> cyc_res;  // sketched residuals of this cycle
         for (int k = 0; k < m_ && total < maxit_; ++k) {
             const int vk = window.back();
+            const int nw_k = (int)window.size();
             TTSG_HIP(hipEventRecord(side.v, st_));   // v_k (and S r0) are in place
-            // 1) (stream K) w_k = S A v_k, then the least-squares update of W_k
             auto t1 = now();
+            if (pre_) {
+                precond_step(k, vk, window);
+                add_phase(TTSG_PH_STTA, t1);
+            } else {
+            // 1) (stream K) w_k = S A v_k, then the least-squares update of W_k
+            if (!white_) {
             TTSG_HIP(hipStreamWaitEvent(side.k, side.v, 0));
             {
                 std::vector<const void*> SA64(SA64_.begin(), SA64_.end());
@@ -673,6 +867,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             hipLaunchKernelGGL(k_ls_append, dim3(1), dim3(LS_THREADS), 0, side.k, s, k, m_ + 1, W_, Q_, Rls_, cls_,
                                z_, lsres_);
             TTSG_HIP(hipGetLastError());
+            }
             add_phase(TTSG_PH_KR, t1);
             // 2) (stream H) the STTA sketch of v_k, kept for the final solution,
             // and h_{i,k} for the window
@@ -705,6 +900,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
                 lin_comb_dev(sk_len_, 1 + nw, xs.data(), hco_, sg.data(), skC_, st_);
             }
             add_phase(TTSG_PH_STTA, t1);
+            }
             // 4) recover + TT-SVD into a free slot
             t1 = now();
             int fs = -1;
@@ -728,14 +924,33 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             // bfloat16 sketches of A v_k err by about its unit roundoff (2^-8):
             // directions below that are noise and are not kept in the basis
             const double basis_tol = p_ == Prec::BF16 ? std::max(o.round_tol, 0.00390625) : o.round_tol;
+            (void)take_rank_cap_events();
             const double h = tt_svd_inplace(d, n, slot_r_[fs], slots_[fs], cap_, basis_tol, o.maxrank, scratch_,
                                             st_, nullptr);
+            cap_events += take_rank_cap_events();
             add_phase(TTSG_PH_TTSVD, t1);
             TTSG_CHECK(std::isfinite(h), TTSG_ERR_NONFINITE, "non-finite basis vector");
             // 5) least-squares residual (stream K finished long ago)
             t1 = now();
             double sres = 0.0;
-            sres = *static_cast<const double*>(read_back(lsres_, sizeof(double), &sres, side.k));
+            if (white_) {
+                // S v_{k+1} extends the QR of S V; one Givens step of T H
+                if (h > 0.0 && std::isfinite(h)) {
+                    std::vector<const void*> S64(in_.S.begin(), in_.S.end()), c64(slots_[fs].begin(), slots_[fs].end());
+                    kr_sketch_run(Prec::F64, d, n, s, R1, S64, slot_r_[fs], c64, SV_ + (int64_t)(k + 1) * s, scratch_,
+                                  st_);
+                    scale_f64(s, 1.0 / h, SV_ + (int64_t)(k + 1) * s, st_);
+                    hipLaunchKernelGGL(k_ls_append, dim3(1), dim3(LS_THREADS), 0, st_, s, k + 1, ldw_, SV_, Q2_, T2_,
+                                       c2_, z2_, res2_);
+                    TTSG_HIP(hipGetLastError());
+                }
+                hipLaunchKernelGGL(k_whiten_step, dim3(1), dim3(64), 0, st_, k, ldw_, nw_k, T2_, hco_ + 1, h,
+                                   h > 0.0 ? 1 : 0, Gr_, cs_, sn_, g_, lsres_);
+                TTSG_HIP(hipGetLastError());
+                sres = *static_cast<const double*>(read_back(lsres_, sizeof(double), &sres, st_));
+            } else {
+                sres = *static_cast<const double*>(read_back(lsres_, sizeof(double), &sres, pre_ ? st_ : side.k));
+            }
             add_phase(TTSG_PH_LS, t1);
             TTSG_CHECK(std::isfinite(sres), TTSG_ERR_NONFINITE, "non-finite sketched residual");
             kk = k + 1;
@@ -772,7 +987,10 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         }
         // ---- solution of the cycle ----
         auto t2 = now();
-        hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(64), 0, st_, kk, m_ + 1, Rls_, cls_, y_);
+        if (white_)
+            hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(64), 0, st_, kk, ldw_, Gr_, g_, y_);
+        else
+            hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(64), 0, st_, kk, m_ + 1, Rls_, cls_, y_);
         TTSG_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_gemv_cols, dim3(grid_for(sk_len_)), dim3(256), 0, st_, sk_len_, kk, sk_len_,
                            sketches_, y_, skC_);
@@ -794,6 +1012,23 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             int cap = 0;
             for (int k = 0; k <= d; ++k) cap = std::max(cap, in_.rx[k]);
             tt_svd_inplace(d, n, cr, slots_[fs], cap_, final_tol, cap, scratch_, st_, nullptr);
+            if (pre_) {
+                // x gains P^{-1} u: the STTA sketches of the zeta terms
+                // alpha_j (x)_k E_jk u are summed, recovered and rounded
+                std::vector<double*> pa, oa, pt, ot;
+                sk_ptrs(skA_, pa, oa);
+                sk_ptrs(skT_, pt, ot);
+                std::vector<const void*> z64(zbuf_.begin(), zbuf_.end());
+                for (int j = 0; j < in_.zeta; ++j) {
+                    mode_product_tt(d, n, cr, cvec(slots_[fs]), Eterm(j), in_.alpha[j], zbuf_, st_, &scratch_);
+                    stta_sketch(so_plain, cr, z64, (j == 0 ? pa : pt).data(), (j == 0 ? oa : ot).data(), scratch_,
+                                st_);
+                    if (j > 0) axpby(sk_len_, 1.0, skT_, 1.0, skA_, st_);
+                }
+                std::vector<const double*> ppsi(pa.begin(), pa.end()), pom(oa.begin(), oa.end());
+                stta_recover(d, n, in_.rho, in_.rx, ppsi, pom, o.rcond, slots_[fs], cr, scratch_, st_);
+                tt_svd_inplace(d, n, cr, slots_[fs], cap_, final_tol, cap, scratch_, st_, nullptr);
+            }
             if (!have_x) {
                 for (int mu = 0; mu < d; ++mu)
                     copy_f64((int64_t)cr[mu] * n[mu] * cr[mu + 1], slots_[fs][mu], xcur_[mu], st_);
@@ -814,7 +1049,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         add_phase(TTSG_PH_OTHER, t2);
         if (info && info->true_history && cycles - 1 < max_cycles) info->true_history[cycles - 1] = last_true;
         if (last_true <= o.tol) {
-            status = breakdown ? TTSG_BREAKDOWN : TTSG_OK;
+            status = breakdown ? TTSG_BREAKDOWN : (cap_events > 0 ? TTSG_RANK_CAPPED : TTSG_OK);
             break;
         }
         (void)corr;
@@ -843,8 +1078,8 @@ int sgmres_solve(const SolverInputs& in, double* const* x, int32_t* x_r, ttsg_sg
     return s.run(x, x_r, info, ws, ws_bytes);
 }
 
-size_t sgmres_workspace(const SolverInputs& in, hipStream_t st) {
-    SgmresSolver s(in, st);
+size_t sgmres_workspace(const SolverInputs& in) {
+    SgmresSolver s(in, nullptr);
     return s.workspace_bytes();
 }
 

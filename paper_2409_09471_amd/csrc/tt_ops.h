@@ -175,6 +175,10 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
                       const std::vector<int64_t>& cap_elems, double tol, int maxrank, Arena& ar,
                       hipStream_t st, double* norm_before = nullptr);
 
+// Number of bonds, since the last call on this host thread, whose TT-SVD rank
+// was decided by the rank cap rather than the tolerance (then reset to 0).
+int take_rank_cap_events();
+
 // STTA recovery: cores of Omega^+ applied to Psi, compacted to the numerical
 // ranks of the Omega_b (relative cutoff rcond).  out cores need capacity
 // rx[mu] * n[mu] * rx[mu+1].  Writes the recovered ranks to r_out.
@@ -186,6 +190,22 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
 // float64 back).  Cores are modified in place; ranks may shrink.
 double tt_norm_orth(int d, const int* n, std::vector<int>& r, const std::vector<double*>& w, Arena& ar,
                     hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Exponential-sum preconditioner (precond.hip, Sec. 4.1)
+// ---------------------------------------------------------------------------
+// alpha_j, beta_j (j < zeta) with |z E(z) - 1| <= tol on [zmin, zmax]; returns
+// zeta, -zeta when max_terms is too small, -1 for bad arguments.
+int expsum_coefficients(double zmin, double zmax, double tol, int max_terms, double* alpha, double* beta);
+// out[k] (zeta x n_k x n_k, row-major, term-major) = exp(-beta_j M_k) for every
+// term j and mode k; beta ascending.  Synchronizes once (mode norms).
+void mode_exponentials(int zeta, const double* beta, int d, const int* n, const std::vector<const double*>& M,
+                       const std::vector<double*>& out, Arena& ar, hipStream_t st);
+// z = alpha (x)_k E_k x: E_k applied to the mode index of core k (ranks kept),
+// alpha folded into the first core.  E[k]: n_k x n_k row-major.
+void mode_product_tt(int d, const int* n, const std::vector<int>& r, const std::vector<const double*>& x,
+                     const std::vector<const double*>& E, double alpha, const std::vector<double*>& z, hipStream_t st,
+                     Arena* ar = nullptr);
 
 // ---------------------------------------------------------------------------
 // Solver (solver.hip)
@@ -202,10 +222,20 @@ struct SolverInputs {
     std::vector<int> rho, rx;
     std::vector<const double*> Y, X;
     ttsg_sgmres_opts o;
+    // optional initial guess of x (x0_r empty: x0 = 0)
+    std::vector<int> x0_r;
+    std::vector<const double*> x0;
+    // optional exponential-sum right preconditioner (zeta = 0: none)
+    int zeta = 0;
+    std::vector<double> alpha, beta;
+    std::vector<const double*> M;     // d mode matrices n_k x n_k
+    int ls_mode = TTSG_LS_PINV;
 };
 
 int sgmres_solve(const SolverInputs& in, double* const* x, int32_t* x_r, ttsg_sgmres_info* info, void* ws,
                  size_t ws_bytes, hipStream_t st);
+// Workspace bytes sgmres_solve needs for these sizes and options (reads no pointers).
+size_t sgmres_workspace(const SolverInputs& in);
 
 // a + bscale * b as block cores (ranks add); first/last cores concatenated.
 void tt_add_block(int d, const int* n, const std::vector<int>& ra, const std::vector<double*>& a,

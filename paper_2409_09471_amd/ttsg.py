@@ -24,12 +24,25 @@ PREC_BF16 = 2
 OK = 0
 NOT_CONVERGED = 1
 BREAKDOWN = 2
+RANK_CAPPED = 3
+
+ERR_ARG = -1
+ERR_CAPACITY = -2
+ERR_WS = -3
+ERR_NONFINITE = -4
+ERR_HIP = -5
+ERR_DTYPE = -6
+
+LS_PINV = 0
+LS_WHITEN = 1
 
 _lib = None
 
 
 class TTSGError(RuntimeError):
-    pass
+    def __init__(self, msg, code=0):
+        super().__init__(msg)
+        self.code = code
 
 
 def lib():
@@ -50,6 +63,8 @@ EXPORTED = [
     "ttsg_round_rand", "ttsg_round_svd", "ttsg_sgmres_solve", "ttsg_true_residual", "ttsg_dot",
     "ttsg_sgmres_solve_batched", "ttsg_autotune", "ttsg_autotune_save", "ttsg_autotune_load", "ttsg_autotune_clear",
     "ttsg_grad_kron_sum", "ttsg_tt_axpby", "ttsg_stats_enable", "ttsg_stats_read",
+    "ttsg_sgmres_solve_ex", "ttsg_sgmres_workspace_size", "ttsg_expsum", "ttsg_precond_round",
+    "ttsg_kr_sketch_workspace_size", "ttsg_stta_sketch_workspace_size", "ttsg_round_rand_workspace_size",
 ]
 
 STAT_CLASSES = {0: "contract_f64", 1: "contract_f32", 2: "contract_bf16", 3: "qr", 4: "svd_jacobi",
@@ -114,6 +129,14 @@ class SgmresInfo(ctypes.Structure):
     ]
 
 
+class SgmresExt(ctypes.Structure):
+    _fields_ = [
+        ("x0_r", ctypes.c_void_p), ("x0", ctypes.c_void_p),
+        ("zeta", ctypes.c_int32), ("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p), ("M", ctypes.c_void_p),
+        ("ls_mode", ctypes.c_int32),
+    ]
+
+
 PHASES = ["kr_sketch", "inner_products", "stta_sketch", "stta_recover", "tt_svd", "least_squares",
           "final_solution", "other"]
 
@@ -136,8 +159,13 @@ def _stream() -> ctypes.c_void_p:
 def _check(rc: int, what: str) -> int:
     if rc < 0:
         msg = lib().ttsg_last_error().decode()
-        raise TTSGError(f"{what} failed ({rc}): {msg}")
+        raise TTSGError(f"{what} failed ({rc}): {msg}", rc)
     return rc
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    """Caller-owned scratch for one call (the library then allocates nothing)."""
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
 def ranks_of(cores: Sequence[torch.Tensor]) -> List[int]:
@@ -192,6 +220,30 @@ def kron_sum_operator(terms, device="cuda") -> List[torch.Tensor]:
     return to_device(cores, device)
 
 
+def markov_operator(Q, J, P, rate: float, device="cuda") -> List[torch.Tensor]:
+    """TT-matrix cores of the synchronized Markov chain (Sec. 5.1.2):
+    sum_k Q_k + rate sum_k (J_k x J_{k+1}) - rate sum_k (P_k x P_{k+1}).
+
+    Bond states: 0 = nothing placed, 1 = a term completed, 2 = the J of a
+    synchronization pair is open, 3 = its P is open (closed on the next mode)."""
+    import numpy as np
+    d = len(Q)
+    n = Q[0].shape[0]
+    eye = np.eye(n)
+    cores = []
+    for k in range(d):
+        left = [0] if k == 0 else [0, 1, 2, 3]
+        right = [1] if k == d - 1 else [0, 1, 2, 3]
+        D = np.zeros((len(left), n, n, len(right)))
+        blocks = {(0, 0): eye, (1, 1): eye, (0, 1): Q[k], (0, 2): rate * J, (0, 3): -rate * P,
+                  (2, 1): J, (3, 1): P}
+        for (a, b), blk in blocks.items():
+            if a in left and b in right:
+                D[left.index(a), :, :, right.index(b)] = blk
+        cores.append(D)
+    return to_device(cores, device)
+
+
 # ----------------------------------------------------------------------------
 # Entry points
 # ----------------------------------------------------------------------------
@@ -213,9 +265,13 @@ def kr_sketch(S: Sequence[torch.Tensor], x: Sequence[torch.Tensor], A: Optional[
     w = torch.empty(s, dtype=torch.float64, device=x[0].device)
     Rp = _i32(op_ranks(A)) if A is not None else None
     Ap = _ptrs(A) if A is not None else None
+    nb = ctypes.c_size_t(0)
+    _check(lib().ttsg_kr_sketch_workspace_size(d, _i32(sizes_of(x)), s, Rp, _i32(ranks_of(x)), precision,
+                                               ctypes.byref(nb)), "ttsg_kr_sketch_workspace_size")
+    ws = _workspace(nb.value, x[0].device)
     _check(lib().ttsg_kr_sketch(d, _i32(sizes_of(x)), s, _ptrs(S), Rp, Ap, _i32(ranks_of(x)), _ptrs(x),
-                                ctypes.c_void_p(w.data_ptr()), precision, None, ctypes.c_size_t(0), _stream()),
-           "ttsg_kr_sketch")
+                                ctypes.c_void_p(w.data_ptr()), precision, ctypes.c_void_p(ws.data_ptr()), nb,
+                                _stream()), "ttsg_kr_sketch")
     return w
 
 
@@ -228,9 +284,13 @@ def stta_sketch(x, X, Y, rx, rho, A=None, precision: int = PREC_F64):
     Om = [torch.empty((rho[b], rx[b]), dtype=torch.float64, device=dev) for b in range(1, d)]
     Rp = _i32(op_ranks(A)) if A is not None else None
     Ap = _ptrs(A) if A is not None else None
+    nb = ctypes.c_size_t(0)
+    _check(lib().ttsg_stta_sketch_workspace_size(d, _i32(n), _i32(rho), _i32(rx), Rp, _i32(ranks_of(x)), precision,
+                                                 ctypes.byref(nb)), "ttsg_stta_sketch_workspace_size")
+    ws = _workspace(nb.value, dev)
     _check(lib().ttsg_stta_sketch(d, _i32(n), _i32(rho), _ptrs(Y), _i32(rx), _ptrs(X), Rp, Ap, _i32(ranks_of(x)),
-                                  _ptrs(x), _ptrs(Psi), _ptrs(Om), precision, None, ctypes.c_size_t(0), _stream()),
-           "ttsg_stta_sketch")
+                                  _ptrs(x), _ptrs(Psi), _ptrs(Om), precision, ctypes.c_void_p(ws.data_ptr()), nb,
+                                  _stream()), "ttsg_stta_sketch")
     return Psi, Om
 
 
@@ -246,9 +306,13 @@ def round_rand(x, X, Y, rx, rho, tol: float, maxrank: int = 0, rcond: float = 1e
     dev = x[0].device
     out = [torch.empty((rx[k], n[k], rx[k + 1]), dtype=torch.float64, device=dev) for k in range(d)]
     out_r = (ctypes.c_int32 * (d + 1))()
+    nb = ctypes.c_size_t(0)
+    _check(lib().ttsg_round_rand_workspace_size(d, _i32(n), _i32(ranks_of(x)), _i32(rho), _i32(rx), precision,
+                                                ctypes.byref(nb)), "ttsg_round_rand_workspace_size")
+    ws = _workspace(nb.value, dev)
     _check(lib().ttsg_round_rand(d, _i32(n), _i32(ranks_of(x)), _ptrs(x), _i32(rho), _ptrs(Y), _i32(rx), _ptrs(X),
                                  ctypes.c_double(tol), int(maxrank), ctypes.c_double(rcond), _ptrs(out), out_r,
-                                 precision, None, ctypes.c_size_t(0), _stream()), "ttsg_round_rand")
+                                 precision, ctypes.c_void_p(ws.data_ptr()), nb, _stream()), "ttsg_round_rand")
     return _trim(out, list(out_r))
 
 
@@ -318,16 +382,83 @@ class SolveResult:
     phase_seconds: dict = field(default_factory=dict)
 
 
+@dataclass
+class Preconditioner:
+    """Exponential-sum right preconditioner P^{-1} = sum_j alpha[j] (x)_k exp(-beta[j] M[k])
+    (Sec. 4.1): M are the d mode matrices (CUDA float64, n_k x n_k)."""
+    alpha: Sequence[float]
+    beta: Sequence[float]
+    M: List[torch.Tensor]
+
+
+def expsum(zmin: float, zmax: float, tol: float, max_terms: int = 1024):
+    """(alpha, beta) with |z E(z) - 1| <= tol on [zmin, zmax] (ttsg_expsum)."""
+    import numpy as np
+    a = (ctypes.c_double * max_terms)()
+    b = (ctypes.c_double * max_terms)()
+    z = _check(lib().ttsg_expsum(ctypes.c_double(zmin), ctypes.c_double(zmax), ctypes.c_double(tol),
+                                 int(max_terms), a, b), "ttsg_expsum")
+    return np.array(a[:z]), np.array(b[:z])
+
+
+def _dbl(vals) -> ctypes.Array:
+    return (ctypes.c_double * len(vals))(*[float(v) for v in vals])
+
+
+def precond_round(x, pre: Preconditioner, X, Y, rx, rho, tol: float, maxrank: int = 0,
+                  rcond: float = 1e-12) -> List[torch.Tensor]:
+    """Round(P^{-1} x) by the STTA streaming sum of the preconditioner's terms."""
+    d = len(x)
+    n = sizes_of(x)
+    dev = x[0].device
+    out = [torch.empty((rx[k], n[k], rx[k + 1]), dtype=torch.float64, device=dev) for k in range(d)]
+    out_r = (ctypes.c_int32 * (d + 1))()
+    _check(lib().ttsg_precond_round(d, _i32(n), len(pre.alpha), _dbl(pre.alpha), _dbl(pre.beta), _ptrs(pre.M),
+                                    _i32(ranks_of(x)), _ptrs(x), _i32(rho), _ptrs(Y), _i32(rx), _ptrs(X),
+                                    ctypes.c_double(tol), int(maxrank), ctypes.c_double(rcond), _ptrs(out), out_r,
+                                    None, ctypes.c_size_t(0), _stream()), "ttsg_precond_round")
+    return _trim(out, list(out_r))
+
+
+def sgmres_workspace_size(A, b, S, rx, rho, opts: "SgmresOpts", ext: Optional["SgmresExt"] = None) -> int:
+    nb = ctypes.c_size_t(0)
+    _check(lib().ttsg_sgmres_workspace_size(len(b), _i32(sizes_of(b)), _i32(op_ranks(A)), _i32(ranks_of(b)),
+                                            int(S[0].shape[0]), _i32(rho), _i32(rx), ctypes.byref(opts),
+                                            ctypes.byref(ext) if ext is not None else None, ctypes.byref(nb)),
+           "ttsg_sgmres_workspace_size")
+    return nb.value
+
+
 def sgmres_solve(A, b, S, X, Y, rx, rho, *, maxit: int, tol: float, q: int = 1, round_tol: float = 1e-7,
                  maxrank: int = 0, restart: int = 0, final_tol: float = 0.0, stop_safety: float = 0.1,
                  rcond: float = 1e-12, precision: int = PREC_F64, max_cycles: int = 50,
-                 phase_timing: bool = False) -> SolveResult:
+                 phase_timing: bool = False, x0: Optional[Sequence[torch.Tensor]] = None,
+                 precond: Optional[Preconditioner] = None, ls: int = LS_PINV,
+                 workspace: Optional[torch.Tensor] = None, raise_on_error: bool = True) -> SolveResult:
+    """Alg. 4 (Alg. 5 with `precond`).  The workspace is queried and allocated
+    here (or passed in), so the library allocates no device memory."""
     d = len(b)
     n = sizes_of(b)
     dev = b[0].device
     opts = SgmresOpts(maxit=maxit, restart=restart, q=q, maxrank=maxrank, precision=precision,
                       max_cycles=max_cycles, tol=tol, round_tol=round_tol, final_tol=final_tol,
                       stop_safety=stop_safety, rcond=rcond)
+    keep = []
+    ext = SgmresExt(ls_mode=int(ls))
+    if x0 is not None:
+        r0a, p0a = _i32(ranks_of(x0)), _ptrs(x0)
+        keep += [r0a, p0a]
+        ext.x0_r = ctypes.cast(r0a, ctypes.c_void_p)
+        ext.x0 = ctypes.cast(p0a, ctypes.c_void_p)
+    if precond is not None:
+        aa, ba, ma = _dbl(precond.alpha), _dbl(precond.beta), _ptrs(precond.M)
+        keep += [aa, ba, ma]
+        ext.zeta = len(precond.alpha)
+        ext.alpha = ctypes.cast(aa, ctypes.c_void_p)
+        ext.beta = ctypes.cast(ba, ctypes.c_void_p)
+        ext.M = ctypes.cast(ma, ctypes.c_void_p)
+    if workspace is None:
+        workspace = _workspace(sgmres_workspace_size(A, b, S, rx, rho, opts, ext), dev)
     sh = (ctypes.c_double * maxit)()
     rh = (ctypes.c_int32 * maxit)()
     th = (ctypes.c_double * max_cycles)()
@@ -336,11 +467,16 @@ def sgmres_solve(A, b, S, X, Y, rx, rho, *, maxit: int, tol: float, q: int = 1, 
                       phase_seconds=ph if phase_timing else None)
     x = [torch.zeros((rx[k], n[k], rx[k + 1]), dtype=torch.float64, device=dev) for k in range(d)]
     xr = (ctypes.c_int32 * (d + 1))()
-    rc = lib().ttsg_sgmres_solve(d, _i32(n), _i32(op_ranks(A)), _ptrs(A), _i32(ranks_of(b)), _ptrs(b),
-                                 int(S[0].shape[0]), _ptrs(S), _i32(rho), _ptrs(Y), _i32(rx), _ptrs(X),
-                                 ctypes.byref(opts), _ptrs(x), xr, ctypes.byref(info), None, ctypes.c_size_t(0),
-                                 _stream())
-    _check(rc, "ttsg_sgmres_solve")
+    rc = lib().ttsg_sgmres_solve_ex(d, _i32(n), _i32(op_ranks(A)), _ptrs(A), _i32(ranks_of(b)), _ptrs(b),
+                                    int(S[0].shape[0]), _ptrs(S), _i32(rho), _ptrs(Y), _i32(rx), _ptrs(X),
+                                    ctypes.byref(opts), ctypes.byref(ext), _ptrs(x), xr, ctypes.byref(info),
+                                    ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()),
+                                    _stream())
+    if raise_on_error:
+        _check(rc, "ttsg_sgmres_solve")
+    elif rc < 0:
+        return SolveResult(x=[], status=rc, iterations=0, cycles=0, true_residual=float("nan"),
+                           sketched_residual=float("nan"), max_rank=0)
     it = info.iterations
     return SolveResult(
         x=_trim(x, list(xr)), status=rc, iterations=it, cycles=info.cycles,

@@ -74,3 +74,63 @@ def test_autotune_table_round_trip(tmp_path):
     assert ttsg.autotune_clear() == 2
     with pytest.raises(ttsg.TTSGError):
         ttsg.autotune_load(str(tmp_path / "missing.txt"))
+
+
+def test_expsum_coefficients_match_the_oracle():
+    """ttsg_expsum (host arithmetic in the library) and oracle.precond implement
+    the same quadrature independently; both must give the same terms and meet
+    the accuracy bound on the interval."""
+    import numpy as np
+    from oracle import precond as opc
+    from paper_2409_09471_amd import ttsg
+    for zmin, zmax, tol in [(1.0, 100.0, 1e-2), (197.0, 1.33e6, 1e-3), (0.3, 5e4, 1e-6)]:
+        a, b = ttsg.expsum(zmin, zmax, tol)
+        ao, bo = opc.expsum_coefficients(zmin, zmax, tol)
+        assert len(a) == len(ao)
+        assert np.allclose(a, ao, rtol=1e-13) and np.allclose(b, bo, rtol=1e-13)
+        z = np.geomspace(zmin, zmax, 5001)
+        assert np.max(np.abs(z * opc.expsum_eval(a, b, z) - 1.0)) <= tol
+    with pytest.raises(ttsg.TTSGError) as e:
+        ttsg.expsum(1.0, 1e6, 1e-8, max_terms=4)
+    assert e.value.code == ttsg.ERR_CAPACITY
+    with pytest.raises(ttsg.TTSGError) as e:
+        ttsg.expsum(2.0, 1.0, 1e-2)
+    assert e.value.code == ttsg.ERR_ARG
+
+
+def test_workspace_queries_without_gpu(lib):
+    """Workspace sizes are host arithmetic: they grow with the options that need
+    buffers, and an unknown precision is rejected with TTSG_ERR_DTYPE."""
+    from paper_2409_09471_amd import ttsg
+    d = 4
+    n = (ctypes.c_int32 * d)(16, 16, 16, 16)
+    R = (ctypes.c_int32 * (d + 1))(1, 2, 2, 2, 1)
+    rb = (ctypes.c_int32 * (d + 1))(1, 2, 2, 2, 1)
+    rx = (ctypes.c_int32 * (d + 1))(1, 16, 32, 16, 1)
+    rho = (ctypes.c_int32 * (d + 1))(1, 16, 52, 36, 1)
+    opts = ttsg.SgmresOpts(maxit=40, q=1, tol=1e-6, round_tol=1e-8, stop_safety=0.1, rcond=1e-12)
+    sizes = []
+    for ext in [None, ttsg.SgmresExt(ls_mode=ttsg.LS_WHITEN), ttsg.SgmresExt(zeta=9, alpha=1, beta=1, ls_mode=0)]:
+        if ext is not None and ext.zeta:
+            a = (ctypes.c_double * 9)(*[1.0] * 9)
+            b = (ctypes.c_double * 9)(*[float(j) for j in range(9)])
+            ext.alpha = ctypes.cast(a, ctypes.c_void_p)
+            ext.beta = ctypes.cast(b, ctypes.c_void_p)
+        nb = ctypes.c_size_t(0)
+        rc = lib.ttsg_sgmres_workspace_size(d, n, R, rb, 80, rho, rx, ctypes.byref(opts),
+                                            ctypes.byref(ext) if ext is not None else None, ctypes.byref(nb))
+        assert rc == 0
+        sizes.append(nb.value)
+    assert sizes[0] > 0 and sizes[1] > sizes[0] and sizes[2] > sizes[0]
+    opts.precision = 7
+    nb = ctypes.c_size_t(0)
+    assert lib.ttsg_sgmres_workspace_size(d, n, R, rb, 80, rho, rx, ctypes.byref(opts), None,
+                                          ctypes.byref(nb)) == ttsg.ERR_DTYPE
+    assert lib.ttsg_kr_sketch_workspace_size(d, n, 80, R, rb, 7, ctypes.byref(nb)) == ttsg.ERR_DTYPE
+    assert lib.ttsg_stta_sketch_workspace_size(d, n, rho, rx, None, rb, 0, ctypes.byref(nb)) == 0
+    assert nb.value > 0
+    # a rank of b above the STTA target ranks is a capacity error
+    big = (ctypes.c_int32 * (d + 1))(1, 32, 2, 2, 1)
+    opts.precision = 0
+    assert lib.ttsg_sgmres_workspace_size(d, n, R, big, 80, rho, rx, ctypes.byref(opts), None,
+                                          ctypes.byref(nb)) == ttsg.ERR_CAPACITY
