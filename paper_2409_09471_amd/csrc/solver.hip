@@ -961,11 +961,21 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             max_rank = std::max(max_rank, mr);
             if (info && info->sketched_history && total - 1 < o.maxit) info->sketched_history[total - 1] = last_sres;
             if (info && info->rank_history && total - 1 < o.maxit) info->rank_history[total - 1] = mr;
-            if (h == 0.0) {
-                breakdown = true;
+            // Lucky breakdown: v~ = A v_k - sum_i h_{i,k} v_i vanishes to rounding,
+            // i.e. h_{k+1,k} <= 1e-12 ||A v_k|| with ||A v_k||^2 ~ h_{k+1,k}^2 +
+            // sum_i h_{i,k}^2.  The coefficients are read back only when the
+            // cycle stops anyway (the Krylov space is then invariant and the
+            // least-squares residual is at rounding level too).
+            if (h == 0.0 || sres <= stop) {
+                double hb[16];  // hco_ holds 16 values; the ABI caps q at 7
+                const int nwr = std::min(nw_k, 15);
+                const double* hv =
+                    static_cast<const double*>(read_back(hco_, (1 + nwr) * sizeof(double), hb, st_));
+                double hn2 = h * h;
+                for (int t = 1; t <= nwr; ++t) hn2 += hv[t] * hv[t];
+                if (h <= 1e-12 * std::sqrt(hn2)) breakdown = true;
                 break;
             }
-            if (sres <= stop) break;
             if (k + 1 >= m_ || total >= maxit_) break;
             // Low-precision sketches of A v_k put a floor under what one cycle can
             // reach (about the working precision's rounding relative to the

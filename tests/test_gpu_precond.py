@@ -91,7 +91,12 @@ def test_preconditioned_solve_matches_oracle(ls, precision):
     A = oops.tt_kron_sum(terms)
     S, X, Y, rx, rho = _sketches(rng, [n] * d, 40, 48)
     a, be = _precond_for(mats, 1e-2)
-    kw = dict(maxit=20, tol=tol, q=1, round_tol=1e-9, final_tol=1e-9, stop_safety=0.1)
+    # The basis ranks reach the STTA cap here, and the recovered correction
+    # sum_i y_i v_i has many singular values between 1e-14 and 1e-9 of its
+    # norm: a pseudo-inverse cutoff of 1e-12 in STTA_recover then amplifies the
+    # sketches' rounding (recovery error ~7e-6, measured on the oracle), 1e-10
+    # does not (~6e-8).  Both sides use 1e-10.
+    kw = dict(maxit=20, tol=tol, q=1, round_tol=1e-9, final_tol=1e-9, stop_safety=0.1, rcond=1e-10)
     pre = ttsg.Preconditioner(list(a), list(be), dev(mats))
     res = ttsg.sgmres_solve(dev(A), dev(b), dev(S), dev(X), dev(Y), rx, rho, precond=pre, ls=ls,
                             precision=precision, **kw)
@@ -100,7 +105,9 @@ def test_preconditioned_solve_matches_oracle(ls, precision):
     xo, io = osol.tt_sgmres(A, b, S, X, Y, precond=(a, E), ls="whiten" if ls == ttsg.LS_WHITEN else "pinv", **kw)
     tr = osol.true_residual(A, b, x)
     assert res.status in (ttsg.OK, ttsg.RANK_CAPPED) and tr <= tol, (res.status, tr)
-    assert res.iterations <= 8                       # unpreconditioned: ~60
+    # unpreconditioned: ~60.  The float32 sketches of A P^-1 v_k floor a cycle's
+    # sketched residual near 2e-7; the cycle then ends on the stall test (8 steps)
+    assert res.iterations <= (4 if precision == ttsg.PREC_F64 else 12), res.sketched_history
     if precision == ttsg.PREC_F64:
         assert res.iterations == io["iterations"]
         m = min(3, res.iterations)
