@@ -129,6 +129,28 @@ int ttsg_stta_sketch(int32_t d, const int32_t* n,
                      double* const* Psi, double* const* Omega, int32_t precision,
                      void* ws, size_t ws_bytes, ttsg_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * STTA sketch as ttsg_stta_sketch, with the same arguments, layouts, results
+ * and stream ordering, but without a workspace argument.  Its scratch is a
+ * static device buffer of 128 MiB inside the library (one per GPU, held until
+ * the process ends); the call makes no hipMalloc/hipFree and no allocating
+ * library call.  Shapes whose scratch exceeds the buffer return -TTSG_ERR_WS
+ * before any work is queued (ttsg_stta_sketch_workspace_size gives the need;
+ * e.g. d = 10, n = 64, ranks 64, rho 84, operator rank 3 needs about 70 MiB
+ * in float64).  With the tile autotuner on it returns -TTSG_ERR_ARG (tuning
+ * allocates).  Every call on one GPU shares that GPU's buffer: calls that
+ * overlap on one GPU (different streams or host threads) race and must be
+ * serialized by the caller.  The stream must belong to the current device.
+ * Does not synchronize. */
+int ttsg_stta_sketch_noalloc(int32_t d, const int32_t* n,
+                             const int32_t* rho, const double* const* Y,
+                             const int32_t* rx, const double* const* X,
+                             const int32_t* R, const double* const* A,
+                             const int32_t* r, const double* const* x,
+                             double* const* Psi, double* const* Omega, int32_t precision,
+                             ttsg_stream_t stream);
+
 /* ------------------------------------------------------------------------- */
 /* Randomized rounding (Sec. 3.3, STTA_sketch + STTA_recover):                */
 /* sketch x with (Y, X), recover C^_0 = Psi_0, C^_k = Omega_k^+ Psi_k (pseudo-  */

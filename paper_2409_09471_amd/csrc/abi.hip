@@ -3,7 +3,9 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <numeric>
 #include <thread>
@@ -183,19 +185,41 @@ static void stta_common(int32_t d, const int32_t* n, const int32_t* rho, const d
     ttsg::stta_sketch(o, vec(r, d + 1), xs, Psi, Omega, ar, st);
 }
 
+// Arena::get rounds every request up to 256 bytes.
+static size_t gran(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+
+// Bytes the single-stream STTA sketch takes from its arena for these shapes
+// (R == NULL: no operator): the float32 copies of the operands in the
+// reduced precisions, the sweep intermediates T1/T2/U1/U2, two left
+// environments, the right environments F_1..F_d, and the split-K partials of
+// one contraction (released after it; splits x workgroups < 1024 tiles of
+// 64 x 64, so fewer than 4M partial values).
 static size_t stta_ws(int32_t d, const int32_t* n, const int32_t* rho, const int32_t* rx, const int32_t* R,
-                      const int32_t* r) {
-    size_t big = 0, tot = 0;
-    for (int mu = 0; mu < d; ++mu) {
-        const size_t Rl = R ? R[mu] : 1, Rr = R ? R[mu + 1] : 1;
-        size_t m = (size_t)std::max(rho[mu], rx[mu]) * std::max<size_t>(r[mu], 1) * n[mu] *
-                   std::max(r[mu + 1], std::max(rx[mu + 1], rho[mu + 1])) * Rl * Rr;
-        big = std::max(big, m);
-        tot += (size_t)r[mu + 1] * Rr * rx[mu + 1] + (size_t)r[mu] * n[mu] * r[mu + 1] +
-               (size_t)Rl * n[mu] * n[mu] * Rr + (size_t)rho[mu] * n[mu] * rho[mu + 1] +
-               (size_t)rx[mu] * n[mu] * rx[mu + 1] + (size_t)rho[mu] * n[mu] * rx[mu + 1];
+                      const int32_t* r, ttsg::Prec p) {
+    const size_t es = ttsg::elem_size(p);
+    auto Rk = [&](int b) -> int64_t { return R ? R[b] : 1; };
+    size_t tot = 0;
+    if (p != ttsg::Prec::F64) {
+        for (int k = 0; k < d - 1; ++k) {
+            tot += gran((size_t)rho[k] * n[k] * rho[k + 1] * 4);
+            tot += gran((size_t)rx[k + 1] * n[k + 1] * rx[k + 2] * 4);
+        }
+        if (R)
+            for (int mu = 0; mu < d; ++mu) tot += gran((size_t)R[mu] * n[mu] * n[mu] * R[mu + 1] * 4);
+        for (int mu = 0; mu < d; ++mu) tot += gran((size_t)r[mu] * n[mu] * r[mu + 1] * 4);
     }
-    return (8 * big + 2 * tot) * 8 + (1 << 20);
+    int64_t t1 = 1, t2 = 1, u1 = 1, u2 = 1, env = 1;
+    for (int mu = 0; mu < d; ++mu) {
+        const int64_t rl = r[mu], rr = r[mu + 1], nn = n[mu];
+        t1 = std::max<int64_t>(t1, rho[mu] * Rk(mu) * nn * rr);
+        t2 = std::max<int64_t>(t2, rho[mu] * nn * Rk(mu + 1) * rr);
+        u1 = std::max<int64_t>(u1, rl * nn * Rk(mu + 1) * rx[mu + 1]);
+        u2 = std::max<int64_t>(u2, rl * Rk(mu) * nn * rx[mu + 1]);
+        env = std::max<int64_t>(env, rho[mu + 1] * Rk(mu + 1) * rr);
+    }
+    tot += gran(t1 * es) + gran(t2 * es) + gran(u1 * es) + gran(u2 * es) + 2 * gran(env * es) + gran(16);
+    for (int b = 1; b <= d; ++b) tot += gran((size_t)r[b] * Rk(b) * rx[b] * es);
+    return tot + kSplitSlack;
 }
 
 int ttsg_stta_sketch(int32_t d, const int32_t* n, const int32_t* rho, const double* const* Y, const int32_t* rx,
@@ -217,13 +241,93 @@ int ttsg_stta_sketch(int32_t d, const int32_t* n, const int32_t* rho, const doub
             check_shape(d, n, R, "stta A");
             check_ptrs(d, (const void* const*)A, "stta A");
         }
-        ttsg::Workspace W(ws, ws_bytes, (stta_ws(d, n, rho, rx, A ? R : nullptr, r)) + kSplitSlack, S(stream));
+        ttsg::Workspace W(ws, ws_bytes, stta_ws(d, n, rho, rx, A ? R : nullptr, r, prec_of(precision)), S(stream));
         stta_common(d, n, rho, Y, rx, X, A ? R : nullptr, A, r, x, Psi, Omega, precision, W.arena, S(stream));
         return 0;
     });
 }
 
-static size_t round_rand_ws(int32_t d, const int32_t* n, const int32_t* r, const int32_t* rho, const int32_t* rx) {
+// ---------------------------------------------------------------------------
+// The STTA sketch without any allocation: its scratch is a file-scope device
+// array.  In host code `scratch` only names the symbol; its device address
+// (one copy per GPU) comes from hipGetSymbolAddress, taken once per device
+// with that device current, and only that address is handed to kernels.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, char*> g_scratch_dev;  // device ordinal -> address of its copy of `scratch`
+
+static char* static_scratch_of_current_device() {
+    int dev = -1;
+    TTSG_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_dev.find(dev);
+    if (it != g_scratch_dev.end()) return it->second;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    TTSG_CHECK(e == hipSuccess && ptr != nullptr, TTSG_ERR_HIP,
+               std::string("stta_sketch_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<char*>(ptr);
+    return static_cast<char*>(ptr);
+}
+
+int ttsg_stta_sketch_noalloc(int32_t d, const int32_t* n, const int32_t* rho, const double* const* Y,
+                             const int32_t* rx, const double* const* X, const int32_t* R, const double* const* A,
+                             const int32_t* r, const double* const* x, double* const* Psi, double* const* Omega,
+                             int32_t precision, ttsg_stream_t stream) {
+    return guarded([&]() {
+        check_shape(d, n, r, "stta_noalloc x");
+        check_shape(d, n, rho, "stta_noalloc rho");
+        check_shape(d, n, rx, "stta_noalloc rx");
+        TTSG_CHECK(d >= 2, TTSG_ERR_ARG, "stta_noalloc: d must be >= 2");
+        const ttsg::Prec p = prec_of(precision);
+        check_ptrs(d - 1, (const void* const*)Y, "stta_noalloc Y");
+        check_ptrs(d - 1, (const void* const*)X, "stta_noalloc X");
+        check_ptrs(d, (const void* const*)x, "stta_noalloc x");
+        check_ptrs(d, (const void* const*)Psi, "stta_noalloc Psi");
+        check_ptrs(d - 1, (const void* const*)Omega, "stta_noalloc Omega");
+        if (A) {
+            check_shape(d, n, R, "stta_noalloc A");
+            check_ptrs(d, (const void* const*)A, "stta_noalloc A");
+        }
+        // the tile autotuner times new shape classes into a buffer it allocates
+        TTSG_CHECK(!ttsg::autotune_is_on(), TTSG_ERR_ARG,
+                   "stta_sketch_noalloc: the tile autotuner is on (tuning allocates); switch it off first");
+        const size_t need = stta_ws(d, n, rho, rx, A ? R : nullptr, r, p);
+        if (need > kStaticScratchBytes) {
+            char m[160];
+            std::snprintf(m, sizeof(m), "stta_sketch_noalloc: these shapes need %zu bytes of scratch, above the %zu "
+                          "of the static buffer", need, kStaticScratchBytes);
+            throw Error(TTSG_ERR_WS, m);
+        }
+        char* base = static_scratch_of_current_device();
+        ttsg::Arena ar;
+        ar.reset(base, kStaticScratchBytes);
+        stta_common(d, n, rho, Y, rx, X, A ? R : nullptr, A, r, x, Psi, Omega, precision, ar, S(stream));
+        return 0;
+    });
+}
+
+// A generous bound on the sketch's scratch (every intermediate at the largest
+// rank product), kept for the rounding entry points, whose recovery and TT-SVD
+// scratch terms are estimated beside it.
+static size_t stta_ws_loose(int32_t d, const int32_t* n, const int32_t* rho, const int32_t* rx, const int32_t* r) {
+    size_t big = 0, tot = 0;
+    for (int mu = 0; mu < d; ++mu) {
+        size_t m = (size_t)std::max(rho[mu], rx[mu]) * std::max<size_t>(r[mu], 1) * n[mu] *
+                   std::max(r[mu + 1], std::max(rx[mu + 1], rho[mu + 1]));
+        big = std::max(big, m);
+        tot += (size_t)r[mu + 1] * rx[mu + 1] + (size_t)r[mu] * n[mu] * r[mu + 1] + (size_t)n[mu] * n[mu] +
+               (size_t)rho[mu] * n[mu] * rho[mu + 1] + (size_t)rx[mu] * n[mu] * rx[mu + 1] +
+               (size_t)rho[mu] * n[mu] * rx[mu + 1];
+    }
+    return (8 * big + 2 * tot) * 8 + (1 << 20);
+}
+
+static size_t round_rand_ws(int32_t d, const int32_t* n, const int32_t* r, const int32_t* rho, const int32_t* rx,
+                            ttsg::Prec p) {
     size_t sk = 0;
     for (int mu = 0; mu < d; ++mu) sk += (size_t)rho[mu] * n[mu] * rx[mu + 1] + (size_t)rho[mu] * rx[mu] + 64;
     size_t core = 0, rmax = 1;
@@ -231,7 +335,7 @@ static size_t round_rand_ws(int32_t d, const int32_t* n, const int32_t* r, const
         core = std::max(core, (size_t)rx[mu] * n[mu] * rx[mu + 1]);
         rmax = std::max(rmax, (size_t)std::max(rho[mu], rx[mu]));
     }
-    const size_t need = stta_ws(d, n, rho, rx, nullptr, r) + sk * 8 + (8 * core + 12 * rmax * rmax) * 8 +
+    const size_t need = stta_ws_loose(d, n, rho, rx, r) + stta_ws(d, n, rho, rx, nullptr, r, p) + sk * 8 + (8 * core + 12 * rmax * rmax) * 8 +
                         (size_t)d * 16 * rmax * rmax * 8 + (4 << 20) + ttsg::tt_svd_extra_bytes(d, n, rx);
     return need + kSplitSlack;
 }
@@ -252,7 +356,7 @@ int ttsg_round_rand(int32_t d, const int32_t* n, const int32_t* r, const double*
         check_ptrs(d, (const void* const*)x, "round_rand x");
         check_ptrs(d, (const void* const*)out, "round_rand out");
         TTSG_CHECK(out_r != nullptr, TTSG_ERR_ARG, "round_rand: null out_r");
-        ttsg::Workspace W(ws, ws_bytes, round_rand_ws(d, n, r, rho, rx), S(stream));
+        ttsg::Workspace W(ws, ws_bytes, round_rand_ws(d, n, r, rho, rx, prec_of(precision)), S(stream));
         ttsg::Arena& ar = W.arena;
         std::vector<double*> psi(d), om(d - 1);
         for (int mu = 0; mu < d; ++mu) psi[mu] = ar.get<double>((int64_t)rho[mu] * n[mu] * rx[mu + 1]);
@@ -291,7 +395,7 @@ int ttsg_stta_sketch_workspace_size(int32_t d, const int32_t* n, const int32_t* 
         TTSG_CHECK(bytes != nullptr, TTSG_ERR_ARG, "stta_sketch_workspace_size: null output");
         (void)prec_of(precision);
         if (R) check_shape(d, n, R, "stta A");
-        *bytes = stta_ws(d, n, rho, rx, R, r) + kSplitSlack;
+        *bytes = stta_ws(d, n, rho, rx, R, r, prec_of(precision));
         return 0;
     });
 }
@@ -304,7 +408,7 @@ int ttsg_round_rand_workspace_size(int32_t d, const int32_t* n, const int32_t* r
         check_shape(d, n, rx, "round_rand rx");
         TTSG_CHECK(bytes != nullptr, TTSG_ERR_ARG, "round_rand_workspace_size: null output");
         (void)prec_of(precision);
-        *bytes = round_rand_ws(d, n, r, rho, rx);
+        *bytes = round_rand_ws(d, n, r, rho, rx, prec_of(precision));
         return 0;
     });
 }
@@ -621,7 +725,7 @@ int ttsg_precond_round(int32_t d, const int32_t* n, int32_t zeta, const double* 
         }
         size_t zc = 0;
         for (int mu = 0; mu < d; ++mu) zc += (size_t)r[mu] * n[mu] * r[mu + 1] + 64;
-        const size_t need = stta_ws(d, n, rho, rx, nullptr, r) + 2 * sk * 8 + ee * 8 + zc * 8 +
+        const size_t need = stta_ws_loose(d, n, rho, rx, r) + 2 * sk * 8 + ee * 8 + zc * 8 +
                             (8 * core + 12 * rmax * rmax) * 8 + (size_t)d * 16 * rmax * rmax * 8 + (4 << 20) +
                             ttsg::tt_svd_extra_bytes(d, n, rx);
         ttsg::Workspace W(ws, ws_bytes, need + kSplitSlack, S(stream));

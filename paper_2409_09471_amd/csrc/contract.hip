@@ -550,6 +550,8 @@ void contract(Prec p, const ContractDesc& d, const void* A, const void* B, void*
     }
 }
 
+bool autotune_is_on() { return autotune_on(); }
+
 int autotune_set(int on) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     const int old = g_tune_on ? 1 : 0;

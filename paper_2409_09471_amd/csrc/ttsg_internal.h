@@ -139,6 +139,7 @@ void contract(Prec p, const ContractDesc& d, const void* A, const void* B, void*
               Arena* ar = nullptr);
 // Tile autotuner of the contraction kernel (contract.hip).
 int autotune_set(int on);
+bool autotune_is_on();
 int autotune_save(const char* path);
 int autotune_load(const char* path);
 int autotune_clear();

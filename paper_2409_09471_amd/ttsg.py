@@ -65,6 +65,7 @@ EXPORTED = [
     "ttsg_grad_kron_sum", "ttsg_tt_axpby", "ttsg_stats_enable", "ttsg_stats_read",
     "ttsg_sgmres_solve_ex", "ttsg_sgmres_workspace_size", "ttsg_expsum", "ttsg_precond_round",
     "ttsg_kr_sketch_workspace_size", "ttsg_stta_sketch_workspace_size", "ttsg_round_rand_workspace_size",
+    "ttsg_stta_sketch_noalloc",
 ]
 
 STAT_CLASSES = {0: "contract_f64", 1: "contract_f32", 2: "contract_bf16", 3: "qr", 4: "svd_jacobi",
@@ -291,6 +292,26 @@ def stta_sketch(x, X, Y, rx, rho, A=None, precision: int = PREC_F64):
     _check(lib().ttsg_stta_sketch(d, _i32(n), _i32(rho), _ptrs(Y), _i32(rx), _ptrs(X), Rp, Ap, _i32(ranks_of(x)),
                                   _ptrs(x), _ptrs(Psi), _ptrs(Om), precision, ctypes.c_void_p(ws.data_ptr()), nb,
                                   _stream()), "ttsg_stta_sketch")
+    return Psi, Om
+
+
+def stta_sketch_noalloc(x, X, Y, rx, rho, A=None, precision: int = PREC_F64, out=None):
+    """ttsg_stta_sketch_noalloc: the sketch with the library's static scratch
+    (no workspace).  `out` = (Psi, Om) lists to write into (allocated here
+    when None)."""
+    d = len(x)
+    n = sizes_of(x)
+    dev = x[0].device
+    if out is None:
+        Psi = [torch.empty((rho[k], n[k], rx[k + 1]), dtype=torch.float64, device=dev) for k in range(d)]
+        Om = [torch.empty((rho[b], rx[b]), dtype=torch.float64, device=dev) for b in range(1, d)]
+    else:
+        Psi, Om = out
+    Rp = _i32(op_ranks(A)) if A is not None else None
+    Ap = _ptrs(A) if A is not None else None
+    _check(lib().ttsg_stta_sketch_noalloc(d, _i32(n), _i32(rho), _ptrs(Y), _i32(rx), _ptrs(X), Rp, Ap,
+                                          _i32(ranks_of(x)), _ptrs(x), _ptrs(Psi), _ptrs(Om), precision, _stream()),
+           "ttsg_stta_sketch_noalloc")
     return Psi, Om
 
 

@@ -134,3 +134,31 @@ def test_workspace_queries_without_gpu(lib):
     opts.precision = 0
     assert lib.ttsg_sgmres_workspace_size(d, n, R, big, 80, rho, rx, ctypes.byref(opts), None,
                                           ctypes.byref(nb)) == ttsg.ERR_CAPACITY
+
+
+def test_noalloc_sketch_rejects_shapes_beyond_its_buffer(lib):
+    """ttsg_stta_sketch_noalloc refuses shapes whose scratch exceeds its static
+    buffer with TTSG_ERR_WS before touching the device (d = 20, n = 128,
+    ranks 128, rho 160, operator rank 3 needs about 264 MiB)."""
+    from paper_2409_09471_amd import ttsg
+    d = 20
+    I = lambda v: (ctypes.c_int32 * len(v))(*v)  # noqa: E731
+    n = I([128] * d)
+    r = I([1] + [128] * (d - 1) + [1])
+    rx = I([1] + [128] * (d - 1) + [1])
+    rho = I([1, 128] + [160] * (d - 3) + [128, 1])
+    R = I([1] + [3] * (d - 1) + [1])
+    nb = ctypes.c_size_t(0)
+    assert lib.ttsg_stta_sketch_workspace_size(d, n, rho, rx, R, r, 0, ctypes.byref(nb)) == 0
+    assert nb.value > (128 << 20)
+    fake = (ctypes.c_void_p * d)(*([16] * d))    # never dereferenced: the size check comes first
+    rc = lib.ttsg_stta_sketch_noalloc(d, n, rho, fake, rx, fake, R, fake, r, fake, fake, fake, 0, None)
+    assert rc == ttsg.ERR_WS
+    lib.ttsg_last_error.restype = ctypes.c_char_p
+    assert b"static buffer" in lib.ttsg_last_error()
+    # the C2-shaped sketch of A v_k (d = 10, n = 64, ranks 64, rho 84, R = 3) fits
+    d = 10
+    n, r, rx = I([64] * d), I([1] + [64] * 9 + [1]), I([1] + [64] * 9 + [1])
+    rho, R = I([1, 64] + [84] * 7 + [64, 1]), I([1] + [3] * 9 + [1])
+    assert lib.ttsg_stta_sketch_workspace_size(d, n, rho, rx, R, r, 0, ctypes.byref(nb)) == 0
+    assert nb.value <= (128 << 20)
