@@ -145,7 +145,8 @@ def tt_sgmres(A: Cores, b: Cores, S: List[np.ndarray], X: Cores, Y: Cores, *,
               rcond: float = 1e-12, x0: Optional[Cores] = None,
               track_true_residual: bool = False, max_cycles: int = 50,
               fixed_iterations: Optional[int] = None, keep_basis: bool = False,
-              precond=None, ls: str = "pinv", final_rcond: Optional[float] = None):
+              precond=None, ls: str = "pinv", final_rcond: Optional[float] = None,
+              solution: bool = True):
     """Sketched TT-GMRES.  Returns (x, info).
 
     rounding: "stta" (Alg. 4: randomized streaming rounding through STTA) or
@@ -170,7 +171,10 @@ def tt_sgmres(A: Cores, b: Cores, S: List[np.ndarray], X: Cores, Y: Cores, *,
               Arnoldi relation, eq. sketched_argmin2, residual from
               eq. sketched_residualnorm; W_k is not formed).
     final_rcond: pseudo-inverse cutoff of the final solution's recovery
-              (default rcond)."""
+              (default rcond).
+    solution: False stops after the first cycle's iterations, before the
+              final solution is formed (x is then None): for comparisons of the
+              iteration's own quantities at sizes where forming x is costly."""
     final_tol = round_tol if final_tol is None else final_tol
     final_rcond = rcond if final_rcond is None else final_rcond
     nb = ttm.norm(b)
@@ -254,6 +258,8 @@ def tt_sgmres(A: Cores, b: Cores, S: List[np.ndarray], X: Cores, Y: Cores, *,
                 sk.append(skm.stta_sketch(vnext, X, Y))
         info["iterations"] = total
         info["y"] = y
+        if not solution:
+            break
         if keep_basis:
             info["basis"], info["sketches"] = basis, sk
             info["W"], info["Sr0"] = (np.array(W).T if W else None), Sr0

@@ -12,6 +12,7 @@
 // Q was not nearly orthonormal); callers read the flag at their next
 // synchronization and redo the factorization with Householder QR.
 #include <cmath>
+#include <mutex>
 
 #include "tt_ops.h"
 
@@ -121,6 +122,66 @@ __global__ __launch_bounds__(CQ_T) void k_chol_inv(int c, const double* __restri
     slot_end(slot);
 }
 
+// The same elimination for 64 < c <= 128: the c x c working matrix lives in
+// dynamic LDS (ld c | 1, 132 KB at c = 128), thread (rg, l) owns column
+// l = tid % 128 and every 8th row.  The second pass's product R2 R1 is left to
+// a matrix-core contraction (R1 does not fit beside the working matrix).
+constexpr int CQ_BIG = 128;
+constexpr int CQ_RG2 = CQ_T / CQ_BIG;
+
+__global__ __launch_bounds__(CQ_T) void k_chol_inv_big(int c, const double* __restrict__ G, double* __restrict__ R,
+                                                        double* __restrict__ Ri, int* __restrict__ flag,
+                                                        int second_pass, DevSlot* slot) {
+    extern __shared__ double lds[];
+    __shared__ double d0[CQ_BIG], pd[CQ_BIG], rd[CQ_BIG];
+    __shared__ int s_bad;
+    slot_begin(slot);
+    const int ld = c | 1;
+    double* A = lds;   // A[i * ld + l]
+    const int tid = threadIdx.x;
+    for (int e = tid; e < c * c; e += CQ_T) {
+        const int l = e / c, i = e - l * c;
+        A[i * ld + l] = i <= l ? G[i + (int64_t)l * c] : 0.0;
+    }
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    for (int j = tid; j < c; j += CQ_T) d0[j] = A[j * ld + j];
+    __syncthreads();
+    const int l = tid % CQ_BIG, rg = tid / CQ_BIG;
+    for (int j = 0; j < c; ++j) {
+        double p = A[j * ld + j];
+        const double dj = d0[j];
+        const bool ok = p > 1e-10 * dj && p <= 4.0 * dj && dj < INFINITY;
+        if (!ok) p = (dj > 0.0 && dj < INFINITY) ? dj : 1.0;   // keep going; the flag discards the result
+        if (tid == 0) {
+            pd[j] = p;
+            if (!ok) s_bad = 1;
+        }
+        if (l < c) {
+            const double ip = 1.0 / p;
+            const double x = l == j ? 1.0 : A[j * ld + l];
+            const int hi = l > j ? l : c - 1;
+            for (int i = j + 1 + rg; i <= hi; i += CQ_RG2) A[i * ld + l] -= (A[j * ld + i] * ip) * x;
+        }
+        __syncthreads();
+    }
+    for (int j = tid; j < c; j += CQ_T) rd[j] = sqrt(pd[j]);
+    __syncthreads();
+    for (int e = tid; e < c * c; e += CQ_T) {
+        const int cl = e / c, j = e - cl * c;
+        const double v = cl > j ? A[j * ld + cl] / rd[j] : (cl == j ? rd[j] : 0.0);
+        R[j + (int64_t)cl * c] = v;
+        if (second_pass && fabs(v - (cl == j ? 1.0 : 0.0)) > 0.1) s_bad = 1;
+        Ri[j + (int64_t)cl * c] = j <= cl ? (j == cl ? 1.0 : A[cl * ld + j]) / rd[cl] : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0 && s_bad) flag[0] = 1;
+    slot_end(slot);
+}
+
+std::mutex g_cq_mu;
+size_t g_cq_lds = 0;
+
 __global__ void k_zero_flags(int n, int* __restrict__ f) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) f[i] = 0;
@@ -134,11 +195,11 @@ void zero_flags(int n, int* f, hipStream_t st) {
     TTSG_HIP(hipGetLastError());
 }
 
-bool cholqr_fits(int m, int c) { return c >= 1 && c <= CQ_MAX && m >= c; }
+bool cholqr_fits(int m, int c) { return c >= 1 && c <= CQ_BIG && m >= c; }
 
 void cholqr2(int m, int c, const double* X, int64_t xr, int64_t xc, double* Q, int64_t qr, int64_t qc, double* R,
              int* flag, Arena& ar, hipStream_t st, double* RT) {
-    TTSG_CHECK(cholqr_fits(m, c), TTSG_ERR_ARG, "cholqr2: needs m >= c and c <= 64");
+    TTSG_CHECK(cholqr_fits(m, c), TTSG_ERR_ARG, "cholqr2: needs m >= c and c <= 128");
     const size_t mark = ar.mark();
     double* G = ar.get<double>((int64_t)c * c);
     double* R1 = ar.get<double>((int64_t)c * c);
@@ -168,10 +229,44 @@ void cholqr2(int m, int c, const double* X, int64_t xr, int64_t xc, double* Q, i
         contract(Prec::F64, d, Y, Ri, Z, st, &ar);
     };
     auto chol = [&](double* Rf, double* Rfi, int second, const double* Rprev, double* Rout, double* RTout) {
-        StatScope sc(TTSG_ST_QR, (double)c * c * c / 3.0 + (double)c * c * c / 3.0, 0.0, st);
-        hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(CQ_T), 0, st, c, G, Rf, Rfi, flag, second, Rprev, Rout, RTout,
-                           sc.slot());
-        TTSG_HIP(hipGetLastError());
+        if (c <= CQ_MAX) {
+            StatScope sc(TTSG_ST_QR, (double)c * c * c / 3.0 + (double)c * c * c / 3.0, 0.0, st);
+            hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(CQ_T), 0, st, c, G, Rf, Rfi, flag, second, Rprev, Rout,
+                               RTout, sc.slot());
+            TTSG_HIP(hipGetLastError());
+            return;
+        }
+        const size_t lds = (size_t)(c | 1) * c * sizeof(double);
+        {
+            std::lock_guard<std::mutex> lk(g_cq_mu);
+            if (lds > g_cq_lds) {
+                TTSG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_inv_big),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                g_cq_lds = lds;
+            }
+        }
+        {
+            StatScope sc(TTSG_ST_QR, (double)c * c * c / 3.0 + (double)c * c * c / 3.0, 0.0, st);
+            hipLaunchKernelGGL(k_chol_inv_big, dim3(1), dim3(CQ_T), lds, st, c, G, Rf, Rfi, flag, second,
+                               sc.slot());
+            TTSG_HIP(hipGetLastError());
+        }
+        if (second) {
+            // R = R2 R1 (column-major c x c) and, when asked, R^T
+            ContractDesc d = cdesc(c, c, c);
+            d.am = idx1(1);
+            d.ak = idx1(c);
+            d.bk = idx1(1);
+            d.bn = idx1(c);
+            d.cm = idx1(1);
+            d.cn = idx1(c);
+            contract(Prec::F64, d, Rf, Rprev, Rout, st, &ar);
+            if (RTout != nullptr) {
+                d.cm = idx1(c);
+                d.cn = idx1(1);
+                contract(Prec::F64, d, Rf, Rprev, RTout, st, &ar);
+            }
+        }
     };
     gram(X, xr, xc);
     chol(R1, R1i, 0, nullptr, nullptr, nullptr);

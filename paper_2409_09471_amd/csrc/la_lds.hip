@@ -306,6 +306,235 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
     slot_end(slot, (unsigned long long)sweeps_done);
 }
 
+// One-sided Jacobi for 64 < c <= 128 columns and up to 16 JR rows: 64 lane
+// groups of 16 (1024 threads), one column pair per group and round.  The m x c
+// matrix fills the LDS (149 x 128 doubles = 149 KB at the largest shape used),
+// so the rotation accumulator, when one is asked for (ACC), is kept in global
+// memory: a group loads its pair's two accumulator columns at the start of the
+// round (their latency overlaps the dot products) and stores them rotated
+// before the round's barrier.  Without ACC only the rotated matrix B = A V and
+// the singular values are produced (callers that need a factor of V form it
+// from B).  Norm reductions are fixed-order, so results do not depend on
+// wavefront timing.
+constexpr int JTB = 1024;
+constexpr int JB_CMAX = 128;
+
+template <int JR, bool ACC>
+__global__ __launch_bounds__(JTB) void k_jacobi_big(JacobiBatch jb, int maxsweeps, DevSlot* slot) {
+    extern __shared__ double lds[];
+    slot_begin(slot);
+    int sweeps_done = 0;
+    __shared__ int s_rot;
+    __shared__ unsigned long long s_moff, s_cmax;
+    __shared__ double s_part[JTB / 64];
+    __shared__ double s_cn[JB_CMAX], s_sig[JB_CMAX];
+    __shared__ int s_perm[JB_CMAX], s_rank[JB_CMAX];
+    __shared__ int s_cact;
+    __shared__ double s_fro;
+    const int bi = blockIdx.x;
+    const int m = jb.m[bi], c = jb.c[bi], lda = jb.lda[bi];
+    const double tol = jb.tol[bi];
+    double* Ag = jb.A[bi];
+    double* Vg = jb.V[bi];
+    const int ldm = m | 1;
+    double* A = lds;
+    const int tid = threadIdx.x;
+    const int grp = tid / JG, lt = tid - grp * JG;
+    for (int e = tid; e < m * c; e += JTB) {
+        const int j = e / m, i = e - j * m;
+        A[j * ldm + i] = Ag[(int64_t)j * lda + i];
+    }
+    if (tid == 0) {
+        s_rot = 0;
+        s_moff = 0ull;
+        s_cmax = 0ull;
+    }
+    __syncthreads();
+    // column norms (one lane group per column) and the Frobenius norm as their
+    // sum in column order
+    for (int l = grp; l < c; l += JTB / JG) {
+        double s2 = 0.0;
+        for (int i = lt; i < m; i += JG) s2 += A[l * ldm + i] * A[l * ldm + i];
+        s2 = row_sum16(s2);
+        if (lt == 0) {
+            s_cn[l] = s2;
+            atomicMax(&s_cmax, (unsigned long long)__double_as_longlong(s2));
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double f = 0.0;
+        for (int l = 0; l < c; ++l) f += s_cn[l];
+        s_fro = f;
+    }
+    __syncthreads();
+    const double nz = 2.0 * m * 2.220446049250313e-16;
+    const double tiny0 = nz * nz * s_fro;
+    const double tol2 = tol * tol;
+    double drop2 = jb.drop_abs2[bi];
+    if (jb.drop_rel2[bi] > 0.0) drop2 = fmax(drop2, jb.drop_rel2[bi] * __longlong_as_double((long long)s_cmax));
+    const double tiny = fmax(tiny0, drop2);
+    // active columns first (index order), the rest after them
+    if (tid == 0) {
+        int pos = 0;
+        for (int l = 0; l < c; ++l)
+            if (s_cn[l] > tiny) s_perm[pos++] = l;
+        s_cact = pos;
+        for (int l = 0; l < c; ++l)
+            if (!(s_cn[l] > tiny)) s_perm[pos++] = l;
+    }
+    __syncthreads();
+    const int c_act = s_cact;
+    if (c_act < c) {
+        for (int e = tid; e < m * c; e += JTB) {
+            const int j = e / m, i = e - j * m;
+            A[j * ldm + i] = Ag[(int64_t)s_perm[j] * lda + i];
+        }
+    }
+    if (ACC) {
+        for (int e = tid; e < c * c; e += JTB) {
+            const int j = e / c, i = e - j * c;
+            Vg[(int64_t)j * c + i] = (i == s_perm[j]) ? 1.0 : 0.0;
+        }
+    }
+    __syncthreads();
+    constexpr int VR = JB_CMAX / JG;   // accumulator rows per lane
+    const int cp = c_act + (c_act & 1);
+    const int npair = cp / 2;
+    const int nround = cp - 1;
+    for (int sweep = 0; sweep < maxsweeps && cp > 1; ++sweep) {
+        int rotated = 0;
+        double mo2 = 0.0;
+        sweeps_done = sweep + 1;
+        int p = grp == 0 ? cp - 1 : grp, q = grp == 0 ? 0 : cp - 1 - grp;
+        for (int r = 0; r < nround; ++r) {
+            if (grp < npair && p < c_act && q < c_act) {
+                double* ap = A + p * ldm;
+                double* aq = A + q * ldm;
+                double* vp = Vg + (int64_t)p * c;
+                double* vq = Vg + (int64_t)q * c;
+                double xp[JR], xq[JR], yp[VR], yq[VR];
+                if (ACC) {
+#pragma unroll
+                    for (int u = 0; u < VR; ++u) {
+                        const int i = lt + u * JG;
+                        const int ic = i < c ? i : 0;
+                        yp[u] = vp[ic];
+                        yq[u] = vq[ic];
+                    }
+                }
+                double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                for (int t = 0; t < JR; ++t) {
+                    const int i = lt + t * JG;
+                    xp[t] = 0.0;
+                    xq[t] = 0.0;
+                    if (i < m) {
+                        xp[t] = ap[i];
+                        xq[t] = aq[i];
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < JR; ++t) {
+                    al += xp[t] * xp[t];
+                    be += xq[t] * xq[t];
+                    ga += xp[t] * xq[t];
+                }
+                al = row_sum16(al);
+                be = row_sum16(be);
+                ga = row_sum16(ga);
+                const double g2 = ga * ga, ab = al * be;
+                if (al > tiny && be > tiny) {
+                    mo2 = fmax(mo2, g2 * rcp_nr(ab));
+                    if (g2 > tol2 * ab) {
+                        const double dd = be - al;
+                        const double qq = fma(dd, dd, 4.0 * g2);
+                        double t = 2.0 * ga * rcp_nr(fabs(dd) + qq * rsq_nr(qq));
+                        if (dd < 0.0) t = -t;
+                        const double cs = rsq_nr(fma(t, t, 1.0));
+                        const double sn = cs * t;
+#pragma unroll
+                        for (int u = 0; u < JR; ++u) {
+                            const int i = lt + u * JG;
+                            if (i < m) {
+                                ap[i] = cs * xp[u] - sn * xq[u];
+                                aq[i] = sn * xp[u] + cs * xq[u];
+                            }
+                        }
+                        if (ACC) {
+#pragma unroll
+                            for (int u = 0; u < VR; ++u) {
+                                const int i = lt + u * JG;
+                                if (i < c) {
+                                    vp[i] = cs * yp[u] - sn * yq[u];
+                                    vq[i] = sn * yp[u] + cs * yq[u];
+                                }
+                            }
+                        }
+                        rotated = 1;
+                    }
+                }
+            }
+            if (grp == 0) {
+                q += 1;
+            } else {
+                p = p + 1 == cp - 1 ? 0 : p + 1;
+                q = q + 1 == cp - 1 ? 0 : q + 1;
+            }
+            __syncthreads();
+        }
+        if (rotated && lt == 0) s_rot = 1;
+        if (lt == 0 && mo2 > 0.0) atomicMax(&s_moff, (unsigned long long)__double_as_longlong(mo2));
+        __syncthreads();
+        const int any = s_rot;
+        const double moff = __longlong_as_double((long long)s_moff);
+        __syncthreads();
+        if (tid == 0) {
+            s_rot = 0;
+            s_moff = 0ull;
+        }
+        if (any == 0 || moff < 0.01 * tol) break;
+    }
+    __syncthreads();
+    // singular values = column norms, output sorted in descending order (ties
+    // by column index)
+    for (int l = grp; l < c; l += JTB / JG) {
+        const double* al = A + l * ldm;
+        double s2 = 0.0;
+        for (int i = lt; i < m; i += JG) s2 += al[i] * al[i];
+        s2 = row_sum16(s2);
+        if (lt == 0) s_sig[l] = sqrt(s2);
+    }
+    __syncthreads();
+    for (int l = tid; l < c; l += JTB) {
+        const double v = s_sig[l];
+        int rk = 0;
+        for (int t = 0; t < c; ++t) rk += (s_sig[t] > v || (s_sig[t] == v && t < l)) ? 1 : 0;
+        s_rank[l] = rk;
+        jb.sig[bi][rk] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < m * c; e += JTB) {
+        const int j = e / m, i = e - j * m;
+        Ag[(int64_t)s_rank[j] * lda + i] = A[j * ldm + i];
+    }
+    if (ACC) {
+        // sort the accumulator's columns through the LDS (free again: m >= c)
+        __syncthreads();
+        const int ldv = c | 1;
+        for (int e = tid; e < c * c; e += JTB) {
+            const int j = e / c, i = e - j * c;
+            A[j * ldv + i] = Vg[(int64_t)j * c + i];
+        }
+        __syncthreads();
+        for (int e = tid; e < c * c; e += JTB) {
+            const int j = e / c, i = e - j * c;
+            Vg[(int64_t)s_rank[j] * c + i] = A[j * ldv + i];
+        }
+    }
+    slot_end(slot, (unsigned long long)sweeps_done);
+}
+
 // Leaf i of a TSQR level: rows [r0, r1) of the column-major m x c matrix A.
 __device__ __forceinline__ void leaf_rows(int m, int nleaves, int i, int& r0, int& r1) {
     r0 = (int)(((int64_t)i * m) / nleaves);
@@ -659,6 +888,71 @@ void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st) {
         } else {
             allow_lds(reinterpret_cast<const void*>(&k_jacobi_lds<JROWS>), lds, g_lds_jacobi);
             hipLaunchKernelGGL(k_jacobi_lds<JROWS>, dim3(cnt), dim3(JT), lds, st, jb, 30, scope.slot());
+        }
+        TTSG_HIP(hipGetLastError());
+    }
+}
+
+size_t g_lds_big8 = 0, g_lds_big10 = 0, g_lds_big8v = 0, g_lds_big10v = 0;
+
+size_t jacobi_big_lds_bytes(int m, int c) { return (size_t)(m | 1) * c * 8; }
+
+// 64 < c <= 128 columns, m <= 160 rows, and the matrix within 152 KB of LDS
+// (the kernel's static arrays take about 4 KB more)
+bool jacobi_big_fits(int m, int c) {
+    return m >= c && c <= JB_CMAX && m <= JG * 10 && jacobi_big_lds_bytes(m, c) <= 152 * 1024 + 1024;
+}
+
+void svd_jacobi_big(const std::vector<JacobiJob>& jobs, bool accumulate, hipStream_t st) {
+    size_t i = 0;
+    while (i < jobs.size()) {
+        JacobiBatch jb{};
+        size_t lds = 0;
+        int cnt = 0, mmax = 0, cmax = 0;
+        double flops = 0.0;
+        for (; i < jobs.size() && cnt < 32; ++i, ++cnt) {
+            const JacobiJob& j = jobs[i];
+            TTSG_CHECK(jacobi_big_fits(j.m, j.c), TTSG_ERR_ARG, "jacobi job does not fit the 128-column kernel");
+            TTSG_CHECK(!accumulate || j.V != nullptr, TTSG_ERR_ARG, "jacobi: accumulator requested without V");
+            jb.m[cnt] = j.m;
+            jb.c[cnt] = j.c;
+            jb.lda[cnt] = j.lda;
+            jb.A[cnt] = j.A;
+            jb.V[cnt] = accumulate ? j.V : nullptr;
+            jb.sig[cnt] = j.sig;
+            jb.tol[cnt] = j.tol > 0.0 ? j.tol : 4.0 * j.m * 2.220446049250313e-16;
+            jb.drop_abs2[cnt] = j.drop_abs2;
+            jb.drop_rel2[cnt] = j.drop_rel2;
+            lds = std::max(lds, jacobi_big_lds_bytes(j.m, j.c));
+            mmax = std::max(mmax, j.m);
+            cmax = std::max(cmax, j.c);
+            flops += 0.5 * j.c * (j.c - 1.0) * ((accumulate ? 12.0 : 6.0) * j.m + (accumulate ? 6.0 * j.c : 0.0));
+            if (bounds_checking()) {
+                check_range(j.A, ((int64_t)(j.c - 1) * j.lda + j.m) * 8, "jacobi_big A");
+                if (accumulate) check_range(j.V, (int64_t)j.c * j.c * 8, "jacobi_big V");
+                check_range(j.sig, (int64_t)j.c * 8, "jacobi_big sig");
+            }
+        }
+        jb.count = cnt;
+        StatScope scope(TTSG_ST_SVD, flops, 0.0, st);
+        scope.shape(cnt, mmax, cmax, 0, 0);
+        const bool r8 = mmax <= 8 * JG;
+        if (accumulate) {
+            if (r8) {
+                allow_lds(reinterpret_cast<const void*>(&k_jacobi_big<8, true>), lds, g_lds_big8v);
+                hipLaunchKernelGGL((k_jacobi_big<8, true>), dim3(cnt), dim3(JTB), lds, st, jb, 30, scope.slot());
+            } else {
+                allow_lds(reinterpret_cast<const void*>(&k_jacobi_big<10, true>), lds, g_lds_big10v);
+                hipLaunchKernelGGL((k_jacobi_big<10, true>), dim3(cnt), dim3(JTB), lds, st, jb, 30, scope.slot());
+            }
+        } else {
+            if (r8) {
+                allow_lds(reinterpret_cast<const void*>(&k_jacobi_big<8, false>), lds, g_lds_big8);
+                hipLaunchKernelGGL((k_jacobi_big<8, false>), dim3(cnt), dim3(JTB), lds, st, jb, 30, scope.slot());
+            } else {
+                allow_lds(reinterpret_cast<const void*>(&k_jacobi_big<10, false>), lds, g_lds_big10);
+                hipLaunchKernelGGL((k_jacobi_big<10, false>), dim3(cnt), dim3(JTB), lds, st, jb, 30, scope.slot());
+            }
         }
         TTSG_HIP(hipGetLastError());
     }

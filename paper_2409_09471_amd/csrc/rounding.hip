@@ -182,8 +182,11 @@ size_t tt_svd_extra_bytes(int d, const int* n, const int* r) {
         mx = std::max(mx, e);
         rmax = std::max(rmax, (size_t)std::max(r[mu], r[mu + 1]));
     }
-    // + the host read-back block (squared norm, flags, per-bond singular values)
-    return (sum + 2 * mx + 6 * 64 * 64 + 256) * sizeof(double) + (size_t)(d + 1) * 64 +
+    // four core-sized buffers (A, Q, T, QV), the snapshot of every core, the
+    // first CholQR2 pass's Q, the c x c factors (R, V, the Jacobi buffer and
+    // CholQR2's five), + the host read-back block (squared norm, flags,
+    // per-bond singular values)
+    return (sum + 6 * mx + 12 * rmax * rmax + 4096) * sizeof(double) + (size_t)(d + 1) * 64 +
            (4 + (rmax + 1) * d) * sizeof(double) + 256;
 }
 
@@ -202,6 +205,7 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
     double* Rm = ar.get<double>(maxr * maxr);
     double* V = ar.get<double>(maxr * maxr);
     double* QV = ar.get<double>(maxcore);
+    double* Jb = ar.get<double>(maxr * maxr);   // 128-column Jacobi: R in, R V out
     double* tau = ar.get<double>(maxr);
     double* sig = ar.get<double>(maxr);
     double* part = ar.get<double>(1024);
@@ -323,7 +327,27 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
                     extract_r(c, c, A, m, Rm, c, st);
                 }
             };
+            // 64 < c <= 128: one-sided Jacobi on R itself (the matrix fills the
+            // LDS, so no rotation accumulator): R V = B = U_R S gives U_R = B / s,
+            // and S V_R^T = U_R^T R is one small matrix-core product afterwards
+            const bool big = c > 64 && jacobi_big_fits(c, c);
             auto small_svd = [&](bool have_rt) {
+                if (big) {
+                    // U_R = B / s is orthonormal only to the Jacobi tolerance, and the
+                    // reconstruction Q U_k (U_k^T R) errs by about that much relative
+                    // to ||R||: the tolerance follows the rounding tolerance
+                    // (1e-3 of it, at most 1e-11, at least 4 c eps)
+                    const double jt = std::max(4.0 * c * 2.220446049250313e-16, std::min(1e-11, 1e-3 * tol));
+                    copy_f64((int64_t)c * c, Rm, Jb, st);
+                    svd_jacobi_big({JacobiJob{c, c, c, Jb, nullptr, bond_blk(mu), jt, delta * delta / (16.0 * c),
+                                              0.0}},
+                                   false, st);
+                    const double* hr =
+                        static_cast<const double*>(read_back(bond_blk(mu), sbk * sizeof(double), hb.data(), st));
+                    std::copy(hr, hr + sbk, hb.begin());
+                    hsig.assign(hb.begin(), hb.begin() + c);
+                    return;
+                }
                 // SVD of R through one-sided Jacobi on R^T (rows of a QR factor of a
                 // graded unfolding converge in few sweeps): R^T V' = U' S gives
                 // R = V' S U'^T, i.e. U_R = V' and S V_R^T = (U' S)^T.  Relative
@@ -364,7 +388,28 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             bool sorted = true;
             for (int t = 0; t < c; ++t) sorted = sorted && perm[t] == t;
             const double* Uk = V;
-            if (!sorted) {
+            if (big) {
+                // U_k = B[:, :k] / s (zero for a zero singular value)
+                std::vector<int> pk(k);
+                std::vector<double> inv(k);
+                for (int t = 0; t < k; ++t) {
+                    pk[t] = t;
+                    inv[t] = sd[t] > 0.0 ? 1.0 / sd[t] : 0.0;
+                }
+                hold_i.push_back(pk);
+                hold_d.push_back(inv);
+                upload_perm(hold_i.back(), hold_d.back(), perm_dev, fac_dev, st);
+                gather_cols(c, k, Jb, c, V, c, perm_dev, fac_dev, st);
+                // QV (column-major c x k) = R^T U_k, i.e. S V_R^T read row-major
+                ContractDesc dr = cdesc(c, k, c);
+                dr.am = idx1(c);
+                dr.ak = idx1(1);
+                dr.bk = idx1(1);
+                dr.bn = idx1(c);
+                dr.cm = idx1(1);
+                dr.cn = idx1(c);
+                contract(Prec::F64, dr, Rm, V, QV, st, &ar);
+            } else if (!sorted) {
                 std::vector<int> pk(perm.begin(), perm.begin() + k);
                 hold_i.push_back(pk);
                 hold_d.push_back(std::vector<double>(k, 1.0));
@@ -390,7 +435,7 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
             ar.release(mk);
             // S V_R^T (row-major k x c == column-major c x k) = (U' S)[:, perm]:
             // the leading k columns of QV when sorted
-            if (!sorted) {
+            if (!sorted && !big) {
                 gather_cols(c, k, QV, c, Rm, c, perm_dev, fac_dev, st);
                 copy_f64((int64_t)c * k, Rm, QV, st);
             }
@@ -481,7 +526,7 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
     for (int b = 1; b <= d - 1; ++b) u_tot += rx[b] + (rx[b] + 1) / 2;
     double* Uall = ar.get<double>(std::max<int64_t>(u_tot, 1));
     std::vector<TsqrPlan> plans(d);
-    std::vector<bool> use_tsqr(d, false), use_small(d, false);
+    std::vector<bool> use_tsqr(d, false), use_small(d, false), use_big(d, false);
     std::vector<int*> pivb(d, nullptr);
     std::vector<QrJob> qjobs;
     int64_t maxT = 1;
@@ -497,6 +542,13 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         Wk[b] = ar.get<double>((int64_t)c * c);
         use_small[b] = qr_small_fits(m, c);
         use_tsqr[b] = !use_small[b] && tsqr_fits(m, c);
+        // 64 < rx_b <= 128: one-sided Jacobi on Omega itself with the rotations
+        // accumulated (Omega V = B = U S, so Omega^+ = (V S^-1) (B S^-1)^T)
+        use_big[b] = !use_small[b] && !use_tsqr[b] && c > 64 && jacobi_big_fits(m, c);
+        if (use_big[b]) {
+            transpose2d(m, c, Omega[b - 1], c, Ab[b], m, st);    // column-major m x c
+            continue;
+        }
         if (use_small[b]) {
             // column-pivoted: R^T is then graded and the Jacobi SVD below
             // converges in fewer sweeps; Omega is read row-major as it is and
@@ -526,20 +578,24 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
     // all small QRs of the bonds in one launch
     if (!qjobs.empty()) qr_small_batched(qjobs, st);
     {
-        std::vector<JacobiJob> jobs;
+        std::vector<JacobiJob> jobs, big_jobs;
         for (int b = 1; b <= d - 1; ++b) {
             // singular values below rcond * s_max are dropped, so rotations
             // that leave 1e-3 rcond of non-orthogonality change nothing kept
             const double jt = std::max(4.0 * rx[b] * 2.220446049250313e-16, 1e-3 * rcond);
             // singular values below rcond s_max are dropped: columns shorter
             // than rcond / 16 times the longest one are not rotated any more
-            if (jacobi_lds_fits(rx[b], rx[b]))
+            if (use_big[b])
+                big_jobs.push_back(JacobiJob{rho[b], rx[b], rho[b], Ab[b], Wb[b], Sb[b], jt, 0.0,
+                                             (rcond / 16.0) * (rcond / 16.0)});
+            else if (jacobi_lds_fits(rx[b], rx[b]))
                 jobs.push_back(JacobiJob{rx[b], rx[b], rx[b], Rt[b], Wb[b], Sb[b], jt, 0.0,
                                          (rcond / 16.0) * (rcond / 16.0)});
             else
                 svd_jacobi(1, rx[b], rx[b], Rt[b], rx[b], 0, Wb[b], rx[b], 0, Sb[b], 0, st);
         }
         if (!jobs.empty()) svd_jacobi_batched(jobs, st);
+        if (!big_jobs.empty()) svd_jacobi_big(big_jobs, true, st);
     }
     for (int mu = 0; mu < d; ++mu) maxT = std::max<int64_t>(maxT, (int64_t)rx[mu] * n[mu] * rx[mu + 1]);
     for (int b = 1; b <= d - 1; ++b) maxT = std::max<int64_t>(maxT, (int64_t)rho[b] * rx[b]);
@@ -590,6 +646,12 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
         std::vector<GatherJob> gj;
         for (int b = 1; b <= d - 1; ++b) {
             const int k = r_out[b], c = rx[b];
+            if (use_big[b]) {
+                // V'_b = V[:, keep] / s and G_b = B[:, keep] / s (column-major rho x k)
+                gj.push_back(GatherJob{c, k, c, c, Wb[b], Vk[b], permb[b], facb[b], nullptr});
+                gj.push_back(GatherJob{rho[b], k, rho[b], rho[b], Ab[b], Gb[b], permb[b], facb[b], nullptr});
+                continue;
+            }
             gj.push_back(GatherJob{c, k, c, c, Rt[b], Vk[b], permb[b], facb[b], pivb[b]});
             gj.push_back(GatherJob{c, k, c, c, Wb[b], Wk[b], permb[b], facb[b], nullptr});
         }
@@ -608,7 +670,9 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
     for (int b = 1; b <= d - 1; ++b) {
         const int k = r_out[b];
         const int m = rho[b], c = rx[b];
-        if (use_small[b]) {
+        if (use_big[b]) {
+            // G_b was gathered directly
+        } else if (use_small[b]) {
             // G_b (column-major m x k) = Q (column-major m x c) * W[:, keep] / s
             ContractDesc dg = cdesc(m, k, c);
             dg.am = idx1(1);

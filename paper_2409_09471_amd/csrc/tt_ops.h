@@ -125,6 +125,11 @@ struct JacobiJob {
 bool jacobi_lds_fits(int m, int c);
 // One launch for up to 32 matrices (more are split into several launches).
 void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st);
+// One-sided Jacobi for 64 < c <= 128 (m <= 160): A (column-major, in place)
+// becomes B = A V with columns sorted by norm, sig the sorted singular values;
+// V (c x c, ld c, sorted like B) only when `accumulate` (else V is ignored).
+bool jacobi_big_fits(int m, int c);
+void svd_jacobi_big(const std::vector<JacobiJob>& jobs, bool accumulate, hipStream_t st);
 
 // Householder QR of several small column-major matrices in one launch (one
 // workgroup each, the matrix and Q in LDS): Q (m x c, column-major, ld m) and

@@ -1,0 +1,86 @@
+"""GPU parity of the factorizations at bond ranks 65..128 (the d = 20, n = 128
+workload's ranks): CholQR2 with the 128-column Cholesky, the 128-column
+one-sided Jacobi on R in the TT-SVD sweep (no rotation accumulator), and the
+accumulating 128-column Jacobi on Omega in the STTA recovery (Sec. 3.3).
+Compared as tensors and ranks with the FP64 oracle on the same inputs."""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import sketch as osk
+from oracle import tt as ott
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2409_09471_amd import ttsg  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def host(cores):
+    return [c.detach().cpu().numpy() for c in cores]
+
+
+def tt_rel(x, y):
+    return ott.norm(ott.add(x, y, 1.0, -1.0)) / ott.norm(y)
+
+
+def _decaying_tt(rng, ns, terms, rate, rank_each):
+    """Sum of `terms` Gaussian TTs of rank `rank_each`, the j-th scaled by rate^j:
+    singular values that decay geometrically across blocks of rank_each."""
+    acc = None
+    for j in range(terms):
+        t = ott.scale(syn.gaussian_tt(rng, ns, [1] + [rank_each] * (len(ns) - 1) + [1]), rate ** j)
+        acc = t if acc is None else ott.add(acc, t)
+    return acc
+
+
+@pytest.mark.parametrize("terms,rank_each,tol,maxrank", [
+    (20, 6, 1e-7, 0),     # middle bond 120 -> truncated by tolerance (rank > 64)
+    (20, 6, 0.0, 0),      # exact: every rank kept (middle bond 120)
+    (16, 8, 1e-9, 96),    # cap active at 96
+])
+def test_round_svd_rank_up_to_128(terms, rank_each, tol, maxrank):
+    n, d = 32, 4
+    rng = np.random.default_rng(81)
+    x = _decaying_tt(rng, [n] * d, terms, 0.7, rank_each)
+    print(f"round_svd ranks {ott.ranks(x)} tol {tol} maxrank {maxrank}", flush=True)
+    y = ttsg.round_svd(ttsg.to_device(x, DEV), tol, maxrank)
+    ref = ott.round_svd(x, tol, maxrank if maxrank else None)
+    assert ttsg.ranks_of(y) == ott.ranks(ref)
+    assert max(ott.ranks(ref)) > 64
+    assert tt_rel(host(y), ref) < 1e-9 + 1e-3 * tol
+    if maxrank == 0:
+        # above 64 columns U_R = B / s is orthonormal to the Jacobi tolerance
+        # (4 c eps at tol = 0), which bounds the reconstruction error
+        assert tt_rel(host(y), x) <= max(tol, 1e-12) * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("ranks,tol,maxrank", [
+    ([1, 32, 100, 32, 1], 1e-8, 0),      # rank 100 below rx = 128: Omega_2 (148 x 128) rank-deficient
+    ([1, 32, 128, 32, 1], 1e-6, 0),      # full target rank
+    ([1, 32, 120, 32, 1], 1e-9, 90),     # cap after recovery
+])
+def test_round_rand_rank_up_to_128(ranks, tol, maxrank):
+    n, d = 32, 4
+    rng = np.random.default_rng(82)
+    # geometric decay inside the tensor so tolerances have something to cut
+    x = syn.gaussian_tt(rng, [n] * d, ranks)
+    x[1] = x[1] * (0.93 ** np.arange(ranks[2]))[None, None, :]
+    rx, rho = syn.stta_ranks([n] * d, 128, 20)
+    assert rx[2] == 128 and rho[2] == 148
+    X = syn.tt_drm(rng, [n] * d, rx, 1, d)
+    Y = syn.tt_drm(rng, [n] * d, rho, 0, d - 1)
+    print(f"round_rand ranks {ranks} rx {rx} rho {rho} tol {tol} maxrank {maxrank}", flush=True)
+    y = ttsg.round_rand(ttsg.to_device(x, DEV), ttsg.to_device(X, DEV), ttsg.to_device(Y, DEV), rx, rho, tol,
+                        maxrank)
+    ref = osk.round_rand(x, X, Y, tol, maxrank if maxrank else None)
+    assert ttsg.ranks_of(y) == ott.ranks(ref)
+    assert tt_rel(host(y), ref) < 1e-8 + 1e-3 * tol
+    if maxrank == 0:
+        # target ranks at least the tensor's: STTA is exact, so the rounding error is the tolerance
+        assert tt_rel(host(y), x) <= tol * (1 + 1e-6) + 1e-10
