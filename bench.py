@@ -1,16 +1,27 @@
 """Benchmark: sketched TT-GMRES time to a 1e-6 true relative residual on one MI355X.
 
-Workload: convection-diffusion, d = 10, n = 64 per mode: Laplacian (h = 1/65)
-plus 0.1 x upwind convection in mode 1 as a rank-3 TT-matrix; right-hand side a
-seeded random rank-4 TT with Gaussian cores; basis ranks capped at 64; Khatri-Rao
-sketch with s = 1000 rows; STTA target ranks 64 and left ranks 84; q = 1;
-basis rounding tolerance 1e-7; stop on the FP64 true residual <= 1e-6.
+Default workload (d = 20, n = 128): the d-dimensional Laplacian (h = 1/129)
+plus the potential sum_k diag(sin(pi x_k)) as a rank-3 TT-matrix; right-hand
+side a seeded Gaussian rank-8 TT with ||b|| = 1; basis ranks capped at 128;
+Khatri-Rao sketch with s = 2000 rows; STTA target ranks 128 and left ranks 148
+(<= 160); q = 1; basis rounding 1e-7; restart cycles of 20; TT-sPGMRES (Alg. 5)
+with the exponential-sum right preconditioner of the operator's Kronecker sum
+(8 terms, relative accuracy 0.1 on its spectrum interval); stop on the FP64
+true residual <= 1e-6.  `--workload c2` selects the d = 10, n = 64
+convection-diffusion system (rank-3 operator, rank-4 rhs, ranks <= 64,
+s = 1000, no preconditioner).
 
 One step = one complete solve (every Krylov step of the hot path: Khatri-Rao
-sketch of A v_k, orthogonalization coefficients, STTA sketch and streaming
+sketch, orthogonalization coefficients and STTA sketch of A P^-1 v_k, streaming
 combination, STTA recovery + TT-SVD rounding, sketch of v_{k+1}, sketched least
-squares; then the final solution and its FP64 true residual).  Inputs are
-resident on the GPU before the timed region.
+squares; then the final solution, P^-1 applied to it, and its FP64 true
+residual).  Inputs are resident on the GPU before the timed region.
+
+Beside the timed leg the line carries: the kernel classes of one measured
+solve with the roofline of the dominant one, the mixed-precision (FP32
+contractions) and FP64 solve times of the d = 10 workload (the precision
+comparison), the randomized rounding's GFLOP/s at the workload's shapes in
+FP64 and FP32, and the FP64 CPU oracle timed on this host.
 
 Prints one JSON line.  Only N = 1 is supported (one GPU).
 """
@@ -34,16 +45,27 @@ PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15}
 PEAK_F64_VECTOR = 78.6e12
 HBM_PEAK = 8.0e12
 
+WORKLOAD_TEXT = {
+    "c5": "potential d=20 n=128: Laplacian + sum_k diag(sin(pi x_k)) as rank-3 TT operator, rank-8 Gaussian rhs, "
+          "ranks<=128, rho<=160 (148), s=2000, q=1, restart 20, exponential-sum right preconditioner (8 terms), "
+          "tol 1e-6 (true residual)",
+    "c2": "convection-diffusion d=10 n=64, rank-3 TT operator, rank-4 rhs, ranks<=64, s=1000, q=1, "
+          "tol 1e-6 (true residual)",
+}
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["mixed", "f64"], default="mixed")
+    ap.add_argument("--workload", choices=["c5", "c2"], default="c5")
+    ap.add_argument("--precision", choices=["auto", "mixed", "f64"], default="auto",
+                    help="arithmetic of the timed leg (auto: f64 for c5, mixed for c2)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="wall-clock budget of the oracle sample")
-    ap.add_argument("--no-fp64-leg", action="store_true", help="skip timing the FP64 path beside the mixed one")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="wall-clock budget of the oracle sample (c2)")
+    ap.add_argument("--no-precision-legs", action="store_true",
+                    help="skip the mixed / FP64 solves of the d = 10 workload")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default contraction tiles (no tuned table, no tuning)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -51,14 +73,20 @@ def parse():
     return ap.parse_args()
 
 
-def build_inputs(dev):
+def build_inputs(name, dev):
+    import numpy as np
     import synthetic as syn
     from paper_2409_09471_amd import ttsg
-    w = syn.config_c2()
+    w = syn.config_c5() if name == "c5" else syn.config_c2()
     t = dict(
         A=ttsg.kron_sum_operator(w.terms, dev), b=ttsg.to_device(w.b, dev), S=ttsg.to_device(w.S, dev),
-        X=ttsg.to_device(w.X, dev), Y=ttsg.to_device(w.Y, dev),
+        X=ttsg.to_device(w.X, dev), Y=ttsg.to_device(w.Y, dev), pre=None,
     )
+    if "mode_matrices" in w.extra:
+        mats = w.extra["mode_matrices"]
+        ev = [np.linalg.eigvalsh(M) for M in mats]           # spectrum interval of the Kronecker sum
+        alpha, beta = ttsg.expsum(sum(e.min() for e in ev), sum(e.max() for e in ev), w.extra["precond_tol"])
+        t["pre"] = ttsg.Preconditioner(list(alpha), list(beta), ttsg.to_device(mats, dev))
     return w, t
 
 
@@ -66,10 +94,10 @@ def solve(w, t, precision, phase_timing=False):
     from paper_2409_09471_amd import ttsg
     return ttsg.sgmres_solve(t["A"], t["b"], t["S"], t["X"], t["Y"], w.rx, w.rho, maxit=w.maxit, tol=w.tol,
                              q=w.q, round_tol=w.round_tol, maxrank=w.cap, stop_safety=w.stop_safety,
-                             precision=precision, phase_timing=phase_timing)
+                             restart=w.restart, precision=precision, precond=t["pre"], phase_timing=phase_timing)
 
 
-def timed_solves(w, t, precision, steps, warmup, measure=True, tune=False):
+def timed_solves(w, t, precision, steps, warmup, measure=True, tune=False, tag=""):
     """Wall-clock time of `steps` solves (measurement off), then (measure=True)
     one more solve with the per-launch device timers on for the kernel figures.
     With tune=True the first warmup solve runs with the tile autotuner on."""
@@ -79,13 +107,13 @@ def timed_solves(w, t, precision, steps, warmup, measure=True, tune=False):
         ttsg.autotune(tune and i == 0)
         r = solve(w, t, precision)
         ttsg.autotune(False)
-        print(f"# warmup {i}: its={r.iterations} true_res={r.true_residual:.3e}", file=sys.stderr, flush=True)
+        print(f"# {tag}warmup {i}: its={r.iterations} true_res={r.true_residual:.3e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
     for i in range(steps):
         results.append(solve(w, t, precision))
-        print(f"# step {i}: its={results[-1].iterations} true_res={results[-1].true_residual:.3e}",
+        print(f"# {tag}step {i}: its={results[-1].iterations} true_res={results[-1].true_residual:.3e}",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -98,8 +126,10 @@ def timed_solves(w, t, precision, steps, warmup, measure=True, tune=False):
     return elapsed, results, stats
 
 
-def rounding_gflops(w, t):
-    """ttsg_round_rand on a materialized A v (rank 3 x 64 -> 64) at the workload's shapes."""
+def rounding_gflops(w, t, precision):
+    """ttsg_round_rand on a materialized A v (ranks op_rank x cap -> cap) at the
+    workload's shapes: algorithmic flops of its contractions and factorizations
+    over the wall-clock time of the call."""
     import numpy as np
     import torch
     import synthetic as syn
@@ -107,36 +137,40 @@ def rounding_gflops(w, t):
     rng = np.random.default_rng(7)
     v = ttsg.to_device(syn.gaussian_tt(rng, w.ns, [1] + [w.cap] * (w.d - 1) + [1]), "cuda:0")
     av = ttsg.matvec(t["A"], v)
-    ttsg.round_rand(av, t["X"], t["Y"], w.rx, w.rho, w.round_tol, w.cap)
+    del v
+    ttsg.round_rand(av, t["X"], t["Y"], w.rx, w.rho, w.round_tol, w.cap, precision=precision)
     torch.cuda.synchronize()
     ttsg.stats_enable(True)
     t0 = time.perf_counter()
     reps = 3
     for _ in range(reps):
-        ttsg.round_rand(av, t["X"], t["Y"], w.rx, w.rho, w.round_tol, w.cap)
+        ttsg.round_rand(av, t["X"], t["Y"], w.rx, w.rho, w.round_tol, w.cap, precision=precision)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / reps
     st = ttsg.stats_read()
     ttsg.stats_enable(False)
+    del av
     fl = sum(v["flops"] for v in st.values()) / reps
     return dict(seconds=el, gflop=fl / 1e9, gflops_per_s=fl / el / 1e9)
 
 
-# HBM counter summaries per kernel class: (file under profiles/, kernel source
-# whose SHA-256 the summary records)
+# Counter summaries per (workload, kernel class): (file under profiles/, kernel
+# source whose SHA-256 the summary records)
 COUNTER_SUMMARIES = {
-    "contract_f64": ("contract_kernel_f64_hbm_counters_convdiff_d10_n64.md", "contract.hip"),
-    "contract_f32": ("contract_kernel_f32_hbm_counters_convdiff_d10_n64.md", "contract.hip"),
-    "svd_jacobi": ("k_jacobi_lds_hbm_counters_convdiff_d10_n64.md", "la_lds.hip"),
+    "c2": {
+        "contract_f64": ("contract_kernel_f64_hbm_counters_convdiff_d10_n64.md", "contract.hip"),
+        "contract_f32": ("contract_kernel_f32_hbm_counters_convdiff_d10_n64.md", "contract.hip"),
+        "svd_jacobi": ("k_jacobi_lds_hbm_counters_convdiff_d10_n64.md", "la_lds.hip"),
+    },
+    "c5": {
+        "contract_f64": ("contract_kernel_f64_counters_potential_d20_n128.md", "contract.hip"),
+    },
 }
 TILE_TABLE = os.path.join(ROOT, "paper_2409_09471_amd", "tiles_gfx950.txt")
 
 
-def counter_traffic(cls):
-    """HBM bytes per launch of the kernel class `cls` from its committed
-    FETCH_SIZE / WRITE_SIZE summary, or None when there is none for the class or
-    it was taken on a different version of the kernel's source."""
-    ent = COUNTER_SUMMARIES.get(cls)
+def _summary_fields(cls, workload):
+    ent = COUNTER_SUMMARIES.get(workload, {}).get(cls)
     if ent is None:
         return None
     path = os.path.join(ROOT, "profiles", ent[0])
@@ -151,13 +185,28 @@ def counter_traffic(cls):
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if fields.get("kernel_source_sha256") != sha or fields.get("class") != cls:
         return None
+    return fields
+
+
+def counter_value(cls, key, workload="c2"):
+    """A figure (`key`) of the kernel class `cls` from its committed rocprofv3
+    counter summary, or None when there is none for the class and workload or
+    it was taken on a different version of the kernel's source."""
+    fields = _summary_fields(cls, workload)
+    if fields is None:
+        return None
     try:
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[key])
     except (KeyError, ValueError):
         return None
 
 
-def cpu_baseline(w, gpu_iterations, budget_s):
+def counter_traffic(cls, workload="c2"):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading)."""
+    return counter_value(cls, "traffic_bytes_per_launch", workload)
+
+
+def cpu_baseline_iterations(w, gpu_iterations, budget_s):
     """The oracle's TT-sGMRES on the same inputs, timed for a bounded number of
     iterations (k = 1, 2, 4, ... while the next run fits in the budget); the
     rest of the GPU's iteration count is extrapolated at the incremental rate of
@@ -193,6 +242,37 @@ def cpu_baseline(w, gpu_iterations, budget_s):
                 extrapolated=gpu_iterations > kmax)
 
 
+def cpu_baseline_first_iteration(w, gpu_iterations):
+    """The oracle's TT-sPGMRES (same inputs, same preconditioner terms) timed for
+    its first iteration (the solution is not formed); the solve is extrapolated
+    as that time x the GPU's iteration count.  The first iteration works on the
+    rank-8 right-hand side while later ones reach rank 128, so this is a lower
+    bound on the oracle's full solve."""
+    import numpy as np
+    from oracle import operators as oops
+    from oracle import precond as opc
+    from oracle import solvers as osol
+    A = oops.tt_kron_sum(w.terms)
+    mats = w.extra["mode_matrices"]
+    ev = [np.linalg.eigvalsh(M) for M in mats]
+    s0 = time.perf_counter()
+    alpha, beta = opc.expsum_coefficients(sum(e.min() for e in ev), sum(e.max() for e in ev),
+                                          w.extra["precond_tol"])
+    E = opc.mode_exponentials(beta, mats)
+    setup = time.perf_counter() - s0
+    s = time.perf_counter()
+    osol.tt_sgmres(A, w.b, w.S, w.X, w.Y, maxit=1, tol=w.tol, q=w.q, round_tol=w.round_tol, maxrank=w.cap,
+                   stop_safety=w.stop_safety, fixed_iterations=1, precond=(alpha, E), solution=False)
+    el = time.perf_counter() - s
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return dict(value=setup + el * gpu_iterations, unit="s", cores=cores, kind="oracle",
+                sample=f"oracle TT-sPGMRES (numpy float64, {cores} threads) on the same inputs: the mode "
+                       f"exponentials ({setup:.1f} s) and the first Krylov iteration ({el:.1f} s, rank-8 basis "
+                       f"vector, {len(alpha)} preconditioner terms); the GPU's {gpu_iterations} iterations are "
+                       f"extrapolated at that rate (a lower bound: later iterations reach rank 128)",
+                extrapolated=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -210,8 +290,10 @@ def main():
         torch.cuda.synchronize()
         print("# calibration copy: 268435456 bytes read, 268435456 bytes written", file=sys.stderr, flush=True)
         del src, dst
-    w, t = build_inputs("cuda:0")
-    prec = ttsg.PREC_MIXED if args.precision == "mixed" else ttsg.PREC_F64
+    wl = args.workload
+    w, t = build_inputs(wl, "cuda:0")
+    prec_name = args.precision if args.precision != "auto" else ("f64" if wl == "c5" else "mixed")
+    prec = ttsg.PREC_MIXED if prec_name == "mixed" else ttsg.PREC_F64
     # contraction tiles: the committed table from the tile tuner, else tune
     # during the first warmup solve
     tune = False
@@ -224,15 +306,18 @@ def main():
     per = el / args.steps
     last = results[-1]
     converged = all(r.status == ttsg.OK for r in results)
+    cfg = {"workload": WORKLOAD_TEXT[wl], "d": w.d, "n": w.ns[0], "op_rank": w.op_rank,
+           "rhs_rank": max(int(c.shape[2]) for c in w.b[:-1]), "maxrank": w.cap, "s": w.s, "rho": max(w.rho),
+           "rx": max(w.rx), "q": w.q, "round_tol": w.round_tol, "tol": w.tol, "restart": w.restart}
+    if t["pre"] is not None:
+        cfg["precond_terms"] = len(t["pre"].alpha)
+        cfg["precond_tol"] = w.extra["precond_tol"]
     out = {
         "metric": METRIC, "value": per, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": per * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if prec == ttsg.PREC_MIXED else "f64", "data": "synthetic",
-        "config": {"workload": "convection-diffusion d=10 n=64, rank-3 TT operator, rank-4 rhs, ranks<=64, "
-                               "s=1000, q=1, tol 1e-6 (true residual)",
-                   "d": w.d, "n": w.ns[0], "op_rank": w.op_rank, "rhs_rank": 4, "maxrank": w.cap, "s": w.s,
-                   "rho": max(w.rho), "rx": max(w.rx), "q": w.q, "round_tol": w.round_tol, "tol": w.tol},
+        "dtype": "f32+f64" if prec == ttsg.PREC_MIXED else "f64", "data": "synthetic", "config": cfg,
         "converged": converged, "iterations": last.iterations, "true_residual": last.true_residual,
+        "true_residual_is_bound": last.true_residual_is_bound,
         "sketched_residual": last.sketched_residual, "max_rank": last.max_rank,
     }
     # per-class kernel figures of one measured solve (device wall-clock per launch)
@@ -242,23 +327,42 @@ def main():
                        tflops=round(v["flops"] / max(v["seconds"], 1e-12) / 1e12, 4),
                        gbs=round(v["bytes"] / max(v["seconds"], 1e-12) / 1e9, 2))
     out["kernels"] = kern
-    # roofline of the dominant kernel class (summed device time of the measured
-    # solve); when that is not a contraction, the leading contraction class is
-    # reported beside it
+
+    # Roofline of the dominant kernel class (summed device time of the measured
+    # solve).  A contraction class is placed by its algorithmic intensity
+    # (flops / operand bytes): below the dtype's ridge (peak flops / 8 TB/s) the
+    # bound is HBM and `achieved` is GB/s, above it the matrix cores and
+    # TFLOP/s.  The single-workgroup factorizations are priced against the FP64
+    # vector ALU peak.
     def roofline(cls):
         v = stats[cls]
-        ach = v["flops"] / v["launches"] / (v["seconds"] / v["launches"])
+        per_launch_s = v["seconds"] / v["launches"]
+        fl, by = v["flops"] / v["launches"], v["bytes"] / v["launches"]
         if cls.startswith("contract"):
             dt = cls.split("_")[1]
             name = f"contract_kernel<{ {'f64': 'double', 'f32': 'float', 'bf16': 'bf16'}[dt]}>"
-            bound, peak, traffic = "mfma", PEAK[dt], counter_traffic(cls)
-        else:
-            # single-workgroup FP64 factorizations: vector ALU work
-            name = {"svd_jacobi": "k_jacobi_lds", "qr": "k_chol_inv + k_qr_small"}.get(cls, cls)
-            bound, peak, traffic = "alu", PEAK_F64_VECTOR, counter_traffic(cls)
-        return {"kernel": name, "bound": bound, "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": traffic, "flop_per_launch": v["flops"] / v["launches"],
-                "avg_launch_us": v["seconds"] / v["launches"] * 1e6}
+            intensity = fl / max(by, 1.0)
+            ridge = PEAK[dt] / HBM_PEAK
+            if intensity < ridge:
+                bound, ach, peak, unit = "hbm", by / per_launch_s, HBM_PEAK, "GB/s"
+                ach_u, peak_u = ach / 1e9, peak / 1e9
+            else:
+                bound, ach, peak, unit = "mfma", fl / per_launch_s, PEAK[dt], "TFLOP/s"
+                ach_u, peak_u = ach / 1e12, peak / 1e12
+            r = {"kernel": name, "bound": bound, "achieved": ach_u, "peak": peak_u, "unit": unit,
+                 "frac": ach / peak, "traffic": counter_traffic(cls, wl), "flop_per_launch": fl,
+                 "bytes_per_launch": by, "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
+                 "avg_launch_us": per_launch_s * 1e6, "tflops": fl / per_launch_s / 1e12,
+                 "gbs": by / per_launch_s / 1e9}
+            mu = counter_value(cls, "mfma_util", wl)
+            if mu is not None:
+                r["mfma_util"] = mu
+            return r
+        name = {"svd_jacobi": "k_jacobi_lds / k_jacobi_big", "qr": "k_chol_inv + k_qr_small"}.get(cls, cls)
+        return {"kernel": name, "bound": "alu", "achieved": fl / per_launch_s / 1e12, "peak": PEAK_F64_VECTOR / 1e12,
+                "unit": "TFLOP/s", "frac": fl / per_launch_s / PEAK_F64_VECTOR, "traffic": counter_traffic(cls, wl),
+                "flop_per_launch": fl, "avg_launch_us": per_launch_s * 1e6}
+
     timed = [k for k in stats if stats[k]["launches"] > 0 and stats[k]["seconds"] > 0 and k != "qr_redo"]
     dom = max(timed, key=lambda k: stats[k]["seconds"], default=None)
     if dom is not None:
@@ -266,15 +370,33 @@ def main():
         top_c = max((k for k in timed if k.startswith("contract")), key=lambda k: stats[k]["seconds"], default=None)
         if top_c is not None and top_c != dom:
             out["roofline_contraction"] = roofline(top_c)
-    if prec == ttsg.PREC_MIXED and not args.no_fp64_leg:
-        el64, res64, _ = timed_solves(w, t, ttsg.PREC_F64, 1, 1 if tune else 0, measure=False, tune=tune)
-        out["fp64_seconds"] = el64
-        out["fp64_iterations"] = res64[-1].iterations
-        out["fp64_true_residual"] = res64[-1].true_residual
-        out["speedup_vs_fp64"] = el64 / per
-    out["rounding"] = rounding_gflops(w, t)
+    # the precision comparison: mixed (FP32 contractions) against FP64 on the
+    # d = 10 workload, the same number of timed solves each
+    if not args.no_precision_legs:
+        if wl == "c2":
+            w2, t2 = w, t
+        else:
+            w2, t2 = build_inputs("c2", "cuda:0")
+        n2 = max(1, min(args.steps, 10))
+        legs = {}
+        for name, p in (("mixed", ttsg.PREC_MIXED), ("f64", ttsg.PREC_F64)):
+            e2, r2, _ = timed_solves(w2, t2, p, n2, 1, measure=False, tag=f"c2 {name} ")
+            legs[name] = dict(seconds=e2 / n2, iterations=r2[-1].iterations, true_residual=r2[-1].true_residual,
+                              converged=all(r.status == ttsg.OK for r in r2))
+        out["precision_legs"] = {"workload": WORKLOAD_TEXT["c2"], "solves_each": n2, **legs,
+                                 "speedup_mixed_vs_fp64": legs["f64"]["seconds"] / legs["mixed"]["seconds"]}
+        if wl != "c2":
+            del t2
+    if wl == "c5":
+        out["precision_note"] = ("d=20 runs FP64: float32 sketches of A P^-1 v_k (a small difference after "
+                                 "preconditioning) lose the new direction in the recovery; see precision_legs")
+    out["rounding"] = {"f64": rounding_gflops(w, t, ttsg.PREC_F64),
+                       "f32": rounding_gflops(w, t, ttsg.PREC_MIXED)}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, last.iterations, args.cpu_seconds)
+        if wl == "c5":
+            out["cpu_baseline"] = cpu_baseline_first_iteration(w, last.iterations)
+        else:
+            out["cpu_baseline"] = cpu_baseline_iterations(w, last.iterations, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -218,6 +218,15 @@ typedef struct {
     int32_t* rank_history;
     double* true_history;
     double* phase_seconds;
+    /* out: 1 when true_residual is the rounding floor of the FP64 identity
+       ||b - A x||^2 = ||b||^2 - 2 <A x, b> + ||A x||^2 rather than a measured
+       value.  The identity is evaluated first; below its floor
+       sqrt(64 eps (||b||^2 + ||A x||^2)) / ||b|| the difference is rounding.  When
+       that floor is already <= tol it is reported (an upper bound of the true
+       residual at the identity's rounding level) and the solve ends; otherwise
+       b - A x is formed as a block TT and its norm measured by
+       orthogonalization (flag 0). */
+    int32_t true_residual_is_bound;
 } ttsg_sgmres_info;
 
 /* Phases reported in info->phase_seconds (host wall clock with stream syncs

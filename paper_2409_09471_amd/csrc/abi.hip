@@ -310,22 +310,6 @@ int ttsg_stta_sketch_noalloc(int32_t d, const int32_t* n, const int32_t* rho, co
     });
 }
 
-// A generous bound on the sketch's scratch (every intermediate at the largest
-// rank product), kept for the rounding entry points, whose recovery and TT-SVD
-// scratch terms are estimated beside it.
-static size_t stta_ws_loose(int32_t d, const int32_t* n, const int32_t* rho, const int32_t* rx, const int32_t* r) {
-    size_t big = 0, tot = 0;
-    for (int mu = 0; mu < d; ++mu) {
-        size_t m = (size_t)std::max(rho[mu], rx[mu]) * std::max<size_t>(r[mu], 1) * n[mu] *
-                   std::max(r[mu + 1], std::max(rx[mu + 1], rho[mu + 1]));
-        big = std::max(big, m);
-        tot += (size_t)r[mu + 1] * rx[mu + 1] + (size_t)r[mu] * n[mu] * r[mu + 1] + (size_t)n[mu] * n[mu] +
-               (size_t)rho[mu] * n[mu] * rho[mu + 1] + (size_t)rx[mu] * n[mu] * rx[mu + 1] +
-               (size_t)rho[mu] * n[mu] * rx[mu + 1];
-    }
-    return (8 * big + 2 * tot) * 8 + (1 << 20);
-}
-
 static size_t round_rand_ws(int32_t d, const int32_t* n, const int32_t* r, const int32_t* rho, const int32_t* rx,
                             ttsg::Prec p) {
     size_t sk = 0;
@@ -335,7 +319,7 @@ static size_t round_rand_ws(int32_t d, const int32_t* n, const int32_t* r, const
         core = std::max(core, (size_t)rx[mu] * n[mu] * rx[mu + 1]);
         rmax = std::max(rmax, (size_t)std::max(rho[mu], rx[mu]));
     }
-    const size_t need = stta_ws_loose(d, n, rho, rx, r) + stta_ws(d, n, rho, rx, nullptr, r, p) + sk * 8 + (8 * core + 12 * rmax * rmax) * 8 +
+    const size_t need = stta_ws(d, n, rho, rx, nullptr, r, p) + sk * 8 + (8 * core + 12 * rmax * rmax) * 8 +
                         (size_t)d * 16 * rmax * rmax * 8 + (4 << 20) + ttsg::tt_svd_extra_bytes(d, n, rx);
     return need + kSplitSlack;
 }
@@ -725,7 +709,7 @@ int ttsg_precond_round(int32_t d, const int32_t* n, int32_t zeta, const double* 
         }
         size_t zc = 0;
         for (int mu = 0; mu < d; ++mu) zc += (size_t)r[mu] * n[mu] * r[mu + 1] + 64;
-        const size_t need = stta_ws_loose(d, n, rho, rx, r) + 2 * sk * 8 + ee * 8 + zc * 8 +
+        const size_t need = stta_ws(d, n, rho, rx, nullptr, r, ttsg::Prec::F64) + 2 * sk * 8 + ee * 8 + zc * 8 +
                             (8 * core + 12 * rmax * rmax) * 8 + (size_t)d * 16 * rmax * rmax * 8 + (4 << 20) +
                             ttsg::tt_svd_extra_bytes(d, n, rx);
         ttsg::Workspace W(ws, ws_bytes, need + kSplitSlack, S(stream));

@@ -645,6 +645,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             info->iterations = 0;
             info->cycles = 0;
             info->true_residual = 0.0;
+            info->true_residual_is_bound = 0;
             info->status = TTSG_OK;
         }
         return TTSG_OK;
@@ -676,6 +677,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         const int64_t gl = (int64_t)in_.R[mu] * in_.rx[mu], gr = (int64_t)in_.R[mu + 1] * in_.rx[mu + 1];
         G[mu] = scratch_.get<double>(gl * n[mu] * gr);
     }
+    bool true_is_bound = false;
     auto true_res = [&](const std::vector<int>& xr, const std::vector<double*>& xc) -> double {
         // ||b - A x||^2 = ||b||^2 - 2 <A x, b> + ||A x||^2  (FP64 throughout)
         std::vector<int> gr(d + 1);
@@ -692,7 +694,16 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         // difference is rounding, not residual.  Then r = b - A x is formed as
         // a block TT and measured by orthogonalization, which does not cancel.
         const double noise2 = 64.0 * 2.220446049250313e-16 * (nb * nb + hb[1]);
+        true_is_bound = false;
         if (r2 > noise2) return std::sqrt(r2) / nb;
+        // Below the floor: when the floor itself is within tol the residual is
+        // known to meet it; the floor is reported as an upper bound (forming
+        // b - A x explicitly costs a QR sweep at ranks R r_x + r_b)
+        const double floor_rel = std::sqrt(std::max(r2, 0.0) + noise2) / nb;
+        if (floor_rel <= o.tol) {
+            true_is_bound = true;
+            return floor_rel;
+        }
         const size_t mk = scratch_.mark();
         std::vector<double*> rc(d);
         for (int mu = 0; mu < d; ++mu)
@@ -1077,6 +1088,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         info->max_rank = max_rank;
         info->status = status;
         info->true_residual = last_true;
+        info->true_residual_is_bound = true_is_bound ? 1 : 0;
         info->sketched_residual = last_sres;
     }
     return status;

@@ -127,6 +127,7 @@ class SgmresInfo(ctypes.Structure):
         ("rank_history", ctypes.POINTER(ctypes.c_int32)),
         ("true_history", ctypes.POINTER(ctypes.c_double)),
         ("phase_seconds", ctypes.POINTER(ctypes.c_double)),
+        ("true_residual_is_bound", ctypes.c_int32),
     ]
 
 
@@ -401,6 +402,9 @@ class SolveResult:
     rank_history: List[int] = field(default_factory=list)
     true_history: List[float] = field(default_factory=list)
     phase_seconds: dict = field(default_factory=dict)
+    # the reported true residual is the rounding floor of the FP64 identity
+    # (an upper bound), not a measured norm
+    true_residual_is_bound: bool = False
 
 
 @dataclass
@@ -502,6 +506,7 @@ def sgmres_solve(A, b, S, X, Y, rx, rho, *, maxit: int, tol: float, q: int = 1, 
     return SolveResult(
         x=_trim(x, list(xr)), status=rc, iterations=it, cycles=info.cycles,
         true_residual=info.true_residual, sketched_residual=info.sketched_residual, max_rank=info.max_rank,
+        true_residual_is_bound=bool(info.true_residual_is_bound),
         sketched_history=[sh[i] for i in range(min(it, maxit))],
         rank_history=[rh[i] for i in range(min(it, maxit))],
         true_history=[th[i] for i in range(min(info.cycles, max_cycles))],
@@ -590,6 +595,7 @@ def sgmres_solve_batched(systems: Sequence[BatchSystem], concurrency: int = 8) -
         res.append(SolveResult(
             x=_trim(x, list(xr)), status=arr[i].status, iterations=it, cycles=info.cycles,
             true_residual=info.true_residual, sketched_residual=info.sketched_residual, max_rank=info.max_rank,
+            true_residual_is_bound=bool(info.true_residual_is_bound),
             sketched_history=[sh[j] for j in range(min(it, q.maxit))],
             rank_history=[rh[j] for j in range(min(it, q.maxit))],
             true_history=[th[j] for j in range(min(info.cycles, q.max_cycles))]))

@@ -38,27 +38,29 @@ def _tree(tmp_path, cls, fname, src, src_text, recorded_sha, traffic="1.5e+06"):
         f"- class: {cls}\n- kernel_source_sha256: {recorded_sha}\n- traffic_bytes_per_launch: {traffic}\n")
 
 
-@pytest.mark.parametrize("cls", ["contract_f64", "contract_f32", "svd_jacobi"])
-def test_counter_traffic_follows_class_and_source(bench, tmp_path, monkeypatch, cls):
-    fname, src = bench.COUNTER_SUMMARIES[cls]
+@pytest.mark.parametrize("wl,cls", [("c2", "contract_f64"), ("c2", "contract_f32"), ("c2", "svd_jacobi"),
+                                    ("c5", "contract_f64")])
+def test_counter_traffic_follows_class_and_source(bench, tmp_path, monkeypatch, wl, cls):
+    fname, src = bench.COUNTER_SUMMARIES[wl][cls]
     text = "__global__ void k() {}\n"
     sha = hashlib.sha256(text.encode()).hexdigest()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     # no summary yet
-    assert bench.counter_traffic(cls) is None
+    assert bench.counter_traffic(cls, wl) is None
     # matching class and source
     _tree(tmp_path, cls, fname, src, text, sha)
-    assert bench.counter_traffic(cls) == 1.5e6
+    assert bench.counter_traffic(cls, wl) == 1.5e6
     # the kernel source changed since the counters were taken
     (tmp_path / "paper_2409_09471_amd" / "csrc" / src).write_text(text + "// edited\n")
-    assert bench.counter_traffic(cls) is None
+    assert bench.counter_traffic(cls, wl) is None
     # a summary recorded for another class is not used
     _tree(tmp_path, "qr", fname, src, text, sha)
-    assert bench.counter_traffic(cls) is None
+    assert bench.counter_traffic(cls, wl) is None
     # a malformed figure is not used
     _tree(tmp_path, cls, fname, src, text, sha, traffic="n/a")
-    assert bench.counter_traffic(cls) is None
+    assert bench.counter_traffic(cls, wl) is None
 
 
 def test_counter_traffic_unknown_class(bench):
     assert bench.counter_traffic("qr") is None
+    assert bench.counter_traffic("contract_f64", "c9") is None
