@@ -6,7 +6,7 @@ side a seeded Gaussian rank-8 TT with ||b|| = 1; basis ranks capped at 128;
 Khatri-Rao sketch with s = 2000 rows; STTA target ranks 128 and left ranks 148
 (<= 160); q = 1; basis rounding 1e-7; restart cycles of 20; TT-sPGMRES (Alg. 5)
 with the exponential-sum right preconditioner of the operator's Kronecker sum
-(8 terms, relative accuracy 0.1 on its spectrum interval); stop on the FP64
+(13 terms, relative accuracy 0.02 on its spectrum interval); stop on the FP64
 true residual <= 1e-6.  `--workload c2` selects the d = 10, n = 64
 convection-diffusion system (rank-3 operator, rank-4 rhs, ranks <= 64,
 s = 1000, no preconditioner).
@@ -47,7 +47,7 @@ HBM_PEAK = 8.0e12
 
 WORKLOAD_TEXT = {
     "c5": "potential d=20 n=128: Laplacian + sum_k diag(sin(pi x_k)) as rank-3 TT operator, rank-8 Gaussian rhs, "
-          "ranks<=128, rho<=160 (148), s=2000, q=1, restart 20, exponential-sum right preconditioner (8 terms), "
+          "ranks<=128, rho<=160 (148), s=2000, q=1, restart 20, exponential-sum right preconditioner (13 terms), "
           "tol 1e-6 (true residual)",
     "c2": "convection-diffusion d=10 n=64, rank-3 TT operator, rank-4 rhs, ranks<=64, s=1000, q=1, "
           "tol 1e-6 (true residual)",

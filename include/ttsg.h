@@ -68,6 +68,9 @@ enum {
                            the residual from eq. sketched_residualnorm.  W_k is not formed */
 };
 
+/* How a cycle's solution is formed from the basis (Alg. 3 vs Alg. 4). */
+enum { TTSG_VARIANT_ENHANCED = 0, TTSG_VARIANT_VANILLA = 1 };
+
 /* Arithmetic of the contraction kernels. */
 typedef enum {
     TTSG_PREC_F64 = 0,   /* everything in float64 (FP64 MFMA) */
@@ -137,7 +140,7 @@ int ttsg_stta_sketch(int32_t d, const int32_t* n,
  * the process ends); the call makes no hipMalloc/hipFree and no allocating
  * library call.  Shapes whose scratch exceeds the buffer return -TTSG_ERR_WS
  * before any work is queued (ttsg_stta_sketch_workspace_size gives the need;
- * e.g. d = 10, n = 64, ranks 64, rho 84, operator rank 3 needs about 70 MiB
+ * e.g. d = 10, n = 64, ranks 64, rho 84, operator rank 3 needs about 101 MiB
  * in float64).  With the tile autotuner on it returns -TTSG_ERR_ARG (tuning
  * allocates).  Every call on one GPU shares that GPU's buffer: calls that
  * overlap on one GPU (different streams or host threads) race and must be
@@ -312,6 +315,11 @@ typedef struct {
     const double* const* M;
     /* least-squares form: TTSG_LS_PINV (default) or TTSG_LS_WHITEN */
     int32_t ls_mode;
+    /* final solution of a cycle: TTSG_VARIANT_ENHANCED (default; the STTA
+       sketches of the basis combined once and recovered, Sec. 3.5) or
+       TTSG_VARIANT_VANILLA (Alg. 3: every basis vector of the cycle is kept and
+       x = Round(x + y_i v_i, final_tol) term by term) */
+    int32_t variant;
 } ttsg_sgmres_ext;
 
 /* ttsg_sgmres_solve with the options above (ext == NULL: plain Alg. 4).
@@ -334,6 +342,41 @@ int ttsg_sgmres_solve_ex(int32_t d, const int32_t* n,
 int ttsg_sgmres_workspace_size(int32_t d, const int32_t* n, const int32_t* R, const int32_t* rb, int32_t s,
                                const int32_t* rho, const int32_t* rx, const ttsg_sgmres_opts* opts,
                                const ttsg_sgmres_ext* ext, size_t* bytes);
+
+/* ------------------------------------------------------------------------- */
+/* TT-GMRES (Alg. 2): the deterministic method the sketched one is compared   */
+/* with (Sec. 5.2).                                                          */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t maxit;       /* Arnoldi steps (no restart) */
+    int32_t maxrank;     /* cap of every basis and solution rank (0 = the full
+                            bond ranks min(prod n_<b, prod n_>=b)); it also sizes
+                            the workspace, which grows as (maxit+1) basis vectors */
+    double tol;          /* stop when the Arnoldi residual <= tol ||b|| */
+    double final_tol;    /* rounding tolerance of the sequential solution sums
+                            (0 = tol) */
+    double max_round;    /* cap of the relaxed rounding tolerance eta_k tol
+                            (eta_k = tol / relative residual of step k-1); the
+                            usual value is 0.1 */
+} ttsg_gmres_opts;
+
+/* Solve A x = b (x_0 = 0) by TT-GMRES: full modified Gram-Schmidt, TT-SVD
+ * rounding of A v_k and after every Gram-Schmidt step at the relaxed
+ * tolerance (Sec. 2.3), Givens reduction of the Hessenberg least-squares
+ * problem (eq. argmin2), x = Round(x + y_i v_i, final_tol) term by term.
+ * x: d DEVICE pointers with capacity c_k x n_k x c_{k+1}, c_b = the rank cap of
+ * bond b; x_r: HOST int32[d+1].  info (may be NULL): iterations, status,
+ * sketched_residual = the final Arnoldi residual / ||b||, true_residual = the
+ * FP64 ||b - A x|| / ||b|| (block TT, orthogonalization norm),
+ * sketched_history / rank_history per step when given (length >= maxit).
+ * Returns TTSG_OK, TTSG_BREAKDOWN, TTSG_NOT_CONVERGED or a negative error.
+ * Synchronizes `stream`. */
+int ttsg_tt_gmres(int32_t d, const int32_t* n, const int32_t* R, const double* const* A,
+                  const int32_t* rb, const double* const* b, const ttsg_gmres_opts* opts,
+                  double* const* x, int32_t* x_r, ttsg_sgmres_info* info,
+                  void* ws, size_t ws_bytes, ttsg_stream_t stream);
+int ttsg_tt_gmres_workspace_size(int32_t d, const int32_t* n, const int32_t* R, const int32_t* rb,
+                                 const ttsg_gmres_opts* opts, size_t* bytes);
 
 /* Exponential-sum coefficients (Sec. 4.1) with |z E(z) - 1| <= tol for every
  * z in [zmin, zmax] (0 < zmin <= zmax, 0 < tol < 1), from the trapezoid rule

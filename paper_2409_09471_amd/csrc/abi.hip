@@ -68,8 +68,9 @@ ttsg::Prec prec_of(int32_t precision) {
                                       : (precision == TTSG_PREC_MIXED ? ttsg::Prec::F32 : ttsg::Prec::BF16);
 }
 
-// Split-K partial sums of one contraction take at most 4M output elements.
-constexpr size_t kSplitSlack = (size_t)40 << 20;
+// Split-K partial sums of one contraction: splits x workgroups < 2048 tiles of
+// 64 x 64, so fewer than 8M partial values (64 MiB in float64).
+constexpr size_t kSplitSlack = (size_t)72 << 20;
 
 }  // namespace
 
@@ -192,8 +193,7 @@ static size_t gran(size_t bytes) { return (bytes + 255) & ~size_t(255); }
 // (R == NULL: no operator): the float32 copies of the operands in the
 // reduced precisions, the sweep intermediates T1/T2/U1/U2, two left
 // environments, the right environments F_1..F_d, and the split-K partials of
-// one contraction (released after it; splits x workgroups < 1024 tiles of
-// 64 x 64, so fewer than 4M partial values).
+// one contraction (released after it).
 static size_t stta_ws(int32_t d, const int32_t* n, const int32_t* rho, const int32_t* rx, const int32_t* R,
                       const int32_t* r, ttsg::Prec p) {
     const size_t es = ttsg::elem_size(p);
@@ -596,6 +596,9 @@ ttsg::SolverInputs solver_inputs(int32_t d, const int32_t* n, const int32_t* R, 
         TTSG_CHECK(ext->ls_mode == TTSG_LS_PINV || ext->ls_mode == TTSG_LS_WHITEN, TTSG_ERR_ARG,
                    "sgmres: unknown least-squares mode");
         in.ls_mode = ext->ls_mode;
+        TTSG_CHECK(ext->variant == TTSG_VARIANT_ENHANCED || ext->variant == TTSG_VARIANT_VANILLA, TTSG_ERR_ARG,
+                   "sgmres: variant must be TTSG_VARIANT_ENHANCED or TTSG_VARIANT_VANILLA");
+        in.variant = ext->variant;
         if (ext->x0 != nullptr || ext->x0_r != nullptr) {
             TTSG_CHECK(ext->x0 != nullptr && ext->x0_r != nullptr, TTSG_ERR_ARG, "sgmres: x0 needs cores and ranks");
             check_shape(d, n, ext->x0_r, "sgmres x0");
@@ -663,6 +666,53 @@ int ttsg_sgmres_workspace_size(int32_t d, const int32_t* n, const int32_t* R, co
         ttsg::SolverInputs in = solver_inputs(d, n, R, nullptr, rb, nullptr, s, nullptr, rho, nullptr, rx, nullptr,
                                               opts, ext, true);
         *bytes = ttsg::sgmres_workspace(in);
+        return 0;
+    });
+}
+
+static ttsg::GmresInputs gmres_inputs(int32_t d, const int32_t* n, const int32_t* R, const double* const* A,
+                                       const int32_t* rb, const double* const* b, const ttsg_gmres_opts* o) {
+    check_shape(d, n, R, "tt_gmres A");
+    check_shape(d, n, rb, "tt_gmres b");
+    TTSG_CHECK(o != nullptr, TTSG_ERR_ARG, "tt_gmres: null options");
+    TTSG_CHECK(o->maxit >= 1 && o->maxit <= 4096, TTSG_ERR_ARG, "tt_gmres: maxit must be in 1..4096");
+    TTSG_CHECK(o->maxrank >= 0, TTSG_ERR_ARG, "tt_gmres: maxrank < 0");
+    TTSG_CHECK(o->tol > 0.0 && o->tol < 1.0 && o->final_tol >= 0.0 && o->max_round > 0.0, TTSG_ERR_ARG,
+               "tt_gmres: need 0 < tol < 1, final_tol >= 0, max_round > 0");
+    ttsg::GmresInputs in;
+    in.d = d;
+    in.n = n;
+    in.R = vec(R, d + 1);
+    in.rb = vec(rb, d + 1);
+    if (A) in.A.assign(A, A + d);
+    if (b) in.b.assign(b, b + d);
+    in.maxit = o->maxit;
+    in.maxrank = o->maxrank;
+    in.tol = o->tol;
+    in.final_tol = o->final_tol > 0.0 ? o->final_tol : o->tol;
+    in.max_round = o->max_round;
+    return in;
+}
+
+int ttsg_tt_gmres(int32_t d, const int32_t* n, const int32_t* R, const double* const* A, const int32_t* rb,
+                  const double* const* b, const ttsg_gmres_opts* opts, double* const* x, int32_t* x_r,
+                  ttsg_sgmres_info* info, void* ws, size_t ws_bytes, ttsg_stream_t stream) {
+    return guarded([&]() {
+        ttsg::GmresInputs in = gmres_inputs(d, n, R, A, rb, b, opts);
+        check_ptrs(d, (const void* const*)A, "tt_gmres A");
+        check_ptrs(d, (const void* const*)b, "tt_gmres b");
+        check_ptrs(d, (const void* const*)x, "tt_gmres x");
+        TTSG_CHECK(x_r != nullptr, TTSG_ERR_ARG, "tt_gmres: null x_r");
+        return ttsg::tt_gmres_solve(in, x, x_r, info, ws, ws_bytes, S(stream));
+    });
+}
+
+int ttsg_tt_gmres_workspace_size(int32_t d, const int32_t* n, const int32_t* R, const int32_t* rb,
+                                 const ttsg_gmres_opts* opts, size_t* bytes) {
+    return guarded([&]() {
+        TTSG_CHECK(bytes != nullptr, TTSG_ERR_ARG, "tt_gmres_workspace_size: null output");
+        ttsg::GmresInputs in = gmres_inputs(d, n, R, nullptr, rb, nullptr, opts);
+        *bytes = ttsg::tt_gmres_workspace(in);
         return 0;
     });
 }

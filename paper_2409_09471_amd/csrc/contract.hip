@@ -13,11 +13,12 @@
 // Matrix-core forms used (gfx950):
 //   FP64: v_mfma_f64_16x16x4_f64      (A, B, C in float64)
 //   FP32: v_mfma_f32_16x16x4_f32      (A, B, C in float32)
-//   BF16: v_mfma_f32_16x16x16_bf16    (A, B stored as float32 and rounded to
+//   BF16: v_mfma_f32_16x16x32_bf16    (A, B stored as float32 and rounded to
 //         bfloat16, nearest-even, while they are staged into LDS; C in float32)
 // Operand layout of the 16x16xK forms: lane l supplies row (l % 16) of A and
-// column (l % 16) of B for the k-group (l / 16); the accumulator of lane l holds
-// column (l % 16), rows given by Traits<T>::acc_row.
+// column (l % 16) of B for the k-group (l / 16) (one k for the 4-deep FP64/FP32
+// forms, eight consecutive k for the 32-deep BF16 form); the accumulator of
+// lane l holds column (l % 16), rows given by Traits<T>::acc_row.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -31,7 +32,8 @@ namespace {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
-typedef short s4_t __attribute__((ext_vector_type(4)));
+typedef short s8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
 constexpr int BM64 = 64;   // tile edge that the split-K decision is based on
 
@@ -217,23 +219,25 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
             lb.fetch(k0 + BK);
         }
         if constexpr (sizeof(lds_t) == 2) {
+            // gfx950's 16x16x32 form: one instruction per 32-deep slab, lane l
+            // supplying k = 8 (l / 16) + 0..7 of row / column l % 16
+            static_assert(BK == 32, "the bf16 slab is one 16x16x32 step");
+            s8_t a[WM], b[WN];
 #pragma unroll
-            for (int kk = 0; kk < BK; kk += 16) {
-                s4_t a[WM], b[WN];
+            for (int i = 0; i < WM; ++i)
 #pragma unroll
-                for (int i = 0; i < WM; ++i)
+                for (int t = 0; t < 8; ++t) a[i][t] = (short)As[8 * lg + t][wm + 16 * i + lr];
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) a[i][t] = (short)As[kk + 4 * lg + t][wm + 16 * i + lr];
+            for (int j = 0; j < WN; ++j)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) b[j][t] = (short)Bs[8 * lg + t][wn + 16 * j + lr];
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
 #pragma unroll
                 for (int j = 0; j < WN; ++j)
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) b[j][t] = (short)Bs[kk + 4 * lg + t][wn + 16 * j + lr];
-#pragma unroll
-                for (int i = 0; i < WM; ++i)
-#pragma unroll
-                    for (int j = 0; j < WN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
-            }
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, a[i]),
+                                                                         __builtin_bit_cast(bf8_t, b[j]), acc[i][j],
+                                                                         0, 0, 0);
         } else {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
@@ -491,19 +495,25 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
     StatScope scope(cls, flops, bytes, st);
     using out_t = typename Traits<T>::out_t;
     // split-K when the output tiles alone cannot fill the chip (at least four
-    // k-slabs per split, at most 64 splits, about two workgroups per CU).  The
-    // decision uses 64 x 64 tiles whatever tile variant runs, so every variant
-    // sums in the same order and gives bit-identical results.
+    // k-slabs per split, at most 64 splits, about two workgroups per CU; four
+    // per CU for reductions of 2048 or more, whose long k-loops otherwise run
+    // with one workgroup per CU and expose the global-load latency of every
+    // slab).  The decision uses 64 x 64 tiles whatever tile variant runs, so
+    // every variant sums in the same order and gives bit-identical results.
     constexpr int BK = Traits<T>::BK;
     const int64_t gx64 = (d.N + BM64 - 1) / BM64, gy64 = (d.M + BM64 - 1) / BM64;
     TTSG_CHECK((d.M + 31) / 32 < 65536, TTSG_ERR_ARG, "contraction: M too large");
     const int64_t wgs = gx64 * gy64 * d.batch;
+    const bool long_k = d.K >= 2048;
+    const int64_t target = long_k ? 1024 : 512;
     int splits = 1, kchunk = d.K;
-    if (ar != nullptr && wgs < 512 && d.K >= 8 * BK) {
-        int want = (int)std::min<int64_t>((512 + wgs - 1) / wgs, d.K / (4 * BK));
+    if (ar != nullptr && wgs < target && d.K >= 8 * BK) {
+        int want = (int)std::min<int64_t>((target + wgs - 1) / wgs, d.K / (4 * BK));
         want = std::min(want, 64);
         want = std::min<int64_t>(want, 65535 / std::max(d.batch, 1));
-        if (want >= 5) {   // two to four splits of an already wide grid cost more in the extra reduction than they save
+        // two to four splits of an already wide grid cost more in the extra
+        // reduction than they save, unless the reduction is long
+        if (want >= 5 || (long_k && want >= 2)) {
             kchunk = ((d.K + want - 1) / want + BK - 1) / BK * BK;
             splits = (d.K + kchunk - 1) / kchunk;
         }

@@ -276,6 +276,12 @@ class SgmresSolver {
     double* z_ = nullptr;
     double* lsres_ = nullptr;
     double* hco_ = nullptr;                     // [1, h_1..h_q]
+    bool vanilla_ = false;                      // Alg. 3 final sums: every basis vector of the cycle kept
+    std::vector<std::vector<double*>> basis_;   // (m + 1) TT buffers at capacity rx (vanilla only)
+    std::vector<std::vector<int>> basis_r_;
+    std::vector<double*> vacc_;                 // running sum of the vanilla solution (capacity rx)
+    std::vector<double*> xbest_;                // iterate with the smallest true residual so far
+    std::vector<int> xbest_r_;
     double* y_ = nullptr;
     double* xw_ = nullptr;                      // one more TT at 2x capacity for sums
     std::vector<double*> xsum_;
@@ -415,6 +421,19 @@ void SgmresSolver::carve(Arena& ar) {
     }
     scal_ = ar.get<double>(8);
     flag_ = ar.get<int>(8);
+    xbest_.assign(d, nullptr);
+    for (int mu = 0; mu < d; ++mu) xbest_[mu] = ar.get<double>(cap_[mu]);
+    vanilla_ = in_.variant == TTSG_VARIANT_VANILLA;
+    basis_.clear();
+    basis_r_.clear();
+    vacc_.assign(d, nullptr);
+    if (vanilla_) {
+        basis_.assign(m_ + 1, std::vector<double*>(d));
+        basis_r_.assign(m_ + 1, std::vector<int>(d + 1, 1));
+        for (int i = 0; i <= m_; ++i)
+            for (int mu = 0; mu < d; ++mu) basis_[i][mu] = ar.get<double>(cap_[mu]);
+        for (int mu = 0; mu < d; ++mu) vacc_[mu] = ar.get<double>(cap_[mu]);
+    }
     pre_ = in_.zeta > 0;
     white_ = in_.ls_mode == TTSG_LS_WHITEN;
     Eblk_.assign(d, nullptr);
@@ -723,6 +742,12 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     // the zeta terms alpha_j A ((x)_k E_jk v_k) in term order; the sketch of
     // v_k itself (kept for the final solution) runs on stream H meanwhile.
     // The combination with the window sketches follows as in Alg. 4.
+    // Arithmetic of this step's sketch of A v_k and coefficients h.  In the
+    // bfloat16 mode the float32 form runs until the sketched residual is below
+    // tol / (4 u_bf16): the perturbation of A v_k that a Krylov step tolerates
+    // grows like tol / (relative residual) (inexact Arnoldi, Sec. 2.3), and a
+    // bfloat16 sketch perturbs the new direction by about its unit roundoff.
+    Prec pk_cur = p_;
     auto precond_step = [&](int k, int vk, const std::vector<int>& window) {
         const int nw = (int)window.size();
         TTSG_HIP(hipStreamWaitEvent(side.h, side.v, 0));
@@ -748,7 +773,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
                 if (j > 0) axpby(s, 1.0, wtmp_, 1.0, wcol, st_);
             }
             for (int t = 0; t < nw; ++t)
-                inner_run(p_, d, n, in_.R, Dv, slot_r_[vk], zop, slot_r_[window[t]], slot_ops(window[t]),
+                inner_run(pk_cur, d, n, in_.R, Dv, slot_r_[vk], zop, slot_r_[window[t]], slot_ops(window[t]),
                           htmp_ + t * in_.zeta + j, scratch_, st_);
             stta_sketch(so_op, slot_r_[vk], zop, (j == 0 ? pa : pt).data(), (j == 0 ? oa : ot).data(), scratch_, st_,
                         &sk_side);
@@ -780,7 +805,8 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         xcur_r_ = in_.x0_r;
         have_x = true;
     }
-    double last_sres = 1.0, last_true = 1.0;
+    double last_sres = 1.0, last_true = 1.0, best_true = INFINITY;
+    bool best_is_bound = false;
     const int max_cycles = o.max_cycles > 0 ? o.max_cycles : 50;
     const double final_tol = o.final_tol > 0.0 ? o.final_tol : o.round_tol;
     const double stop = o.stop_safety * o.tol * Sb;
@@ -832,6 +858,11 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         }
         scale_f64((int64_t)slot_r_[s0][0] * n[0] * slot_r_[s0][1], 1.0 / beta, slots_[s0][0], st_);
         to_lp(s0);
+        if (vanilla_) {
+            basis_r_[0] = slot_r_[s0];
+            for (int mu = 0; mu < d; ++mu)
+                copy_f64((int64_t)slot_r_[s0][mu] * n[mu] * slot_r_[s0][mu + 1], slots_[s0][mu], basis_[0][mu], st_);
+        }
         // S r0 = beta * S v1
         {
             std::vector<const void*> S64(in_.S.begin(), in_.S.end()), c64(slots_[s0].begin(), slots_[s0].end());
@@ -860,6 +891,8 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         for (int k = 0; k < m_ && total < maxit_; ++k) {
             const int vk = window.back();
             const int nw_k = (int)window.size();
+            pk_cur = (p_ == Prec::BF16 && !(last_sres <= o.tol / (4.0 * 0.00390625))) ? Prec::F32 : p_;
+            so_op.p = pk_cur;
             TTSG_HIP(hipEventRecord(side.v, st_));   // v_k (and S r0) are in place
             auto t1 = now();
             if (pre_) {
@@ -889,7 +922,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             const int nw = (int)window.size();
             for (int t = 0; t < nw; ++t) {
                 const int vi = window[t];
-                inner_run(p_, d, n, in_.R, Dv, slot_r_[vk], slot_ops(vk), slot_r_[vi], slot_ops(vi), hco_ + 1 + t,
+                inner_run(pk_cur, d, n, in_.R, Dv, slot_r_[vk], slot_ops(vk), slot_r_[vi], slot_ops(vi), hco_ + 1 + t,
                           scratchH_, side.h);
             }
             TTSG_HIP(hipEventRecord(side.hd, side.h));
@@ -926,15 +959,15 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
                 std::vector<const double*> cpsi(psi.begin(), psi.end()), com(om.begin(), om.end());
                 // sketches of A v_k carry the working precision's rounding: singular
                 // values of Omega below it are noise, not directions
-                const double rc = p_ == Prec::F64 ? o.rcond
-                                                  : std::max(o.rcond, p_ == Prec::F32 ? 1e-6 : 4e-3);
+                const double rc = pk_cur == Prec::F64 ? o.rcond
+                                                      : std::max(o.rcond, pk_cur == Prec::F32 ? 1e-6 : 4e-3);
                 stta_recover(d, n, in_.rho, in_.rx, cpsi, com, rc, slots_[fs], slot_r_[fs], scratch_, st_);
             }
             add_phase(TTSG_PH_RECOVER, t1);
             t1 = now();
             // bfloat16 sketches of A v_k err by about its unit roundoff (2^-8):
             // directions below that are noise and are not kept in the basis
-            const double basis_tol = p_ == Prec::BF16 ? std::max(o.round_tol, 0.00390625) : o.round_tol;
+            const double basis_tol = pk_cur == Prec::BF16 ? std::max(o.round_tol, 0.00390625) : o.round_tol;
             (void)take_rank_cap_events();
             const double h = tt_svd_inplace(d, n, slot_r_[fs], slots_[fs], cap_, basis_tol, o.maxrank, scratch_,
                                             st_, nullptr);
@@ -1002,6 +1035,12 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             t1 = now();
             scale_f64((int64_t)slot_r_[fs][0] * n[0] * slot_r_[fs][1], 1.0 / h, slots_[fs][0], st_);
             to_lp(fs);
+            if (vanilla_) {
+                basis_r_[k + 1] = slot_r_[fs];
+                for (int mu = 0; mu < d; ++mu)
+                    copy_f64((int64_t)slot_r_[fs][mu] * n[mu] * slot_r_[fs][mu + 1], slots_[fs][mu],
+                             basis_[k + 1][mu], st_);
+            }
             window.push_back(fs);
             if ((int)window.size() > q_) window.erase(window.begin());
             add_phase(TTSG_PH_STTA, t1);
@@ -1029,10 +1068,31 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
                     fs = sl;
                     break;
                 }
-            stta_recover(d, n, in_.rho, in_.rx, cpsi, com, o.rcond, slots_[fs], cr, scratch_, st_);
             int cap = 0;
             for (int k = 0; k <= d; ++k) cap = std::max(cap, in_.rx[k]);
-            tt_svd_inplace(d, n, cr, slots_[fs], cap_, final_tol, cap, scratch_, st_, nullptr);
+            if (vanilla_) {
+                // Alg. 3: x = Round(x + y_i v_i, final_tol) one basis vector at a time
+                std::vector<double> hy(std::max(kk, 1));
+                TTSG_HIP(hipMemcpyAsync(hy.data(), y_, kk * sizeof(double), hipMemcpyDeviceToHost, st_));
+                TTSG_HIP(hipStreamSynchronize(st_));
+                cr = basis_r_[0];
+                for (int mu = 0; mu < d; ++mu)
+                    copy_f64((int64_t)cr[mu] * n[mu] * cr[mu + 1], basis_[0][mu], vacc_[mu], st_);
+                scale_f64((int64_t)cr[0] * n[0] * cr[1], hy[0], vacc_[0], st_);
+                for (int i = 1; i < kk; ++i) {
+                    std::vector<int> sr;
+                    tt_add_block(d, n, cr, vacc_, basis_r_[i], cvec(basis_[i]), hy[i], xsum_, sr, st_);
+                    tt_svd_inplace(d, n, sr, xsum_, cap_, final_tol, cap, scratch_, st_, nullptr);
+                    for (int mu = 0; mu < d; ++mu)
+                        copy_f64((int64_t)sr[mu] * n[mu] * sr[mu + 1], xsum_[mu], vacc_[mu], st_);
+                    cr = sr;
+                }
+                for (int mu = 0; mu < d; ++mu)
+                    copy_f64((int64_t)cr[mu] * n[mu] * cr[mu + 1], vacc_[mu], slots_[fs][mu], st_);
+            } else {
+                stta_recover(d, n, in_.rho, in_.rx, cpsi, com, o.rcond, slots_[fs], cr, scratch_, st_);
+                tt_svd_inplace(d, n, cr, slots_[fs], cap_, final_tol, cap, scratch_, st_, nullptr);
+            }
             if (pre_) {
                 // x gains P^{-1} u: the STTA sketches of the zeta terms
                 // alpha_j (x)_k E_jk u are summed, recovered and rounded
@@ -1073,6 +1133,23 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             status = breakdown ? TTSG_BREAKDOWN : (cap_events > 0 ? TTSG_RANK_CAPPED : TTSG_OK);
             break;
         }
+        // A restart cycle that leaves a larger true residual than the best
+        // iterate so far (its correction solved a residual that the rank caps
+        // or the working precision could not represent) ends the solve with
+        // that best iterate.
+        if (cycles > 1 && !(last_true < best_true)) {
+            for (int mu = 0; mu < d; ++mu)
+                copy_f64((int64_t)xbest_r_[mu] * n[mu] * xbest_r_[mu + 1], xbest_[mu], xcur_[mu], st_);
+            xcur_r_ = xbest_r_;
+            last_true = best_true;
+            true_is_bound = best_is_bound;
+            break;
+        }
+        best_true = last_true;
+        best_is_bound = true_is_bound;
+        xbest_r_ = xcur_r_;
+        for (int mu = 0; mu < d; ++mu)
+            copy_f64((int64_t)xcur_r_[mu] * n[mu] * xcur_r_[mu + 1], xcur_[mu], xbest_[mu], st_);
         (void)corr;
     }
     // ---- output ----

@@ -235,7 +235,28 @@ struct SolverInputs {
     std::vector<double> alpha, beta;
     std::vector<const double*> M;     // d mode matrices n_k x n_k
     int ls_mode = TTSG_LS_PINV;
+    int variant = TTSG_VARIANT_ENHANCED;
 };
+
+// TT-GMRES (Alg. 2; gmres.hip): full modified Gram-Schmidt, TT-SVD rounding
+// relaxed as eta_k tol, eta_k = tol / (relative residual of step k-1), capped at
+// max_round; x_0 = 0; solution by sequential rounded sums at final_tol.
+// maxrank > 0 caps every basis rank (and sizes the buffers); 0 = the full bond
+// ranks.
+struct GmresInputs {
+    int d;
+    const int* n;
+    std::vector<int> R;
+    std::vector<const double*> A;
+    std::vector<int> rb;
+    std::vector<const double*> b;
+    int maxit = 1;
+    int maxrank = 0;
+    double tol = 1e-6, final_tol = 1e-6, max_round = 0.1;
+};
+int tt_gmres_solve(const GmresInputs& in, double* const* x, int32_t* x_r, ttsg_sgmres_info* info, void* ws,
+                   size_t ws_bytes, hipStream_t st);
+size_t tt_gmres_workspace(const GmresInputs& in);
 
 int sgmres_solve(const SolverInputs& in, double* const* x, int32_t* x_r, ttsg_sgmres_info* info, void* ws,
                  size_t ws_bytes, hipStream_t st);

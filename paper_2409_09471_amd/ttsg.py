@@ -35,6 +35,8 @@ ERR_DTYPE = -6
 
 LS_PINV = 0
 LS_WHITEN = 1
+VARIANT_ENHANCED = 0   # Alg. 4: the cycle's solution recovered from the combined sketches
+VARIANT_VANILLA = 1    # Alg. 3: sequential rounded sums of the kept basis vectors
 
 _lib = None
 
@@ -65,7 +67,7 @@ EXPORTED = [
     "ttsg_grad_kron_sum", "ttsg_tt_axpby", "ttsg_stats_enable", "ttsg_stats_read",
     "ttsg_sgmres_solve_ex", "ttsg_sgmres_workspace_size", "ttsg_expsum", "ttsg_precond_round",
     "ttsg_kr_sketch_workspace_size", "ttsg_stta_sketch_workspace_size", "ttsg_round_rand_workspace_size",
-    "ttsg_stta_sketch_noalloc",
+    "ttsg_stta_sketch_noalloc", "ttsg_tt_gmres", "ttsg_tt_gmres_workspace_size",
 ]
 
 STAT_CLASSES = {0: "contract_f64", 1: "contract_f32", 2: "contract_bf16", 3: "qr", 4: "svd_jacobi",
@@ -135,7 +137,7 @@ class SgmresExt(ctypes.Structure):
     _fields_ = [
         ("x0_r", ctypes.c_void_p), ("x0", ctypes.c_void_p),
         ("zeta", ctypes.c_int32), ("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p), ("M", ctypes.c_void_p),
-        ("ls_mode", ctypes.c_int32),
+        ("ls_mode", ctypes.c_int32), ("variant", ctypes.c_int32),
     ]
 
 
@@ -458,7 +460,7 @@ def sgmres_solve(A, b, S, X, Y, rx, rho, *, maxit: int, tol: float, q: int = 1, 
                  maxrank: int = 0, restart: int = 0, final_tol: float = 0.0, stop_safety: float = 0.1,
                  rcond: float = 1e-12, precision: int = PREC_F64, max_cycles: int = 50,
                  phase_timing: bool = False, x0: Optional[Sequence[torch.Tensor]] = None,
-                 precond: Optional[Preconditioner] = None, ls: int = LS_PINV,
+                 precond: Optional[Preconditioner] = None, ls: int = LS_PINV, variant: int = VARIANT_ENHANCED,
                  workspace: Optional[torch.Tensor] = None, raise_on_error: bool = True) -> SolveResult:
     """Alg. 4 (Alg. 5 with `precond`).  The workspace is queried and allocated
     here (or passed in), so the library allocates no device memory."""
@@ -469,7 +471,7 @@ def sgmres_solve(A, b, S, X, Y, rx, rho, *, maxit: int, tol: float, q: int = 1, 
                       max_cycles=max_cycles, tol=tol, round_tol=round_tol, final_tol=final_tol,
                       stop_safety=stop_safety, rcond=rcond)
     keep = []
-    ext = SgmresExt(ls_mode=int(ls))
+    ext = SgmresExt(ls_mode=int(ls), variant=int(variant))
     if x0 is not None:
         r0a, p0a = _i32(ranks_of(x0)), _ptrs(x0)
         keep += [r0a, p0a]
@@ -543,6 +545,50 @@ class BatchSystem:
     rcond: float = 1e-12
     precision: int = PREC_F64
     max_cycles: int = 50
+
+
+class GmresOpts(ctypes.Structure):
+    _fields_ = [("maxit", ctypes.c_int32), ("maxrank", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("final_tol", ctypes.c_double), ("max_round", ctypes.c_double)]
+
+
+def tt_gmres(A, b, *, maxit: int, tol: float, final_tol: float = 0.0, max_round: float = 0.1, maxrank: int = 0,
+             raise_on_error: bool = True) -> SolveResult:
+    """TT-GMRES (Alg. 2, ttsg_tt_gmres) with x_0 = 0.  `sketched_history` holds
+    the Arnoldi residuals ||r_k|| / ||b|| of every step."""
+    d = len(b)
+    n = sizes_of(b)
+    dev = b[0].device
+    opts = GmresOpts(maxit=maxit, maxrank=maxrank, tol=tol, final_tol=final_tol, max_round=max_round)
+    nb = ctypes.c_size_t(0)
+    _check(lib().ttsg_tt_gmres_workspace_size(d, _i32(n), _i32(op_ranks(A)), _i32(ranks_of(b)), ctypes.byref(opts),
+                                              ctypes.byref(nb)), "ttsg_tt_gmres_workspace_size")
+    ws = _workspace(nb.value, dev)
+    caps = [1] * (d + 1)
+    left = 1
+    for k in range(1, d):
+        left *= n[k - 1]
+        right = 1
+        for j in range(k, d):
+            right *= n[j]
+        caps[k] = min(left, right) if maxrank <= 0 else min(left, right, maxrank)
+    x = [torch.zeros((caps[k], n[k], caps[k + 1]), dtype=torch.float64, device=dev) for k in range(d)]
+    xr = (ctypes.c_int32 * (d + 1))()
+    sh = (ctypes.c_double * maxit)()
+    rh = (ctypes.c_int32 * maxit)()
+    info = SgmresInfo(sketched_history=sh, rank_history=rh)
+    rc = lib().ttsg_tt_gmres(d, _i32(n), _i32(op_ranks(A)), _ptrs(A), _i32(ranks_of(b)), _ptrs(b), ctypes.byref(opts),
+                             _ptrs(x), xr, ctypes.byref(info), ctypes.c_void_p(ws.data_ptr()), nb, _stream())
+    if raise_on_error:
+        _check(rc, "ttsg_tt_gmres")
+    elif rc < 0:
+        return SolveResult(x=[], status=rc, iterations=0, cycles=0, true_residual=float("nan"),
+                           sketched_residual=float("nan"), max_rank=0)
+    it = info.iterations
+    return SolveResult(x=_trim(x, list(xr)), status=rc, iterations=it, cycles=1, true_residual=info.true_residual,
+                       sketched_residual=info.sketched_residual, max_rank=info.max_rank,
+                       sketched_history=[sh[i] for i in range(min(it, maxit))],
+                       rank_history=[rh[i] for i in range(min(it, maxit))])
 
 
 def sgmres_solve_batched(systems: Sequence[BatchSystem], concurrency: int = 8) -> List[SolveResult]:
