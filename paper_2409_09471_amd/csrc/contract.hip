@@ -24,6 +24,7 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "ttsg_internal.h"
 
@@ -150,6 +151,74 @@ struct SlabLoader {
     }
 };
 
+// A operand of a Khatri-Rao step formed while it is staged (k-fast layout:
+// thread tid owns k = k0 + tid % BK and rows tid / BK + (256 / BK) t): row m =
+// (j, be), column k = (a, i), value sum_al P[j][al][a] SA[j][al][i][be], the RL
+// terms added in order.  fetch() only issues the 2 RL loads per element (they
+// complete while the matrix cores work on the current slab); commit() forms the
+// sums as it writes the LDS slab.  The s R r n intermediate is never stored.
+template <typename T, int ROWS, int RL>
+struct KrLoader {
+    using in_t = typename Traits<T>::in_t;
+    using lds_t = typename Traits<T>::lds_t;
+    static constexpr int BK = Traits<T>::BK;
+    static constexpr int PER = ROWS * BK / 256;
+    const in_t* P;
+    const in_t* SA;
+    int rl, n, Rr, kend;
+    int64_t pb[PER], sb[PER];   // per row: P offset of (j, 0, 0), SA offset of (j, 0, 0, be); pb < 0: outside
+    in_t pv[PER][RL], sv[PER][RL];
+
+    __device__ __forceinline__ void init(const ContractDesc& d, int row0, int kend_) {
+        P = static_cast<const in_t*>(d.kr_P);
+        SA = static_cast<const in_t*>(d.kr_SA);
+        rl = d.kr_rl;
+        n = d.kr_n;
+        Rr = d.kr_Rr;
+        kend = kend_;
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int gr = row0 + tid / BK + (256 / BK) * t;
+            if (gr < d.M) {
+                const int64_t j = gr / Rr;
+                const int be = gr - (int)(j * Rr);
+                pb[t] = j * RL * rl;
+                sb[t] = j * RL * n * Rr + be;
+            } else {
+                pb[t] = -1;
+                sb[t] = 0;
+            }
+        }
+    }
+    __device__ __forceinline__ void fetch(int k0) {
+        const int gk = k0 + (int)(threadIdx.x % BK);
+        const bool kin = gk < kend;
+        const int a = kin ? gk / n : 0;
+        const int i = kin ? gk - a * n : 0;
+        const int64_t nR = (int64_t)n * Rr;
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const bool on = kin && pb[t] >= 0;
+#pragma unroll
+            for (int al = 0; al < RL; ++al) {
+                pv[t][al] = on ? P[pb[t] + a + (int64_t)al * rl] : in_t(0);
+                sv[t][al] = on ? SA[sb[t] + (int64_t)i * Rr + al * nR] : in_t(0);
+            }
+        }
+    }
+    __device__ __forceinline__ void commit(lds_t (*S)[ROWS + 1]) const {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            in_t acc = in_t(0);
+#pragma unroll
+            for (int al = 0; al < RL; ++al) acc += pv[t][al] * sv[t][al];
+            S[tid % BK][tid / BK + (256 / BK) * t] = Traits<T>::stage(acc);
+        }
+    }
+};
+
 __device__ __forceinline__ d4_t mfma(double a, double b, d4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -160,7 +229,7 @@ __device__ __forceinline__ f4_t mfma(float a, float b, f4_t c) {
 // With splits > 1 every workgroup reduces one K-chunk of kchunk values and
 // writes its unscaled partial tile to part[split][batch][M][N]; a second
 // kernel sums the partials in a fixed order (deterministic) into C.
-template <typename T, int WM, int WN>
+template <typename T, int WM, int WN, int KRL>
 __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typename Traits<T>::in_t* __restrict__ A,
                                                        const typename Traits<T>::in_t* __restrict__ B,
                                                        typename Traits<T>::out_t* __restrict__ C,
@@ -184,7 +253,7 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
     const int kend = min(d.K, kbeg + kchunk);
     const int m0 = blockIdx.y * TM;
     const int n0 = blockIdx.x * TN;
-    const in_t* Ab = A + idx_off(d.ab, bidx);
+    const in_t* Ab = KRL > 0 ? A : A + idx_off(d.ab, bidx);
     const in_t* Bb = B + idx_off(d.bb, bidx);
     out_t* Cb = C + idx_off(d.cb, bidx);
 
@@ -201,9 +270,12 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
 #pragma unroll
         for (int j = 0; j < WN; ++j) acc[i][j] = acc4{0, 0, 0, 0};
 
-    SlabLoader<T, TM> la;
+    typename std::conditional<(KRL > 0), KrLoader<T, TM, (KRL > 0 ? KRL : 1)>, SlabLoader<T, TM>>::type la;
     SlabLoader<T, TN> lb;
-    la.init(Ab, d.am, d.ak, m0, d.M, kend, d.ak.s0 == 1);
+    if constexpr (KRL > 0)
+        la.init(d, m0, kend);
+    else
+        la.init(Ab, d.am, d.ak, m0, d.M, kend, d.ak.s0 == 1);
     lb.init(Bb, d.bn, d.bk, n0, d.N, kend, d.bk.s0 == 1);
     if (kbeg < kend) {
         la.fetch(kbeg);
@@ -346,7 +418,7 @@ constexpr int kVariants = 4;
 constexpr int kVarWM[kVariants] = {2, 1, 2, 1};
 constexpr int kVarWN[kVariants] = {2, 2, 1, 1};
 
-template <typename T, int WM, int WN>
+template <typename T, int WM, int WN, int KRL>
 void run_tiles(const ContractDesc& d, const typename Traits<T>::in_t* A, const typename Traits<T>::in_t* B,
                typename Traits<T>::out_t* C, int splits, int kchunk, hipStream_t st, Arena* ar, DevSlot* slot) {
     using out_t = typename Traits<T>::out_t;
@@ -355,15 +427,15 @@ void run_tiles(const ContractDesc& d, const typename Traits<T>::in_t* A, const t
     if (splits > 1) {
         const size_t mark = ar->mark();
         out_t* part = ar->get<out_t>((size_t)splits * d.batch * d.M * d.N);
-        hipLaunchKernelGGL((contract_kernel<T, WM, WN>), dim3(gx, gy, d.batch * splits), dim3(256), 0, st, d, A, B,
-                           C, 0, splits, kchunk, part, slot);
+        hipLaunchKernelGGL((contract_kernel<T, WM, WN, KRL>), dim3(gx, gy, d.batch * splits), dim3(256), 0, st, d,
+                           A, B, C, 0, splits, kchunk, part, slot);
         launch_reduce<out_t>(d, splits, part, C, st);
         ar->release(mark);
     } else {
         for (int b0 = 0; b0 < d.batch; b0 += 65535) {
             const int nb = d.batch - b0 < 65535 ? d.batch - b0 : 65535;
-            hipLaunchKernelGGL((contract_kernel<T, WM, WN>), dim3(gx, gy, nb), dim3(256), 0, st, d, A, B, C, b0, 1,
-                               d.K, static_cast<out_t*>(nullptr), slot);
+            hipLaunchKernelGGL((contract_kernel<T, WM, WN, KRL>), dim3(gx, gy, nb), dim3(256), 0, st, d, A, B, C, b0,
+                               1, d.K, static_cast<out_t*>(nullptr), slot);
         }
     }
     TTSG_HIP(hipGetLastError());
@@ -372,11 +444,35 @@ void run_tiles(const ContractDesc& d, const typename Traits<T>::in_t* A, const t
 template <typename T>
 void run_variant(int v, const ContractDesc& d, const typename Traits<T>::in_t* A, const typename Traits<T>::in_t* B,
                  typename Traits<T>::out_t* C, int splits, int kchunk, hipStream_t st, Arena* ar, DevSlot* slot) {
+    if (d.kr_P != nullptr) {
+        if constexpr (sizeof(typename Traits<T>::lds_t) == 2) {
+            TTSG_CHECK(false, TTSG_ERR_ARG, "contraction: the fused Khatri-Rao operand is float64/float32 only");
+        } else {
+            // 32-row tiles only: the loader keeps 2 RL operand values per element in flight
+            const bool wide = v == 1 || v == 0;
+            switch (d.kr_Rl) {
+                case 1:
+                    if (wide) run_tiles<T, 1, 2, 1>(d, A, B, C, splits, kchunk, st, ar, slot);
+                    else run_tiles<T, 1, 1, 1>(d, A, B, C, splits, kchunk, st, ar, slot);
+                    break;
+                case 2:
+                    if (wide) run_tiles<T, 1, 2, 2>(d, A, B, C, splits, kchunk, st, ar, slot);
+                    else run_tiles<T, 1, 1, 2>(d, A, B, C, splits, kchunk, st, ar, slot);
+                    break;
+                default:
+                    TTSG_CHECK(d.kr_Rl == 3, TTSG_ERR_ARG, "contraction: fused Khatri-Rao operand rank must be 1..3");
+                    if (wide) run_tiles<T, 1, 2, 3>(d, A, B, C, splits, kchunk, st, ar, slot);
+                    else run_tiles<T, 1, 1, 3>(d, A, B, C, splits, kchunk, st, ar, slot);
+                    break;
+            }
+        }
+        return;
+    }
     switch (v) {
-        case 1: run_tiles<T, 1, 2>(d, A, B, C, splits, kchunk, st, ar, slot); break;
-        case 2: run_tiles<T, 2, 1>(d, A, B, C, splits, kchunk, st, ar, slot); break;
-        case 3: run_tiles<T, 1, 1>(d, A, B, C, splits, kchunk, st, ar, slot); break;
-        default: run_tiles<T, 2, 2>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+        case 1: run_tiles<T, 1, 2, 0>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+        case 2: run_tiles<T, 2, 1, 0>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+        case 3: run_tiles<T, 1, 1, 0>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+        default: run_tiles<T, 2, 2, 0>(d, A, B, C, splits, kchunk, st, ar, slot); break;
     }
 }
 
@@ -475,7 +571,15 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         const int64_t ea = idx_max(d.ab, d.batch) + idx_max(d.am, d.M) + idx_max(d.ak, d.K) + 1;
         const int64_t eb = idx_max(d.bb, d.batch) + idx_max(d.bk, d.K) + idx_max(d.bn, d.N) + 1;
         const int64_t ec = idx_max(d.cb, d.batch) + idx_max(d.cm, d.M) + idx_max(d.cn, d.N) + 1;
-        check_range(A, ea * sizeof(in_t), "contract A");
+        if (d.kr_P != nullptr) {
+            const int64_t nj = (d.M + d.kr_Rr - 1) / d.kr_Rr;
+            TTSG_CHECK((int64_t)d.K == (int64_t)d.kr_rl * d.kr_n && d.batch == 1, TTSG_ERR_ARG,
+                       "contract: Khatri-Rao operand shape");
+            check_range(d.kr_P, nj * d.kr_Rl * d.kr_rl * sizeof(in_t), "contract KR P");
+            check_range(d.kr_SA, nj * d.kr_Rl * d.kr_n * d.kr_Rr * sizeof(in_t), "contract KR SA");
+        } else {
+            check_range(A, ea * sizeof(in_t), "contract A");
+        }
         check_range(B, eb * sizeof(in_t), "contract B");
         check_range(C, ec * (d.c_f64 ? sizeof(double) : sizeof(out_t)), "contract C");
     }
@@ -487,7 +591,10 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         using out_t = typename Traits<T>::out_t;
         const double nb = (double)d.batch;
         flops = 2.0 * d.M * (double)d.N * d.K * nb;
-        const double ua = (double)d.M * d.K * (d.ab.s0 == 0 ? 1.0 : nb);
+        // the fused Khatri-Rao operand reads P and S A, not the M x K matrix
+        const double ua = d.kr_P != nullptr
+                              ? (double)(d.M / std::max(d.kr_Rr, 1)) * d.kr_Rl * ((double)d.kr_rl + (double)d.kr_n * d.kr_Rr)
+                              : (double)d.M * d.K * (d.ab.s0 == 0 ? 1.0 : nb);
         const double ub = (double)d.K * d.N * (d.bb.s0 == 0 ? 1.0 : nb);
         const double uc = (double)d.M * d.N * nb * (d.beta != 0.0 ? 2.0 : 1.0);
         bytes = (ua + ub) * sizeof(in_t) + uc * (d.c_f64 ? sizeof(double) : sizeof(out_t));
@@ -519,10 +626,10 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         }
     }
     scope.shape(d.M, d.N, d.K, d.batch, splits);
-    const TuneKey key = tune_key(cls, d, splits);
+    const TuneKey key = tune_key(d.kr_P != nullptr ? cls + 16 : cls, d, splits);
     int variant = tuned_variant(key);
     if (variant < 0 && autotune_on()) variant = tune<T>(key, d, A, B, splits, kchunk, st, ar);
-    if (variant < 0) variant = default_variant(d);
+    if (variant < 0) variant = d.kr_P != nullptr ? 1 : default_variant(d);
     run_variant<T>(variant, d, static_cast<const in_t*>(A), static_cast<const in_t*>(B), static_cast<out_t*>(C),
                    splits, kchunk, st, ar, scope.slot());
 }

@@ -213,6 +213,25 @@ __global__ void k_kr1(int64_t total, int rl, int n, int Rl, int Rr, const T* __r
 
 void kr_step(Prec p, int s, int rl, int n, int rr, int Rl, int Rr, const void* P, const void* SA, const void* C,
              void* Xbuf, void* Pout, hipStream_t st, Arena* ar) {
+    // P'[(j,be)][b] = sum_{(a,i')} X[(j,be)][(a,i')] C[(a,i')][b] with
+    // X[j][be][a][i'] = sum_al P[j][al][a] SA[j][al][i'][be]: for operator ranks
+    // up to 3, X is formed inside the contraction's operand staging and never
+    // stored (the s R r n intermediate would be written and read back)
+    if (Rl <= 3 && p != Prec::BF16) {
+        ContractDesc d = cdesc(s * Rr, rr, rl * n);
+        d.bk = idx1(rr);
+        d.bn = idx1(1);
+        d.cm = idx1(rr);
+        d.cn = idx1(1);
+        d.kr_P = P;
+        d.kr_SA = SA;
+        d.kr_rl = rl;
+        d.kr_n = n;
+        d.kr_Rl = Rl;
+        d.kr_Rr = Rr;
+        contract(p, d, P, C, Pout, st, ar);
+        return;
+    }
     // KR1: X[j][be][a][i'] = sum_al P[j][al][a] SA[j][al][i'][be]
     if (Rl <= 4 && p != Prec::BF16) {
         const int64_t total = (int64_t)s * Rr * rl * n;
