@@ -410,13 +410,14 @@ void launch_reduce(const ContractDesc& d, int splits, const O* part, O* C, hipSt
 
 // ---------------------------------------------------------------------------
 // Tile variants and the autotuner.  Variant v runs WM x WN MFMA blocks per
-// wavefront: 0 = 64 x 64 tiles, 1 = 32 x 64, 2 = 64 x 32, 3 = 32 x 32 (M x N).
-// The tuner times every variant the first time a shape class is met while
-// tuning is on and keeps the fastest; the table can be saved and loaded.
+// wavefront: 0 = 64 x 64 tiles, 1 = 32 x 64, 2 = 64 x 32, 3 = 32 x 32,
+// 4 = 128 x 64, 5 = 64 x 128, 6 = 128 x 128 (M x N).  The larger tiles halve
+// or quarter the operand loads per flop (a 128 x 128 FP64 tile reuses each
+// staged element 128 times), at the price of fewer workgroups.  The tuner
+// times every variant the first time a shape class is met while tuning is on
+// and keeps the fastest; the table can be saved and loaded.
 // ---------------------------------------------------------------------------
-constexpr int kVariants = 4;
-constexpr int kVarWM[kVariants] = {2, 1, 2, 1};
-constexpr int kVarWN[kVariants] = {2, 2, 1, 1};
+constexpr int kVariants = 7;
 
 template <typename T, int WM, int WN, int KRL>
 void run_tiles(const ContractDesc& d, const typename Traits<T>::in_t* A, const typename Traits<T>::in_t* B,
@@ -441,38 +442,50 @@ void run_tiles(const ContractDesc& d, const typename Traits<T>::in_t* A, const t
     TTSG_HIP(hipGetLastError());
 }
 
+template <typename T, int KRL>
+void run_shape(int v, const ContractDesc& d, const typename Traits<T>::in_t* A, const typename Traits<T>::in_t* B,
+               typename Traits<T>::out_t* C, int splits, int kchunk, hipStream_t st, Arena* ar, DevSlot* slot) {
+    switch (v) {
+        case 1: run_tiles<T, 1, 2, KRL>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+        case 2: run_tiles<T, 2, 1, KRL>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+        case 3: run_tiles<T, 1, 1, KRL>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+        case 4: run_tiles<T, 4, 2, KRL>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+        case 5: run_tiles<T, 2, 4, KRL>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+        case 6:
+            // 128 x 128 is FP64 only (the float32 accumulators of the 4 x 4 block spill)
+            if constexpr (sizeof(typename Traits<T>::lds_t) == 8) {
+                run_tiles<T, 4, 4, KRL>(d, A, B, C, splits, kchunk, st, ar, slot);
+                break;
+            }
+            [[fallthrough]];
+        default: run_tiles<T, 2, 2, KRL>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+    }
+}
+
+// Variants a precision has (the 128 x 128 tile is FP64 only).
+template <typename T>
+constexpr int variants_of() {
+    return sizeof(typename Traits<T>::lds_t) == 8 ? 7 : 6;
+}
+
 template <typename T>
 void run_variant(int v, const ContractDesc& d, const typename Traits<T>::in_t* A, const typename Traits<T>::in_t* B,
                  typename Traits<T>::out_t* C, int splits, int kchunk, hipStream_t st, Arena* ar, DevSlot* slot) {
-    if (d.kr_P != nullptr) {
-        if constexpr (sizeof(typename Traits<T>::lds_t) == 2) {
-            TTSG_CHECK(false, TTSG_ERR_ARG, "contraction: the fused Khatri-Rao operand is float64/float32 only");
-        } else {
-            // 32-row tiles only: the loader keeps 2 RL operand values per element in flight
-            const bool wide = v == 1 || v == 0;
-            switch (d.kr_Rl) {
-                case 1:
-                    if (wide) run_tiles<T, 1, 2, 1>(d, A, B, C, splits, kchunk, st, ar, slot);
-                    else run_tiles<T, 1, 1, 1>(d, A, B, C, splits, kchunk, st, ar, slot);
-                    break;
-                case 2:
-                    if (wide) run_tiles<T, 1, 2, 2>(d, A, B, C, splits, kchunk, st, ar, slot);
-                    else run_tiles<T, 1, 1, 2>(d, A, B, C, splits, kchunk, st, ar, slot);
-                    break;
-                default:
-                    TTSG_CHECK(d.kr_Rl == 3, TTSG_ERR_ARG, "contraction: fused Khatri-Rao operand rank must be 1..3");
-                    if (wide) run_tiles<T, 1, 2, 3>(d, A, B, C, splits, kchunk, st, ar, slot);
-                    else run_tiles<T, 1, 1, 3>(d, A, B, C, splits, kchunk, st, ar, slot);
-                    break;
-            }
-        }
+    if (d.kr_P == nullptr) {
+        run_shape<T, 0>(v, d, A, B, C, splits, kchunk, st, ar, slot);
         return;
     }
-    switch (v) {
-        case 1: run_tiles<T, 1, 2, 0>(d, A, B, C, splits, kchunk, st, ar, slot); break;
-        case 2: run_tiles<T, 2, 1, 0>(d, A, B, C, splits, kchunk, st, ar, slot); break;
-        case 3: run_tiles<T, 1, 1, 0>(d, A, B, C, splits, kchunk, st, ar, slot); break;
-        default: run_tiles<T, 2, 2, 0>(d, A, B, C, splits, kchunk, st, ar, slot); break;
+    if constexpr (sizeof(typename Traits<T>::lds_t) == 2) {
+        TTSG_CHECK(false, TTSG_ERR_ARG, "contraction: the fused Khatri-Rao operand is float64/float32 only");
+    } else {
+        switch (d.kr_Rl) {
+            case 1: run_shape<T, 1>(v, d, A, B, C, splits, kchunk, st, ar, slot); break;
+            case 2: run_shape<T, 2>(v, d, A, B, C, splits, kchunk, st, ar, slot); break;
+            default:
+                TTSG_CHECK(d.kr_Rl == 3, TTSG_ERR_ARG, "contraction: fused Khatri-Rao operand rank must be 1..3");
+                run_shape<T, 3>(v, d, A, B, C, splits, kchunk, st, ar, slot);
+                break;
+        }
     }
 }
 
@@ -533,19 +546,20 @@ int tune(const TuneKey& key, const ContractDesc& d, const void* A, const void* B
     dc.cn = idx1(1);
     out_t* scratch = nullptr;
     TTSG_HIP(hipMallocAsync(reinterpret_cast<void**>(&scratch), (size_t)d.batch * d.M * d.N * sizeof(out_t), st));
-    hipEvent_t ev[kVariants + 1];
+    constexpr int nvar = variants_of<T>();
+    hipEvent_t ev[nvar + 1];
     for (auto& e : ev) TTSG_HIP(hipEventCreate(&e));
     TTSG_HIP(hipEventRecord(ev[0], st));
-    for (int v = 0; v < kVariants; ++v) {
+    for (int v = 0; v < nvar; ++v) {
         for (int rep = 0; rep < 3; ++rep)
             run_variant<T>(v, dc, static_cast<const in_t*>(A), static_cast<const in_t*>(B), scratch, splits, kchunk,
                            st, ar, nullptr);
         TTSG_HIP(hipEventRecord(ev[v + 1], st));
     }
-    TTSG_HIP(hipEventSynchronize(ev[kVariants]));
+    TTSG_HIP(hipEventSynchronize(ev[nvar]));
     int best = 0;
     float best_ms = 0.0f;
-    for (int v = 0; v < kVariants; ++v) {
+    for (int v = 0; v < nvar; ++v) {
         float ms = 0.0f;
         TTSG_HIP(hipEventElapsedTime(&ms, ev[v], ev[v + 1]));
         if (v == 0 || ms < best_ms) {

@@ -630,10 +630,17 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     so_op.R = in_.R;
     so_op.D = Dv;
     so_plain.R = R1;
+    // zero and identity blocks of the operator cores (exact; the float32
+    // copies keep them) are copied or skipped in the operator steps
+    const std::vector<std::vector<uint8_t>> blocks =
+        operator_blocks(d, n, in_.R, std::vector<const void*>(in_.A.begin(), in_.A.end()), st_);
+    const std::vector<const uint8_t*> blk = block_ptrs(blocks);
+    so_op.blk = blk;
     // FP64 sketches of A x for the restart residual
     SketchOperands so_op64 = so_plain;
     so_op64.R = in_.R;
     so_op64.D.assign(in_.A.begin(), in_.A.end());
+    so_op64.blk = blk;
 
     auto sk_ptrs = [&](double* base, std::vector<double*>& psi, std::vector<double*>& om) {
         psi.assign(d, nullptr);
@@ -774,7 +781,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             }
             for (int t = 0; t < nw; ++t)
                 inner_run(pk_cur, d, n, in_.R, Dv, slot_r_[vk], zop, slot_r_[window[t]], slot_ops(window[t]),
-                          htmp_ + t * in_.zeta + j, scratch_, st_);
+                          htmp_ + t * in_.zeta + j, scratch_, st_, blk);
             stta_sketch(so_op, slot_r_[vk], zop, (j == 0 ? pa : pt).data(), (j == 0 ? oa : ot).data(), scratch_, st_,
                         &sk_side);
             if (j > 0) axpby(sk_len_, 1.0, skT_, 1.0, skA_, st_);
@@ -923,7 +930,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             for (int t = 0; t < nw; ++t) {
                 const int vi = window[t];
                 inner_run(pk_cur, d, n, in_.R, Dv, slot_r_[vk], slot_ops(vk), slot_r_[vi], slot_ops(vi), hco_ + 1 + t,
-                          scratchH_, side.h);
+                          scratchH_, side.h, blk);
             }
             TTSG_HIP(hipEventRecord(side.hd, side.h));
             add_phase(TTSG_PH_INNER, t1);

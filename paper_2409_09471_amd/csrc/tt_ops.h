@@ -12,7 +12,22 @@ ContractDesc cdesc(int M, int N, int K, int batch = 1);
 // Rl/Rr (1/1 when there is no operator), probe core pl x n x pr.
 struct LeftDims {
     int rl, n, rr, Rl, Rr, pl, pr;
+    // Kinds of the operator core's n x n blocks D[al][:, :][be] (Rl x Rr,
+    // row-major; see operator_blocks), or nullptr: every block dense.
+    const uint8_t* blk = nullptr;
 };
+
+// Kind of an n x n block of an operator core: exactly zero, exactly the
+// identity, or anything else.  Kronecker-sum operators (Sec. 5.1) have mostly
+// zero and identity blocks: the operator steps copy the identity blocks and
+// skip the zero ones instead of multiplying by them.
+enum : uint8_t { kBlkZero = 0, kBlkIdentity = 1, kBlkDense = 2 };
+// Classify every block of the d float64 operator cores D[mu] (R[mu] x n x n x
+// R[mu+1]); synchronizes st once.  Result: per core, R[mu] * R[mu+1] kinds.
+std::vector<std::vector<uint8_t>> operator_blocks(int d, const int* n, const std::vector<int>& R,
+                                                  const std::vector<const void*>& D, hipStream_t st);
+// Host pointers into operator_blocks' result (empty when it is empty).
+std::vector<const uint8_t*> block_ptrs(const std::vector<std::vector<uint8_t>>& kinds);
 
 void matvec_core(int rl, int n, int rr, int Rl, int Rr, const double* D, const double* C, bool transpose,
                  double* G, hipStream_t st);
@@ -74,6 +89,7 @@ struct SketchOperands {
     std::vector<const void*> Y, X;            // d - 1 each, element type of p
     std::vector<int> R;                       // d + 1 (all 1 without operator)
     std::vector<const void*> D;               // d, element type of p, or empty
+    std::vector<const uint8_t*> blk;          // d block-kind tables of D (operator_blocks), or empty
 };
 
 // A second stream for stta_sketch: the right-environment sweep and the Omega
@@ -101,7 +117,8 @@ void kr_sketch_run(Prec p, int d, const int* n, int s, const std::vector<int>& R
 // to out_dev[0].
 void inner_run(Prec p, int d, const int* n, const std::vector<int>& R, const std::vector<const void*>& D,
                const std::vector<int>& rx_, const std::vector<const void*>& x, const std::vector<int>& rz,
-               const std::vector<const void*>& z, double* out_dev, Arena& ar, hipStream_t st);
+               const std::vector<const void*>& z, double* out_dev, Arena& ar, hipStream_t st,
+               const std::vector<const uint8_t*>& blk = {});
 
 // ---------------------------------------------------------------------------
 // LDS-resident factorizations (la_lds.hip)

@@ -52,6 +52,118 @@ void matvec_core(int rl, int n, int rr, int Rl, int Rr, const double* D, const d
 }
 
 // ---------------------------------------------------------------------------
+// Operator block kinds
+// ---------------------------------------------------------------------------
+namespace {
+
+// One workgroup per block (al, be) of a core D[al][i][j][be]: bit 0 = some
+// entry is nonzero, bit 1 = the block differs from the identity.
+__global__ __launch_bounds__(256) void k_block_kinds(int n, int Rr, const double* __restrict__ D,
+                                                     uint8_t* __restrict__ out) {
+    __shared__ int flags;
+    if (threadIdx.x == 0) flags = 0;
+    __syncthreads();
+    const int al = blockIdx.x / Rr, be = blockIdx.x - (blockIdx.x / Rr) * Rr;
+    const int64_t nn = (int64_t)n * n;
+    int f = 0;
+    for (int64_t e = threadIdx.x; e < nn; e += blockDim.x) {
+        const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+        const double v = D[(((int64_t)al * n + i) * n + j) * Rr + be];
+        if (v != 0.0) f |= 1;
+        if (v != (i == j ? 1.0 : 0.0)) f |= 2;
+    }
+    if (f != 0) atomicOr(&flags, f);
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = (flags & 1) == 0 ? kBlkZero : ((flags & 2) == 0 ? kBlkIdentity : kBlkDense);
+}
+
+// out[b][i][c] = in[b][i][c] (+ out[b][i][c] when acc) for b < B, i < I, c < Cn
+template <typename T>
+__global__ void k_block_copy(int64_t total, int I, int Cn, const T* __restrict__ in, int64_t sbi, int64_t sii,
+                             T* __restrict__ out, int64_t sbo, int64_t sio, int acc) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t bi = e / Cn;
+        const int c = (int)(e - bi * Cn);
+        const int64_t b = bi / I;
+        const int i = (int)(bi - b * I);
+        const T v = in[b * sbi + i * sii + c];
+        T* o = out + b * sbo + i * sio + c;
+        *o = acc ? *o + v : v;
+    }
+}
+
+template <typename T>
+__global__ void k_block_zero(int64_t total, int I, int Cn, T* __restrict__ out, int64_t sbo, int64_t sio) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t bi = e / Cn;
+        const int c = (int)(e - bi * Cn);
+        const int64_t b = bi / I;
+        const int i = (int)(bi - b * I);
+        out[b * sbo + i * sio + c] = T(0);
+    }
+}
+
+void block_copy(Prec p, int B, int I, int Cn, const void* in, int64_t sbi, int64_t sii, void* out, int64_t sbo,
+                int64_t sio, bool acc, hipStream_t st) {
+    const int64_t total = (int64_t)B * I * Cn;
+    if (total <= 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 16384);
+    if (p == Prec::F64)
+        hipLaunchKernelGGL(k_block_copy<double>, dim3(g), dim3(256), 0, st, total, I, Cn,
+                           static_cast<const double*>(in), sbi, sii, static_cast<double*>(out), sbo, sio, acc ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_block_copy<float>, dim3(g), dim3(256), 0, st, total, I, Cn,
+                           static_cast<const float*>(in), sbi, sii, static_cast<float*>(out), sbo, sio, acc ? 1 : 0);
+    TTSG_HIP(hipGetLastError());
+}
+
+void block_zero(Prec p, int B, int I, int Cn, void* out, int64_t sbo, int64_t sio, hipStream_t st) {
+    const int64_t total = (int64_t)B * I * Cn;
+    if (total <= 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 16384);
+    if (p == Prec::F64)
+        hipLaunchKernelGGL(k_block_zero<double>, dim3(g), dim3(256), 0, st, total, I, Cn, static_cast<double*>(out),
+                           sbo, sio);
+    else
+        hipLaunchKernelGGL(k_block_zero<float>, dim3(g), dim3(256), 0, st, total, I, Cn, static_cast<float*>(out),
+                           sbo, sio);
+    TTSG_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+std::vector<std::vector<uint8_t>> operator_blocks(int d, const int* n, const std::vector<int>& R,
+                                                  const std::vector<const void*>& D, hipStream_t st) {
+    std::vector<std::vector<uint8_t>> out(d);
+    if (D.empty()) return {};
+    int64_t tot = 0;
+    std::vector<int64_t> off(d + 1, 0);
+    for (int mu = 0; mu < d; ++mu) off[mu + 1] = off[mu] + (int64_t)R[mu] * R[mu + 1];
+    tot = off[d];
+    uint8_t* dev = nullptr;
+    TTSG_HIP(hipMallocAsync(reinterpret_cast<void**>(&dev), (size_t)std::max<int64_t>(tot, 1), st));
+    for (int mu = 0; mu < d; ++mu) {
+        hipLaunchKernelGGL(k_block_kinds, dim3(R[mu] * R[mu + 1]), dim3(256), 0, st, n[mu], R[mu + 1],
+                           static_cast<const double*>(D[mu]), dev + off[mu]);
+        TTSG_HIP(hipGetLastError());
+    }
+    std::vector<uint8_t> h((size_t)tot);
+    TTSG_HIP(hipMemcpyAsync(h.data(), dev, (size_t)tot, hipMemcpyDeviceToHost, st));
+    TTSG_HIP(hipFreeAsync(dev, st));
+    TTSG_HIP(hipStreamSynchronize(st));
+    for (int mu = 0; mu < d; ++mu) out[mu].assign(h.begin() + off[mu], h.begin() + off[mu + 1]);
+    return out;
+}
+
+std::vector<const uint8_t*> block_ptrs(const std::vector<std::vector<uint8_t>>& kinds) {
+    std::vector<const uint8_t*> p;
+    for (const auto& k : kinds) p.push_back(k.data());
+    return p;
+}
+
+// ---------------------------------------------------------------------------
 // Environment steps
 // ---------------------------------------------------------------------------
 static inline int64_t eoff(Prec p) { return p == Prec::F64 ? 8 : 4; }
@@ -71,7 +183,43 @@ void left_step(Prec p, const LeftDims& s, const void* E, const void* C, const vo
         contract(p, d, E, C, T1, st, ar);
     }
     const void* T2in = T1;
-    if (D != nullptr) {
+    if (D != nullptr && s.blk != nullptr) {
+        // L2 block by block: for each be, the dense blocks D[al][:, :][be] on
+        // the matrix cores, the identity blocks as copies of T1[p'][al], in
+        // ascending al; a column be with no nonzero block is zero
+        const size_t es = elem_size(p);
+        for (int be = 0; be < Rr; ++be) {
+            bool first = true;
+            for (int al = 0; al < Rl; ++al) {
+                const uint8_t kind = s.blk[al * Rr + be];
+                if (kind == kBlkZero) continue;
+                void* Cb = static_cast<char*>(T2) + (size_t)be * rr * es;
+                const void* Bb = static_cast<const char*>(T1) + (size_t)al * n * rr * es;
+                if (kind == kBlkIdentity) {
+                    block_copy(p, pl, n, rr, Bb, (int64_t)Rl * n * rr, rr, Cb, (int64_t)n * Rr * rr,
+                               (int64_t)Rr * rr, !first, st);
+                } else {
+                    ContractDesc d = cdesc(n, rr, n, pl);
+                    d.ab = idx1(0);
+                    d.am = idx1((int64_t)n * Rr);
+                    d.ak = idx1(Rr);
+                    d.bb = idx1((int64_t)Rl * n * rr);
+                    d.bk = idx1(rr);
+                    d.bn = idx1(1);
+                    d.cb = idx1((int64_t)n * Rr * rr);
+                    d.cm = idx1((int64_t)Rr * rr);
+                    d.cn = idx1(1);
+                    d.beta = first ? 0.0 : 1.0;
+                    contract(p, d, static_cast<const char*>(D) + ((size_t)al * n * n * Rr + be) * es, Bb, Cb, st, ar);
+                }
+                first = false;
+            }
+            if (first)
+                block_zero(p, pl, n, rr, static_cast<char*>(T2) + (size_t)be * rr * es, (int64_t)n * Rr * rr,
+                           (int64_t)Rr * rr, st);
+        }
+        T2in = T2;
+    } else if (D != nullptr) {
         // L2: T2[p'][i][be][b] = sum_{(al,j)} D[al][i][j][be] T1[p'][al][j][b]
         ContractDesc d = cdesc(n * Rr, rr, Rl * n, pl);
         d.ab = idx1(0);
@@ -115,7 +263,41 @@ void right_step(Prec p, const LeftDims& s, const void* F, const void* C, const v
         contract(p, d, C, F, U1, st, ar);
     }
     const void* U2in = U1;
-    if (D != nullptr) {
+    if (D != nullptr && s.blk != nullptr) {
+        // R2 block by block: for each al, the dense blocks D[al][:, :][be] on
+        // the matrix cores, the identity blocks as copies of U1[a][:, be], in
+        // ascending be; a row al with no nonzero block is zero
+        const size_t es = elem_size(p);
+        for (int al = 0; al < Rl; ++al) {
+            bool first = true;
+            void* Cb = static_cast<char*>(U2) + (size_t)al * n * pr * es;
+            for (int be = 0; be < Rr; ++be) {
+                const uint8_t kind = s.blk[al * Rr + be];
+                if (kind == kBlkZero) continue;
+                const void* Bb = static_cast<const char*>(U1) + (size_t)be * pr * es;
+                if (kind == kBlkIdentity) {
+                    block_copy(p, rl, n, pr, Bb, (int64_t)n * Rr * pr, (int64_t)Rr * pr, Cb, (int64_t)Rl * n * pr, pr,
+                               !first, st);
+                } else {
+                    ContractDesc d = cdesc(n, pr, n, rl);
+                    d.ab = idx1(0);
+                    d.am = idx1((int64_t)n * Rr);
+                    d.ak = idx1(Rr);
+                    d.bb = idx1((int64_t)n * Rr * pr);
+                    d.bk = idx1((int64_t)Rr * pr);
+                    d.bn = idx1(1);
+                    d.cb = idx1((int64_t)Rl * n * pr);
+                    d.cm = idx1(pr);
+                    d.cn = idx1(1);
+                    d.beta = first ? 0.0 : 1.0;
+                    contract(p, d, static_cast<const char*>(D) + ((size_t)al * n * n * Rr + be) * es, Bb, Cb, st, ar);
+                }
+                first = false;
+            }
+            if (first) block_zero(p, rl, n, pr, Cb, (int64_t)Rl * n * pr, pr, st);
+        }
+        U2in = U2;
+    } else if (D != nullptr) {
         // R2: U2[a][al][i][q] = sum_{(j,be)} D[al][i][j][be] U1[a][j][be][q]
         ContractDesc d = cdesc(Rl * n, pr, n * Rr, rl);
         d.ab = idx1(0);
@@ -312,6 +494,10 @@ inline char* adv(const void* p, int64_t elems, Prec pr) {
 
 namespace {
 
+const uint8_t* blk_of(const SketchOperands& o, int mu) {
+    return !o.D.empty() && !o.blk.empty() ? o.blk[mu] : nullptr;
+}
+
 // Two-stream form of the STTA sketch: the side stream computes the right
 // environments F_b (right-to-left) and then Omega_b = E_b F_b; the calling
 // stream computes the left environments E_mu with their T2 intermediates
@@ -353,14 +539,15 @@ void stta_sketch_two_streams(const SketchOperands& o, const std::vector<int>& r,
     TTSG_HIP(hipStreamWaitEvent(sd.st, sd.in, 0));
     set_one(p, F[d], sd.st);
     for (int mu = d - 1; mu >= 1; --mu) {
-        LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rx[mu], o.rx[mu + 1]};
+        LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rx[mu], o.rx[mu + 1], blk_of(o, mu)};
         right_step(p, s, F[mu + 1], x[mu], op ? o.D[mu] : nullptr, o.X[mu - 1], U1, U2, F[mu], sd.st, &ar2);
     }
     TTSG_HIP(hipEventRecord(sd.right, sd.st));
     // main: left sweep, keeping T2 and E of every mode
     set_one(p, E[0], st);
     for (int mu = 0; mu < d; ++mu) {
-        LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rho[mu], mu + 1 < d ? o.rho[mu + 1] : 1};
+        LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rho[mu], mu + 1 < d ? o.rho[mu + 1] : 1,
+                   blk_of(o, mu)};
         // without an operator the first stage's output is the intermediate
         left_step(p, s, E[mu], x[mu], op ? o.D[mu] : nullptr, nullptr, op ? T1 : T2[mu], op ? T2[mu] : nullptr,
                   nullptr, st, &ar);
@@ -428,7 +615,7 @@ void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::
     for (int b = 1; b <= d; ++b) F[b] = ar.get<char>((int64_t)r[b] * Rk(b) * o.rx[b] * es);
     set_one(p, F[d], st);
     for (int mu = d - 1; mu >= 1; --mu) {
-        LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rx[mu], o.rx[mu + 1]};
+        LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rx[mu], o.rx[mu + 1], blk_of(o, mu)};
         right_step(p, s, F[mu + 1], x[mu], op ? o.D[mu] : nullptr, o.X[mu - 1], U1, U2, F[mu], st, &ar);
     }
     // left sweep with Psi and Omega
@@ -436,7 +623,8 @@ void stta_sketch(const SketchOperands& o, const std::vector<int>& r, const std::
     void* E = Ea;
     void* En = Eb;
     for (int mu = 0; mu < d; ++mu) {
-        LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rho[mu], mu + 1 < d ? o.rho[mu + 1] : 1};
+        LeftDims s{r[mu], n[mu], r[mu + 1], Rk(mu), Rk(mu + 1), o.rho[mu], mu + 1 < d ? o.rho[mu + 1] : 1,
+                   blk_of(o, mu)};
         const bool last = (mu == d - 1);
         left_step(p, s, E, x[mu], op ? o.D[mu] : nullptr, nullptr, T1, T2, nullptr, st, &ar);
         const void* T2r = op ? T2 : T1;
@@ -494,7 +682,8 @@ void kr_sketch_run(Prec p, int d, const int* n, int s, const std::vector<int>& R
 
 void inner_run(Prec p, int d, const int* n, const std::vector<int>& R, const std::vector<const void*>& D,
                const std::vector<int>& rx_, const std::vector<const void*>& x, const std::vector<int>& rz,
-               const std::vector<const void*>& z, double* out_dev, Arena& ar, hipStream_t st) {
+               const std::vector<const void*>& z, double* out_dev, Arena& ar, hipStream_t st,
+               const std::vector<const uint8_t*>& blk) {
     const size_t es = elem_size(p);
     const size_t mark = ar.mark();
     const bool op = !D.empty();
@@ -513,7 +702,8 @@ void inner_run(Prec p, int d, const int* n, const std::vector<int>& R, const std
     void* E = Ea;
     void* En = Eb;
     for (int mu = 0; mu < d; ++mu) {
-        LeftDims s{rx_[mu], n[mu], rx_[mu + 1], Rk(mu), Rk(mu + 1), rz[mu], rz[mu + 1]};
+        LeftDims s{rx_[mu], n[mu], rx_[mu + 1], Rk(mu), Rk(mu + 1), rz[mu], rz[mu + 1],
+                   op && !blk.empty() ? blk[mu] : nullptr};
         left_step(p, s, E, x[mu], op ? D[mu] : nullptr, z[mu], T1, T2, En, st, &ar);
         std::swap(E, En);
     }

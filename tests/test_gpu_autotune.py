@@ -1,6 +1,6 @@
 """GPU tests of the contraction tile variants and their autotuner.
 
-All four tile variants sum every output in the same order (the split-K
+All seven tile variants sum every output in the same order (the split-K
 decision does not depend on the tile), so a solve must give bit-identical
 results whether the tuner ran, which variants it picked, or none was tuned."""
 import numpy as np
@@ -8,6 +8,7 @@ import pytest
 import torch
 
 import synthetic as syn
+from oracle import operators as oops
 from oracle import sketch as osk
 from oracle import tt as ott
 
@@ -51,36 +52,41 @@ def test_tuned_solve_is_bit_identical(precision, tmp_path):
     ttsg.autotune_clear()
 
 
-def test_forced_variants_match_oracle(tmp_path):
-    """Force each tile variant for the shape classes of a Khatri-Rao sketch (by
-    tuning on it, then overwriting every entry with one variant) and compare
-    with the oracle's sketch; all variants must agree bit for bit."""
+@pytest.mark.parametrize("with_op,precision,tol", [(False, 0, 1e-12), (True, 0, 1e-12), (True, 1, 2e-5)])
+def test_forced_variants_match_oracle(tmp_path, with_op, precision, tol):
+    """Force each tile variant (32 x 32 up to 128 x 128) for the shape classes
+    of a Khatri-Rao sketch (by tuning on it, then overwriting every entry with
+    one variant) and compare with the oracle's sketch; all variants must agree
+    bit for bit.  With the operator (rank 3, so the Khatri-Rao operand is formed
+    inside the contraction's staging) in FP64 and FP32."""
     ttsg = _ttsg()
     n, d, s = 21, 4, 90
     rng = np.random.default_rng(8)
     x = syn.gaussian_tt(rng, [n] * d, [1, 7, 33, 5, 1])
     S = syn.kr_factors(rng, s, [n] * d)
+    terms = [[syn.laplacian_1d(n)] * d, [np.diag(rng.standard_normal(n)) for _ in range(d)]]
     xs, Ss = ttsg.to_device(x, DEV), ttsg.to_device(S, DEV)
+    As = ttsg.kron_sum_operator(terms, DEV) if with_op else None
     ttsg.autotune_clear()
     ttsg.autotune(True)
     try:
-        ttsg.kr_sketch(Ss, xs)
+        ttsg.kr_sketch(Ss, xs, A=As, precision=precision)
     finally:
         ttsg.autotune(False)
     path = tmp_path / "t.txt"
     ttsg.autotune_save(str(path))
     keys = [l.split()[:8] for l in path.read_text().splitlines() if not l.startswith("#")]
     assert keys
-    ref = osk.kr_sketch(S, x)
+    ref = osk.kr_sketch(S, ott.matvec(oops.tt_kron_sum(terms), x) if with_op else x)
     outs = []
-    for v in range(4):
+    for v in range(7):
         forced = tmp_path / f"v{v}.txt"
         forced.write_text("".join(" ".join(k + [str(v)]) + "\n" for k in keys))
         ttsg.autotune_clear()
-        ttsg.autotune_load(str(forced))
-        w = ttsg.kr_sketch(Ss, xs).cpu().numpy()
-        assert np.linalg.norm(w - ref) <= 1e-12 * np.linalg.norm(ref)
+        assert ttsg.autotune_load(str(forced)) == len(keys)
+        w = ttsg.kr_sketch(Ss, xs, A=As, precision=precision).double().cpu().numpy()
+        assert np.linalg.norm(w - ref) <= tol * np.linalg.norm(ref), v
         outs.append(w)
     ttsg.autotune_clear()
-    for w in outs[1:]:
-        assert np.array_equal(w, outs[0])
+    for v, w in enumerate(outs[1:], 1):
+        assert np.array_equal(w, outs[0]), v
