@@ -320,7 +320,8 @@ static size_t round_rand_ws(int32_t d, const int32_t* n, const int32_t* r, const
         rmax = std::max(rmax, (size_t)std::max(rho[mu], rx[mu]));
     }
     const size_t need = stta_ws(d, n, rho, rx, nullptr, r, p) + sk * 8 + (8 * core + 12 * rmax * rmax) * 8 +
-                        (size_t)d * 16 * rmax * rmax * 8 + (4 << 20) + ttsg::tt_svd_extra_bytes(d, n, rx);
+                        (size_t)d * 16 * rmax * rmax * 8 + (4 << 20) + ttsg::tt_svd_extra_bytes(d, n, rx) +
+                        (size_t)d * ttsg::jacobi_big_log_bytes((int)rmax);
     return need + kSplitSlack;
 }
 
@@ -761,7 +762,7 @@ int ttsg_precond_round(int32_t d, const int32_t* n, int32_t zeta, const double* 
         for (int mu = 0; mu < d; ++mu) zc += (size_t)r[mu] * n[mu] * r[mu + 1] + 64;
         const size_t need = stta_ws(d, n, rho, rx, nullptr, r, ttsg::Prec::F64) + 2 * sk * 8 + ee * 8 + zc * 8 +
                             (8 * core + 12 * rmax * rmax) * 8 + (size_t)d * 16 * rmax * rmax * 8 + (4 << 20) +
-                            ttsg::tt_svd_extra_bytes(d, n, rx);
+                            ttsg::tt_svd_extra_bytes(d, n, rx) + (size_t)d * ttsg::jacobi_big_log_bytes((int)rmax);
         ttsg::Workspace W(ws, ws_bytes, need + kSplitSlack, S(stream));
         ttsg::Arena& ar = W.arena;
         std::vector<double*> Eb(d), z(d);

@@ -35,6 +35,12 @@ struct JacobiBatch {
     double* A[32];
     double* V[32];
     double* sig[32];
+    // 128-column kernel with an accumulator: the rotation log (the tangent of
+    // every rotation, 0 for none, per sweep, round and pair) and meta =
+    // [active-column permutation (c), output rank of each column (c), active
+    // columns, sweeps run], from which k_jacobi_apply_v forms V
+    double* rot[32];
+    int* meta[32];
 };
 
 // Wave leaders add their partial into an LDS scalar (thread 0 first zeroes it
@@ -309,15 +315,17 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
 // One-sided Jacobi for 64 < c <= 128 columns and up to 16 JR rows: 64 lane
 // groups of 16 (1024 threads), one column pair per group and round.  The m x c
 // matrix fills the LDS (149 x 128 doubles = 149 KB at the largest shape used),
-// so the rotation accumulator, when one is asked for (ACC), is kept in global
-// memory: a group loads its pair's two accumulator columns at the start of the
-// round (their latency overlaps the dot products) and stores them rotated
-// before the round's barrier.  Without ACC only the rotated matrix B = A V and
-// the singular values are produced (callers that need a factor of V form it
-// from B).  Norm reductions are fixed-order, so results do not depend on
-// wavefront timing.
+// so there is no room for the rotation accumulator.  When one is asked for
+// (ACC), lane 0 of every group logs the tangent of its round's rotation (0 for
+// none) and the accumulator is formed afterwards by k_jacobi_apply_v, which
+// replays the log on the rows of V in parallel over many workgroups (the rows
+// of V are independent).  Without ACC only the rotated matrix B = A V and the
+// singular values are produced (callers that need a factor of V form it from
+// B).  Norm reductions are fixed-order, so results do not depend on wavefront
+// timing.
 constexpr int JTB = 1024;
 constexpr int JB_CMAX = 128;
+constexpr int kJacobiBigSweeps = 30;   // sweep limit of the 128-column kernel
 
 template <int JR, bool ACC>
 __global__ __launch_bounds__(JTB) void k_jacobi_big(JacobiBatch jb, int maxsweeps, DevSlot* slot) {
@@ -391,14 +399,14 @@ __global__ __launch_bounds__(JTB) void k_jacobi_big(JacobiBatch jb, int maxsweep
             A[j * ldm + i] = Ag[(int64_t)s_perm[j] * lda + i];
         }
     }
+    double* rotg = ACC ? jb.rot[bi] : nullptr;
     if (ACC) {
-        for (int e = tid; e < c * c; e += JTB) {
-            const int j = e / c, i = e - j * c;
-            Vg[(int64_t)j * c + i] = (i == s_perm[j]) ? 1.0 : 0.0;
-        }
+        int* meta = jb.meta[bi];
+        for (int l = tid; l < c; l += JTB) meta[l] = s_perm[l];
+        if (tid == 0) meta[2 * c] = c_act;
     }
+    (void)Vg;
     __syncthreads();
-    constexpr int VR = JB_CMAX / JG;   // accumulator rows per lane
     const int cp = c_act + (c_act & 1);
     const int npair = cp / 2;
     const int nround = cp - 1;
@@ -408,21 +416,11 @@ __global__ __launch_bounds__(JTB) void k_jacobi_big(JacobiBatch jb, int maxsweep
         sweeps_done = sweep + 1;
         int p = grp == 0 ? cp - 1 : grp, q = grp == 0 ? 0 : cp - 1 - grp;
         for (int r = 0; r < nround; ++r) {
+            double tlog = 0.0;   // tangent of this group's rotation, 0 for none
             if (grp < npair && p < c_act && q < c_act) {
                 double* ap = A + p * ldm;
                 double* aq = A + q * ldm;
-                double* vp = Vg + (int64_t)p * c;
-                double* vq = Vg + (int64_t)q * c;
-                double xp[JR], xq[JR], yp[VR], yq[VR];
-                if (ACC) {
-#pragma unroll
-                    for (int u = 0; u < VR; ++u) {
-                        const int i = lt + u * JG;
-                        const int ic = i < c ? i : 0;
-                        yp[u] = vp[ic];
-                        yq[u] = vq[ic];
-                    }
-                }
+                double xp[JR], xq[JR];
                 double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
                 for (int t = 0; t < JR; ++t) {
@@ -461,20 +459,12 @@ __global__ __launch_bounds__(JTB) void k_jacobi_big(JacobiBatch jb, int maxsweep
                                 aq[i] = sn * xp[u] + cs * xq[u];
                             }
                         }
-                        if (ACC) {
-#pragma unroll
-                            for (int u = 0; u < VR; ++u) {
-                                const int i = lt + u * JG;
-                                if (i < c) {
-                                    vp[i] = cs * yp[u] - sn * yq[u];
-                                    vq[i] = sn * yp[u] + cs * yq[u];
-                                }
-                            }
-                        }
+                        tlog = t;
                         rotated = 1;
                     }
                 }
             }
+            if (ACC && grp < npair && lt == 0) rotg[((int64_t)sweep * nround + r) * npair + grp] = tlog;
             if (grp == 0) {
                 q += 1;
             } else {
@@ -519,20 +509,71 @@ __global__ __launch_bounds__(JTB) void k_jacobi_big(JacobiBatch jb, int maxsweep
         Ag[(int64_t)s_rank[j] * lda + i] = A[j * ldm + i];
     }
     if (ACC) {
-        // sort the accumulator's columns through the LDS (free again: m >= c)
-        __syncthreads();
-        const int ldv = c | 1;
-        for (int e = tid; e < c * c; e += JTB) {
-            const int j = e / c, i = e - j * c;
-            A[j * ldv + i] = Vg[(int64_t)j * c + i];
-        }
-        __syncthreads();
-        for (int e = tid; e < c * c; e += JTB) {
-            const int j = e / c, i = e - j * c;
-            Vg[(int64_t)s_rank[j] * c + i] = A[j * ldv + i];
-        }
+        int* meta = jb.meta[bi];
+        for (int l = tid; l < c; l += JTB) meta[c + l] = s_rank[l];
+        if (tid == 0) meta[2 * c + 1] = sweeps_done;
     }
     slot_end(slot, (unsigned long long)sweeps_done);
+}
+
+// The accumulator V of k_jacobi_big from its rotation log: V starts as the
+// active-column permutation, every logged rotation of the circle method is
+// applied to the columns (p, q) it rotated, in sweep and round order, and the
+// columns are written in the output order.  Rows of V are independent, so a
+// workgroup takes JAV_ROWS rows (one lane per row and pair: 16 x 64 = 1024
+// lanes), with one barrier per round; the round's tangents are read one round
+// ahead.  The pair of group g in round r is the one k_jacobi_big used:
+// (cp - 1, r) for g = 0, ((g + r) mod (cp - 1), (cp - 1 - g + r) mod (cp - 1))
+// otherwise, cp the active column count rounded up to even.
+constexpr int JAV_ROWS = 16;
+__global__ __launch_bounds__(JTB) void k_jacobi_apply_v(JacobiBatch jb) {
+    __shared__ double v[JAV_ROWS][JB_CMAX + 1];
+    const int bi = blockIdx.y;
+    const int c = jb.c[bi];
+    const int row0 = blockIdx.x * JAV_ROWS;
+    if (row0 >= c) return;
+    const int* meta = jb.meta[bi];
+    const double* rot = jb.rot[bi];
+    double* Vg = jb.V[bi];
+    const int c_act = meta[2 * c], sweeps = meta[2 * c + 1];
+    const int tid = threadIdx.x;
+    const int rr = tid / 64, g = tid - (tid / 64) * 64;
+    for (int e = tid; e < JAV_ROWS * c; e += JTB) {
+        const int k = e / c, j = e - (e / c) * c;
+        v[k][j] = (row0 + k == meta[j]) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int cp = c_act + (c_act & 1);
+    const int npair = cp / 2, nround = cp - 1;
+    const int64_t total = (int64_t)sweeps * nround;
+    const bool mine = g < npair && cp > 1;
+    double tn = (mine && total > 0) ? rot[g] : 0.0;
+    for (int64_t e = 0; e < total; ++e) {
+        const double t = tn;
+        if (mine && e + 1 < total) tn = rot[(e + 1) * npair + g];
+        const int r = (int)(e % nround);
+        int p, q;
+        if (g == 0) {
+            p = cp - 1;
+            q = r;
+        } else {
+            p = (g + r) % (cp - 1);
+            q = (cp - 1 - g + r) % (cp - 1);
+        }
+        if (mine && t != 0.0) {
+            const double cs = rsq_nr(fma(t, t, 1.0));
+            const double sn = cs * t;
+            const double yp = v[rr][p], yq = v[rr][q];
+            v[rr][p] = cs * yp - sn * yq;
+            v[rr][q] = sn * yp + cs * yq;
+        }
+        __syncthreads();
+    }
+    const int* rank = meta + c;
+    for (int e = tid; e < JAV_ROWS * c; e += JTB) {
+        const int k = e / c, j = e - (e / c) * c;
+        if (row0 + k < c) Vg[(int64_t)rank[j] * c + row0 + k] = v[k][j];
+    }
 }
 
 // Leaf i of a TSQR level: rows [r0, r1) of the column-major m x c matrix A.
@@ -903,13 +944,21 @@ bool jacobi_big_fits(int m, int c) {
     return m >= c && c <= JB_CMAX && m <= JG * 10 && jacobi_big_lds_bytes(m, c) <= 152 * 1024 + 1024;
 }
 
-void svd_jacobi_big(const std::vector<JacobiJob>& jobs, bool accumulate, hipStream_t st) {
+size_t jacobi_big_log_bytes(int c) {
+    // tangents of kJacobiBigSweeps sweeps of at most c rounds of (c + 1) / 2 pairs, and the meta block
+    return ((size_t)kJacobiBigSweeps * c * ((c + 1) / 2) * sizeof(double) + 255) / 256 * 256 +
+           ((size_t)(2 * c + 2) * sizeof(int) + 255) / 256 * 256;
+}
+
+void svd_jacobi_big(const std::vector<JacobiJob>& jobs, bool accumulate, hipStream_t st, Arena* ar) {
+    TTSG_CHECK(!accumulate || ar != nullptr, TTSG_ERR_ARG, "jacobi: the accumulated form needs scratch");
     size_t i = 0;
     while (i < jobs.size()) {
         JacobiBatch jb{};
         size_t lds = 0;
         int cnt = 0, mmax = 0, cmax = 0;
         double flops = 0.0;
+        const size_t mark = ar != nullptr ? ar->mark() : 0;
         for (; i < jobs.size() && cnt < 32; ++i, ++cnt) {
             const JacobiJob& j = jobs[i];
             TTSG_CHECK(jacobi_big_fits(j.m, j.c), TTSG_ERR_ARG, "jacobi job does not fit the 128-column kernel");
@@ -923,6 +972,10 @@ void svd_jacobi_big(const std::vector<JacobiJob>& jobs, bool accumulate, hipStre
             jb.tol[cnt] = j.tol > 0.0 ? j.tol : 4.0 * j.m * 2.220446049250313e-16;
             jb.drop_abs2[cnt] = j.drop_abs2;
             jb.drop_rel2[cnt] = j.drop_rel2;
+            if (accumulate) {
+                jb.rot[cnt] = ar->get<double>((size_t)kJacobiBigSweeps * j.c * ((j.c + 1) / 2));
+                jb.meta[cnt] = ar->get<int>(2 * j.c + 2);
+            }
             lds = std::max(lds, jacobi_big_lds_bytes(j.m, j.c));
             mmax = std::max(mmax, j.m);
             cmax = std::max(cmax, j.c);
@@ -940,10 +993,12 @@ void svd_jacobi_big(const std::vector<JacobiJob>& jobs, bool accumulate, hipStre
         if (accumulate) {
             if (r8) {
                 allow_lds(reinterpret_cast<const void*>(&k_jacobi_big<8, true>), lds, g_lds_big8v);
-                hipLaunchKernelGGL((k_jacobi_big<8, true>), dim3(cnt), dim3(JTB), lds, st, jb, 30, scope.slot());
+                hipLaunchKernelGGL((k_jacobi_big<8, true>), dim3(cnt), dim3(JTB), lds, st, jb, kJacobiBigSweeps,
+                                   scope.slot());
             } else {
                 allow_lds(reinterpret_cast<const void*>(&k_jacobi_big<10, true>), lds, g_lds_big10v);
-                hipLaunchKernelGGL((k_jacobi_big<10, true>), dim3(cnt), dim3(JTB), lds, st, jb, 30, scope.slot());
+                hipLaunchKernelGGL((k_jacobi_big<10, true>), dim3(cnt), dim3(JTB), lds, st, jb, kJacobiBigSweeps,
+                                   scope.slot());
             }
         } else {
             if (r8) {
@@ -955,6 +1010,11 @@ void svd_jacobi_big(const std::vector<JacobiJob>& jobs, bool accumulate, hipStre
             }
         }
         TTSG_HIP(hipGetLastError());
+        if (accumulate) {
+            hipLaunchKernelGGL(k_jacobi_apply_v, dim3((cmax + JAV_ROWS - 1) / JAV_ROWS, cnt), dim3(JTB), 0, st, jb);
+            TTSG_HIP(hipGetLastError());
+            ar->release(mark);
+        }
     }
 }
 

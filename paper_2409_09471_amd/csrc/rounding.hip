@@ -595,7 +595,7 @@ void stta_recover(int d, const int* n, const std::vector<int>& rho, const std::v
                 svd_jacobi(1, rx[b], rx[b], Rt[b], rx[b], 0, Wb[b], rx[b], 0, Sb[b], 0, st);
         }
         if (!jobs.empty()) svd_jacobi_batched(jobs, st);
-        if (!big_jobs.empty()) svd_jacobi_big(big_jobs, true, st);
+        if (!big_jobs.empty()) svd_jacobi_big(big_jobs, true, st, &ar);
     }
     for (int mu = 0; mu < d; ++mu) maxT = std::max<int64_t>(maxT, (int64_t)rx[mu] * n[mu] * rx[mu + 1]);
     for (int b = 1; b <= d - 1; ++b) maxT = std::max<int64_t>(maxT, (int64_t)rho[b] * rx[b]);

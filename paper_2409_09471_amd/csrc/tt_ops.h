@@ -146,7 +146,10 @@ void svd_jacobi_batched(const std::vector<JacobiJob>& jobs, hipStream_t st);
 // becomes B = A V with columns sorted by norm, sig the sorted singular values;
 // V (c x c, ld c, sorted like B) only when `accumulate` (else V is ignored).
 bool jacobi_big_fits(int m, int c);
-void svd_jacobi_big(const std::vector<JacobiJob>& jobs, bool accumulate, hipStream_t st);
+// With accumulate, V comes from a rotation log kept in `ar` (released on
+// return; jacobi_big_log_bytes(c) per job of c columns, batches of 32 jobs).
+void svd_jacobi_big(const std::vector<JacobiJob>& jobs, bool accumulate, hipStream_t st, Arena* ar = nullptr);
+size_t jacobi_big_log_bytes(int c);
 
 // Householder QR of several small column-major matrices in one launch (one
 // workgroup each, the matrix and Q in LDS): Q (m x c, column-major, ld m) and
