@@ -153,8 +153,8 @@ struct SlabLoader {
 
 // A operand of a Khatri-Rao step formed while it is staged (k-fast layout:
 // thread tid owns k = k0 + tid % BK and rows tid / BK + (256 / BK) t): row m =
-// (j, be), column k = (a, i), value sum_al P[j][al][a] SA[j][al][i][be], the RL
-// terms added in order.  fetch() only issues the 2 RL loads per element (they
+// (j, be), column k = (a, i), value sum_al P[j][al][a] SA[j][al][be][i], the RL
+// terms added in order (consecutive k read consecutive i of SA).  fetch() only issues the 2 RL loads per element (they
 // complete while the matrix cores work on the current slab); commit() forms the
 // sums as it writes the LDS slab.  The s R r n intermediate is never stored.
 template <typename T, int ROWS, int RL>
@@ -166,7 +166,7 @@ struct KrLoader {
     const in_t* P;
     const in_t* SA;
     int rl, n, Rr, kend;
-    int64_t pb[PER], sb[PER];   // per row: P offset of (j, 0, 0), SA offset of (j, 0, 0, be); pb < 0: outside
+    int64_t pb[PER], sb[PER];   // per row: P offset of (j, 0, 0), SA offset of (j, 0, be, 0); pb < 0: outside
     in_t pv[PER][RL], sv[PER][RL];
 
     __device__ __forceinline__ void init(const ContractDesc& d, int row0, int kend_) {
@@ -184,7 +184,7 @@ struct KrLoader {
                 const int64_t j = gr / Rr;
                 const int be = gr - (int)(j * Rr);
                 pb[t] = j * RL * rl;
-                sb[t] = j * RL * n * Rr + be;
+                sb[t] = j * RL * n * Rr + (int64_t)be * n;
             } else {
                 pb[t] = -1;
                 sb[t] = 0;
@@ -203,7 +203,7 @@ struct KrLoader {
 #pragma unroll
             for (int al = 0; al < RL; ++al) {
                 pv[t][al] = on ? P[pb[t] + a + (int64_t)al * rl] : in_t(0);
-                sv[t][al] = on ? SA[sb[t] + (int64_t)i * Rr + al * nR] : in_t(0);
+                sv[t][al] = on ? SA[sb[t] + i + al * nR] : in_t(0);
             }
         }
     }

@@ -355,17 +355,22 @@ void omega_step(Prec p, int pl, int Rr, int rr, int qr, const void* E, const voi
 
 // ---------------------------------------------------------------------------
 // Khatri-Rao sketch steps.  P_mu[j][al][a] (s x R x r) is the row vector of
-// sketch row j after mu cores; SA_mu[j][al][i'][be] = sum_i S_mu[j,i] D_mu[al,i,i',be]
+// sketch row j after mu cores; SA_mu[j][al][be][i'] = sum_i S_mu[j,i] D_mu[al,i,i',be]
 // (or S_mu itself when there is no operator, R = 1).
 // ---------------------------------------------------------------------------
 void kr_precompute(Prec p, int s, int n, int Rl, int Rr, const void* S, const void* D, void* SA, hipStream_t st) {
-    ContractDesc d = cdesc(s, Rl * n * Rr, n);
+    // SA[j][al][be][i'] = sum_i S[j][i] D[al][i][i'][be], batched over al; i'
+    // runs fastest so that a Khatri-Rao step reads it along its reduction index
+    ContractDesc d = cdesc(s, n * Rr, n, Rl);
+    d.ab = idx1(0);
     d.am = idx1(n);
     d.ak = idx1(1);
+    d.bb = idx1((int64_t)n * n * Rr);
     d.bk = idx1((int64_t)n * Rr);
-    d.bn = idx2(n * Rr, 1, (int64_t)n * n * Rr);
+    d.bn = idx1(1);
+    d.cb = idx1((int64_t)Rr * n);
     d.cm = idx1((int64_t)Rl * n * Rr);
-    d.cn = idx1(1);
+    d.cn = idx2(Rr, n, 1);
     contract(p, d, S, D, SA, st);
 }
 
@@ -385,7 +390,7 @@ __global__ void k_kr1(int64_t total, int rl, int n, int Rl, int Rr, const T* __r
         const int a = (int)(rem / n);
         const int i = (int)(rem - (int64_t)a * n);
         const T* pj = P + j * Rl * rl + a;
-        const T* sj = SA + ((j * Rl) * n + i) * Rr + be;
+        const T* sj = SA + (j * Rl) * n * Rr + (int64_t)be * n + i;
         T acc = 0;
         for (int al = 0; al < Rl; ++al) acc += pj[(int64_t)al * rl] * sj[(int64_t)al * n * Rr];
         X[e] = acc;
@@ -396,7 +401,7 @@ __global__ void k_kr1(int64_t total, int rl, int n, int Rl, int Rr, const T* __r
 void kr_step(Prec p, int s, int rl, int n, int rr, int Rl, int Rr, const void* P, const void* SA, const void* C,
              void* Xbuf, void* Pout, hipStream_t st, Arena* ar) {
     // P'[(j,be)][b] = sum_{(a,i')} X[(j,be)][(a,i')] C[(a,i')][b] with
-    // X[j][be][a][i'] = sum_al P[j][al][a] SA[j][al][i'][be]: for operator ranks
+    // X[j][be][a][i'] = sum_al P[j][al][a] SA[j][al][be][i']: for operator ranks
     // up to 3, X is formed inside the contraction's operand staging and never
     // stored (the s R r n intermediate would be written and read back)
     if (Rl <= 3 && p != Prec::BF16) {
@@ -414,7 +419,7 @@ void kr_step(Prec p, int s, int rl, int n, int rr, int Rl, int Rr, const void* P
         contract(p, d, P, C, Pout, st, ar);
         return;
     }
-    // KR1: X[j][be][a][i'] = sum_al P[j][al][a] SA[j][al][i'][be]
+    // KR1: X[j][be][a][i'] = sum_al P[j][al][a] SA[j][al][be][i']
     if (Rl <= 4 && p != Prec::BF16) {
         const int64_t total = (int64_t)s * Rr * rl * n;
         const int blocks = (int)std::min<int64_t>((total + 255) / 256, 1 << 16);
@@ -433,7 +438,7 @@ void kr_step(Prec p, int s, int rl, int n, int rr, int Rl, int Rr, const void* P
         d.ak = idx1(rl);
         d.bb = idx1((int64_t)Rl * n * Rr);
         d.bk = idx1((int64_t)n * Rr);
-        d.bn = idx2(n, Rr, 1);
+        d.bn = idx1(1);
         d.cb = idx1((int64_t)Rr * rl * n);
         d.cm = idx1(n);
         d.cn = idx2(n, 1, (int64_t)rl * n);

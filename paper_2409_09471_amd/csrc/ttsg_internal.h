@@ -125,7 +125,7 @@ struct ContractDesc {
     int32_t c_f64;   // F32/BF16 arithmetic writing a float64 C (strides in its elements)
     // Khatri-Rao step (kr_P != nullptr; float64/float32, operator rank kr_Rl of
     // 1..3): the A operand is not read but formed while it is staged,
-    // A[m][k] = sum_al P[(j Rl + al) rl + a] SA[((j Rl + al) n + i) Rr + be]
+    // A[m][k] = sum_al P[(j Rl + al) rl + a] SA[((j Rl + al) Rr + be) n + i]
     // with m = j Rr + be and k = a n + i (the A pointer and the am/ak/ab
     // strides are then unused).
     const void* kr_P;
