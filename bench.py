@@ -68,6 +68,8 @@ def parse():
                     help="skip the mixed / FP64 solves of the d = 10 workload")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default contraction tiles (no tuned table, no tuning)")
+    ap.add_argument("--no-rounding", action="store_true",
+                    help="skip the standalone rounding GFLOP/s legs (profiling runs of the solve alone)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer with a plain device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -390,8 +392,9 @@ def main():
     if wl == "c5":
         out["precision_note"] = ("d=20 runs FP64: float32 sketches of A P^-1 v_k (a small difference after "
                                  "preconditioning) lose the new direction in the recovery; see precision_legs")
-    out["rounding"] = {"f64": rounding_gflops(w, t, ttsg.PREC_F64),
-                       "f32": rounding_gflops(w, t, ttsg.PREC_MIXED)}
+    if not args.no_rounding:
+        out["rounding"] = {"f64": rounding_gflops(w, t, ttsg.PREC_F64),
+                           "f32": rounding_gflops(w, t, ttsg.PREC_MIXED)}
     if not args.no_cpu:
         if wl == "c5":
             out["cpu_baseline"] = cpu_baseline_first_iteration(w, last.iterations)

@@ -90,3 +90,48 @@ def test_forced_variants_match_oracle(tmp_path, with_op, precision, tol):
     ttsg.autotune_clear()
     for v, w in enumerate(outs[1:], 1):
         assert np.array_equal(w, outs[0]), v
+
+
+def test_forced_variants_plain_contractions_agree(tmp_path):
+    """Every tile variant forced on the plain contractions of an STTA sketch of
+    A x (environment steps, Psi/Omega products, split-K reductions): the
+    sketches must equal the oracle's and each other bit for bit."""
+    ttsg = _ttsg()
+    n, d = 17, 4
+    rng = np.random.default_rng(9)
+    x = syn.gaussian_tt(rng, [n] * d, [1, 9, 40, 6, 1])
+    terms = [[syn.laplacian_1d(n)] * d, [np.diag(rng.standard_normal(n)) for _ in range(d)]]
+    rx, rho = syn.stta_ranks([n] * d, 40, 20)
+    X = syn.tt_drm(rng, [n] * d, rx, 1, d)
+    Y = syn.tt_drm(rng, [n] * d, rho, 0, d - 1)
+    xs, Xs, Ys = ttsg.to_device(x, DEV), ttsg.to_device(X, DEV), ttsg.to_device(Y, DEV)
+    As = ttsg.kron_sum_operator(terms, DEV)
+    ttsg.autotune_clear()
+    ttsg.autotune(True)
+    try:
+        ttsg.stta_sketch(xs, Xs, Ys, rx, rho, A=As)
+    finally:
+        ttsg.autotune(False)
+    path = tmp_path / "t.txt"
+    ttsg.autotune_save(str(path))
+    keys = [l.split()[:8] for l in path.read_text().splitlines() if not l.startswith("#")]
+    assert keys
+    Ax = ott.matvec(oops.tt_kron_sum(terms), x)
+    Psi_o, Om_o = osk.stta_sketch(Ax, X, Y)
+    outs = []
+    for v in range(7):
+        forced = tmp_path / f"p{v}.txt"
+        forced.write_text("".join(" ".join(k + [str(v)]) + "\n" for k in keys))
+        ttsg.autotune_clear()
+        assert ttsg.autotune_load(str(forced)) == len(keys)
+        Psi, Om = ttsg.stta_sketch(xs, Xs, Ys, rx, rho, A=As)
+        Psi = [p.cpu().numpy() for p in Psi]
+        Om = [o.cpu().numpy() for o in Om]
+        for a, b in zip(Psi, Psi_o):
+            assert np.linalg.norm(a - b.reshape(a.shape)) <= 1e-12 * np.linalg.norm(b), v
+        for a, b in zip(Om, Om_o):
+            assert np.linalg.norm(a - b.reshape(a.shape)) <= 1e-12 * np.linalg.norm(b), v
+        outs.append(Psi + Om)
+    ttsg.autotune_clear()
+    for v, o in enumerate(outs[1:], 1):
+        assert all(np.array_equal(a, b) for a, b in zip(o, outs[0])), v
