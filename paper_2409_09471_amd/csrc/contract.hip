@@ -37,6 +37,7 @@ typedef short s8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
 constexpr int BM64 = 64;   // tile edge that the split-K decision is based on
+constexpr uint64_t kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
 
 // float32 -> bfloat16 bits, round to nearest even (NaN stays a quiet NaN).
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
@@ -246,13 +247,30 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
     __shared__ lds_t Bs[BK][TN + 1];
 
     slot_begin(slot);
-    const int zz = batch0 + blockIdx.z;
+    // XCD-aware tile order: workgroups are handed to the 8 XCDs round-robin in
+    // launch order, so consecutive tiles (which share operand rows and
+    // columns) would land on 8 different L2s.  Tile t of the launch is instead
+    // given to the workgroup that makes each XCD process a contiguous run of
+    // tiles (x fastest, then y, then batch/split).
+    int tx, ty, tz;
+    {
+        const uint64_t gx = gridDim.x, gy = gridDim.y;
+        const uint64_t total = gx * gy * gridDim.z;
+        const uint64_t hw = blockIdx.x + gx * (blockIdx.y + gy * (uint64_t)blockIdx.z);
+        const uint64_t q = total / kXcds, r = total % kXcds;
+        const uint64_t xcd = hw % kXcds, pos = hw / kXcds;
+        const uint64_t t = xcd * q + (xcd < r ? xcd : r) + pos;
+        tx = (int)(t % gx);
+        ty = (int)((t / gx) % gy);
+        tz = (int)(t / (gx * gy));
+    }
+    const int zz = batch0 + tz;
     const int bidx = zz / splits;
     const int split = zz - bidx * splits;
     const int kbeg = split * kchunk;
     const int kend = min(d.K, kbeg + kchunk);
-    const int m0 = blockIdx.y * TM;
-    const int n0 = blockIdx.x * TN;
+    const int m0 = ty * TM;
+    const int n0 = tx * TN;
     const in_t* Ab = KRL > 0 ? A : A + idx_off(d.ab, bidx);
     const in_t* Bb = B + idx_off(d.bb, bidx);
     out_t* Cb = C + idx_off(d.cb, bidx);
