@@ -254,39 +254,6 @@ int ttsg_sgmres_solve(int32_t d, const int32_t* n,
                       ttsg_sgmres_info* info,
                       void* ws, size_t ws_bytes, ttsg_stream_t stream);
 
-/* Many independent systems (Alg. 4 on each), solved concurrently on one GPU.
- * Each entry carries exactly the arguments of ttsg_sgmres_solve (same meaning,
- * layout and ownership); `status` receives that system's return value.
- * Systems are taken longest-first by `concurrency` host workers (<= 0: 8),
- * each driving its own non-blocking stream of default priority, so the
- * kernels of different systems overlap on the GPU while each system's host
- * rank decisions proceed independently.  All worker streams first wait for
- * the work queued on `stream`.  Returns 0 when every system returned >= 0,
- * else the first negative code (ttsg_last_error names the system).  Returns
- * after every system has finished. */
-typedef struct {
-    int32_t d;
-    const int32_t* n;
-    const int32_t* R;
-    const double* const* A;
-    const int32_t* rb;
-    const double* const* b;
-    int32_t s;
-    const double* const* S;
-    const int32_t* rho;
-    const double* const* Y;
-    const int32_t* rx;
-    const double* const* X;
-    const ttsg_sgmres_opts* opts;
-    double* const* x;
-    int32_t* x_r;
-    ttsg_sgmres_info* info;
-    int32_t status;
-} ttsg_system;
-
-int ttsg_sgmres_solve_batched(int32_t count, ttsg_system* systems, int32_t concurrency,
-                              ttsg_stream_t stream);
-
 /* ------------------------------------------------------------------------- */
 /* TT-sPGMRES (Alg. 5) and the other solve options                            */
 /* ------------------------------------------------------------------------- */
@@ -342,6 +309,43 @@ int ttsg_sgmres_solve_ex(int32_t d, const int32_t* n,
 int ttsg_sgmres_workspace_size(int32_t d, const int32_t* n, const int32_t* R, const int32_t* rb, int32_t s,
                                const int32_t* rho, const int32_t* rx, const ttsg_sgmres_opts* opts,
                                const ttsg_sgmres_ext* ext, size_t* bytes);
+
+/* Many independent systems (Alg. 4, or Alg. 5 with a preconditioner in `ext`,
+ * on each), solved concurrently on one GPU.  Each entry carries exactly the
+ * arguments of ttsg_sgmres_solve_ex (same meaning, layout and ownership);
+ * `status` receives that system's return value.
+ * Systems are taken longest-first by `concurrency` host workers (<= 0: 8),
+ * each driving its own non-blocking stream of default priority, so the
+ * kernels of different systems overlap on the GPU while each system's host
+ * rank decisions proceed independently.  All worker streams first wait for
+ * the work queued on `stream`.  Returns 0 when every system returned >= 0,
+ * else the first negative code (ttsg_last_error names the system).  Returns
+ * after every system has finished. */
+typedef struct {
+    int32_t d;
+    const int32_t* n;
+    const int32_t* R;
+    const double* const* A;
+    const int32_t* rb;
+    const double* const* b;
+    int32_t s;
+    const double* const* S;
+    const int32_t* rho;
+    const double* const* Y;
+    const int32_t* rx;
+    const double* const* X;
+    const ttsg_sgmres_opts* opts;
+    double* const* x;
+    int32_t* x_r;
+    ttsg_sgmres_info* info;
+    int32_t status;
+    /* options of ttsg_sgmres_solve_ex (initial guess, preconditioner of Alg. 5,
+       least-squares form, final-solution variant); NULL: plain Alg. 4 */
+    const ttsg_sgmres_ext* ext;
+} ttsg_system;
+
+int ttsg_sgmres_solve_batched(int32_t count, ttsg_system* systems, int32_t concurrency,
+                              ttsg_stream_t stream);
 
 /* ------------------------------------------------------------------------- */
 /* TT-GMRES (Alg. 2): the deterministic method the sketched one is compared   */

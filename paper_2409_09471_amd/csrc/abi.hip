@@ -875,8 +875,8 @@ int ttsg_sgmres_solve_batched(int32_t count, ttsg_system* sys, int32_t concurren
             }
             for (int j = next++; j < count; j = next++) {
                 ttsg_system& q = sys[order[j]];
-                const int rc = ttsg_sgmres_solve(q.d, q.n, q.R, q.A, q.rb, q.b, q.s, q.S, q.rho, q.Y, q.rx, q.X, q.opts,
-                                                 q.x, q.x_r, q.info, nullptr, 0, st);
+                const int rc = ttsg_sgmres_solve_ex(q.d, q.n, q.R, q.A, q.rb, q.b, q.s, q.S, q.rho, q.Y, q.rx, q.X,
+                                                    q.opts, q.ext, q.x, q.x_r, q.info, nullptr, 0, st);
                 q.status = rc;
                 if (rc < 0) {
                     std::lock_guard<std::mutex> lk(mu);

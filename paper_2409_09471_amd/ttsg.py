@@ -521,7 +521,7 @@ class _System(ctypes.Structure):
                 ("rb", ctypes.c_void_p), ("b", ctypes.c_void_p), ("s", ctypes.c_int32), ("S", ctypes.c_void_p),
                 ("rho", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("rx", ctypes.c_void_p), ("X", ctypes.c_void_p),
                 ("opts", ctypes.c_void_p), ("x", ctypes.c_void_p), ("x_r", ctypes.c_void_p), ("info", ctypes.c_void_p),
-                ("status", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("ext", ctypes.c_void_p)]
 
 
 @dataclass
@@ -545,6 +545,7 @@ class BatchSystem:
     rcond: float = 1e-12
     precision: int = PREC_F64
     max_cycles: int = 50
+    precond: Optional["Preconditioner"] = None
 
 
 class GmresOpts(ctypes.Structure):
@@ -632,6 +633,15 @@ def sgmres_solve_batched(systems: Sequence[BatchSystem], concurrency: int = 8) -
         e.x = addr(_ptrs(x))
         e.x_r = ctypes.cast(xr, ctypes.c_void_p)
         e.info = ctypes.cast(ctypes.pointer(info), ctypes.c_void_p)
+        if q.precond is not None:
+            ext = SgmresExt(ls_mode=LS_PINV, variant=VARIANT_ENHANCED)
+            aa, ba, ma = _dbl(q.precond.alpha), _dbl(q.precond.beta), _ptrs(q.precond.M)
+            ext.zeta = len(q.precond.alpha)
+            ext.alpha = ctypes.cast(aa, ctypes.c_void_p)
+            ext.beta = ctypes.cast(ba, ctypes.c_void_p)
+            ext.M = ctypes.cast(ma, ctypes.c_void_p)
+            keep.extend([ext, aa, ba, ma])
+            e.ext = ctypes.cast(ctypes.pointer(ext), ctypes.c_void_p)
         outs.append((x, xr, info, sh, rh, th, q))
     _check(lib().ttsg_sgmres_solve_batched(len(systems), arr, int(concurrency), _stream()),
            "ttsg_sgmres_solve_batched")

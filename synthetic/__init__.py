@@ -288,13 +288,13 @@ def config_c3_systems(count: int = 64):
     return out
 
 
-def config_c3_system(i: int, d: int, n: int, rb: int, s: int = 1000, maxit: int = 500) -> Workload:
+def config_c3_system(i: int, d: int, n: int, rb: int, s: int = 1000, maxit: int = 500, cap: int = 32) -> Workload:
     rng = rng_for(2, 1 + i)
     ns = [n] * d
     L = laplacian_1d(n)
     b = gaussian_tt(rng, ns, [1] + [rb] * (d - 1) + [1])
-    S, X, Y, rx, rho = _sketches(rng, ns, s, 32, 20)
-    return Workload(f"batch{i}_d{d}_n{n}", d, ns, [[L] * d], 2, b, S, X, Y, rx, rho, 32, s, 1,
+    S, X, Y, rx, rho = _sketches(rng, ns, s, cap, 20)
+    return Workload(f"batch{i}_d{d}_n{n}", d, ns, [[L] * d], 2, b, S, X, Y, rx, rho, cap, s, 1,
                     maxit, 0, 1e-6, 1e-7, 0.1)
 
 
