@@ -529,6 +529,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     struct SideStreams {
         hipStream_t k = nullptr, h = nullptr, r = nullptr;
         hipEvent_t v = nullptr, hd = nullptr;
+        hipEvent_t zr = nullptr, kd = nullptr;   // a preconditioner term is in place / read by stream K
         hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
         ~SideStreams() {
             if (k) (void)hipStreamSynchronize(k);
@@ -536,6 +537,8 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             if (r) (void)hipStreamSynchronize(r);
             if (v) (void)hipEventDestroy(v);
             if (hd) (void)hipEventDestroy(hd);
+            if (zr) (void)hipEventDestroy(zr);
+            if (kd) (void)hipEventDestroy(kd);
             for (hipEvent_t e : ev)
                 if (e) (void)hipEventDestroy(e);
             if (k) (void)hipStreamDestroy(k);
@@ -548,6 +551,9 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     TTSG_HIP(hipStreamCreateWithFlags(&side.r, hipStreamNonBlocking));
     TTSG_HIP(hipEventCreateWithFlags(&side.v, hipEventDisableTiming));
     TTSG_HIP(hipEventCreateWithFlags(&side.hd, hipEventDisableTiming));
+    TTSG_HIP(hipEventCreateWithFlags(&side.zr, hipEventDisableTiming));
+    TTSG_HIP(hipEventCreateWithFlags(&side.kd, hipEventDisableTiming));
+    TTSG_HIP(hipEventRecord(side.kd, side.k));
     for (hipEvent_t& e : side.ev) TTSG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     SketchSide sk_side;
     sk_side.st = side.r;
@@ -770,14 +776,23 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         std::vector<const void*> SA64(SA64_.begin(), SA64_.end());
         double* wcol = W_ + (int64_t)k * s;
         for (int j = 0; j < in_.zeta; ++j) {
+            // the term's mode products overwrite the previous term (of this or
+            // the previous step), which stream K may still be reading
+            if (!white_) TTSG_HIP(hipStreamWaitEvent(st_, side.kd, 0));
             mode_product_tt(d, n, slot_r_[vk], cvec(slots_[vk]), Eterm(j), in_.alpha[j], zbuf_, st_, &scratch_);
             if (p_ != Prec::F64)
                 for (int mu = 0; mu < d; ++mu)
                     convert_f64_f32((int64_t)slot_r_[vk][mu] * n[mu] * slot_r_[vk][mu + 1], zbuf_[mu],
                                     static_cast<float*>(zlp_[mu]), st_);
             if (!white_) {
-                kr_sketch_run(Prec::F64, d, n, s, in_.R, SA64, slot_r_[vk], z64, j == 0 ? wcol : wtmp_, scratch_, st_);
-                if (j > 0) axpby(s, 1.0, wtmp_, 1.0, wcol, st_);
+                // (stream K) the term's Khatri-Rao column, summed into W's column
+                // in term order, while this stream sketches the same term
+                TTSG_HIP(hipEventRecord(side.zr, st_));
+                TTSG_HIP(hipStreamWaitEvent(side.k, side.zr, 0));
+                kr_sketch_run(Prec::F64, d, n, s, in_.R, SA64, slot_r_[vk], z64, j == 0 ? wcol : wtmp_, scratchK_,
+                              side.k);
+                if (j > 0) axpby(s, 1.0, wtmp_, 1.0, wcol, side.k);
+                TTSG_HIP(hipEventRecord(side.kd, side.k));
             }
             for (int t = 0; t < nw; ++t)
                 inner_run(pk_cur, d, n, in_.R, Dv, slot_r_[vk], zop, slot_r_[window[t]], slot_ops(window[t]),
@@ -789,8 +804,8 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         hipLaunchKernelGGL(k_sum_terms, dim3(1), dim3(64), 0, st_, nw, in_.zeta, htmp_, hco_ + 1);
         TTSG_HIP(hipGetLastError());
         if (!white_) {
-            hipLaunchKernelGGL(k_ls_append, dim3(1), dim3(LS_THREADS), 0, st_, s, k, m_ + 1, W_, Q_, Rls_, cls_, z_,
-                               lsres_);
+            hipLaunchKernelGGL(k_ls_append, dim3(1), dim3(LS_THREADS), 0, side.k, s, k, m_ + 1, W_, Q_, Rls_, cls_,
+                               z_, lsres_);
             TTSG_HIP(hipGetLastError());
         }
         TTSG_HIP(hipStreamWaitEvent(st_, side.hd, 0));
@@ -1000,7 +1015,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
                 TTSG_HIP(hipGetLastError());
                 sres = *static_cast<const double*>(read_back(lsres_, sizeof(double), &sres, st_));
             } else {
-                sres = *static_cast<const double*>(read_back(lsres_, sizeof(double), &sres, pre_ ? st_ : side.k));
+                sres = *static_cast<const double*>(read_back(lsres_, sizeof(double), &sres, side.k));
             }
             add_phase(TTSG_PH_LS, t1);
             TTSG_CHECK(std::isfinite(sres), TTSG_ERR_NONFINITE, "non-finite sketched residual");
