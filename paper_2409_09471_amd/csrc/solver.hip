@@ -530,6 +530,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         hipStream_t k = nullptr, h = nullptr, r = nullptr;
         hipEvent_t v = nullptr, hd = nullptr;
         hipEvent_t zr = nullptr, kd = nullptr;   // a preconditioner term is in place / read by stream K
+        hipEvent_t hz = nullptr;                 // ... / read by stream H
         hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
         ~SideStreams() {
             if (k) (void)hipStreamSynchronize(k);
@@ -539,6 +540,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             if (hd) (void)hipEventDestroy(hd);
             if (zr) (void)hipEventDestroy(zr);
             if (kd) (void)hipEventDestroy(kd);
+            if (hz) (void)hipEventDestroy(hz);
             for (hipEvent_t e : ev)
                 if (e) (void)hipEventDestroy(e);
             if (k) (void)hipStreamDestroy(k);
@@ -554,6 +556,8 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     TTSG_HIP(hipEventCreateWithFlags(&side.zr, hipEventDisableTiming));
     TTSG_HIP(hipEventCreateWithFlags(&side.kd, hipEventDisableTiming));
     TTSG_HIP(hipEventRecord(side.kd, side.k));
+    TTSG_HIP(hipEventCreateWithFlags(&side.hz, hipEventDisableTiming));
+    TTSG_HIP(hipEventRecord(side.hz, side.h));
     for (hipEvent_t& e : side.ev) TTSG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     SketchSide sk_side;
     sk_side.st = side.r;
@@ -777,30 +781,35 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
         double* wcol = W_ + (int64_t)k * s;
         for (int j = 0; j < in_.zeta; ++j) {
             // the term's mode products overwrite the previous term (of this or
-            // the previous step), which stream K may still be reading
+            // the previous step), which streams K and H may still be reading
             if (!white_) TTSG_HIP(hipStreamWaitEvent(st_, side.kd, 0));
+            TTSG_HIP(hipStreamWaitEvent(st_, side.hz, 0));
             mode_product_tt(d, n, slot_r_[vk], cvec(slots_[vk]), Eterm(j), in_.alpha[j], zbuf_, st_, &scratch_);
             if (p_ != Prec::F64)
                 for (int mu = 0; mu < d; ++mu)
                     convert_f64_f32((int64_t)slot_r_[vk][mu] * n[mu] * slot_r_[vk][mu + 1], zbuf_[mu],
                                     static_cast<float*>(zlp_[mu]), st_);
+            TTSG_HIP(hipEventRecord(side.zr, st_));
             if (!white_) {
                 // (stream K) the term's Khatri-Rao column, summed into W's column
                 // in term order, while this stream sketches the same term
-                TTSG_HIP(hipEventRecord(side.zr, st_));
                 TTSG_HIP(hipStreamWaitEvent(side.k, side.zr, 0));
                 kr_sketch_run(Prec::F64, d, n, s, in_.R, SA64, slot_r_[vk], z64, j == 0 ? wcol : wtmp_, scratchK_,
                               side.k);
                 if (j > 0) axpby(s, 1.0, wtmp_, 1.0, wcol, side.k);
                 TTSG_HIP(hipEventRecord(side.kd, side.k));
             }
+            // (stream H) the term's coefficients against the window
+            TTSG_HIP(hipStreamWaitEvent(side.h, side.zr, 0));
             for (int t = 0; t < nw; ++t)
                 inner_run(pk_cur, d, n, in_.R, Dv, slot_r_[vk], zop, slot_r_[window[t]], slot_ops(window[t]),
-                          htmp_ + t * in_.zeta + j, scratch_, st_, blk);
+                          htmp_ + t * in_.zeta + j, scratchH_, side.h, blk);
+            TTSG_HIP(hipEventRecord(side.hz, side.h));
             stta_sketch(so_op, slot_r_[vk], zop, (j == 0 ? pa : pt).data(), (j == 0 ? oa : ot).data(), scratch_, st_,
                         &sk_side);
             if (j > 0) axpby(sk_len_, 1.0, skT_, 1.0, skA_, st_);
         }
+        TTSG_HIP(hipStreamWaitEvent(st_, side.hz, 0));
         hipLaunchKernelGGL(k_sum_terms, dim3(1), dim3(64), 0, st_, nw, in_.zeta, htmp_, hco_ + 1);
         TTSG_HIP(hipGetLastError());
         if (!white_) {
