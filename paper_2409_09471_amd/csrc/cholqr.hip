@@ -198,7 +198,7 @@ void zero_flags(int n, int* f, hipStream_t st) {
 bool cholqr_fits(int m, int c) { return c >= 1 && c <= CQ_BIG && m >= c; }
 
 void cholqr2(int m, int c, const double* X, int64_t xr, int64_t xc, double* Q, int64_t qr, int64_t qc, double* R,
-             int* flag, Arena& ar, hipStream_t st, double* RT) {
+             int* flag, Arena& ar, hipStream_t st, double* RT, double* rinv_fro2) {
     TTSG_CHECK(cholqr_fits(m, c), TTSG_ERR_ARG, "cholqr2: needs m >= c and c <= 128");
     const size_t mark = ar.mark();
     double* G = ar.get<double>((int64_t)c * c);
@@ -274,6 +274,20 @@ void cholqr2(int m, int c, const double* X, int64_t xr, int64_t xc, double* Q, i
     gram(Q1, c, 1);
     chol(R2, R2i, 1, R1, R, RT);   // also R = R2 R1 (and R^T)
     times_inv(Q1, c, 1, R2i, Q, qr, qc);
+    if (rinv_fro2 != nullptr) {
+        // R^{-1} = R1^{-1} R2^{-1} (column-major c x c), then its squared Frobenius norm
+        double* Ri = ar.get<double>((int64_t)c * c);
+        double* part = ar.get<double>(1024);
+        ContractDesc d = cdesc(c, c, c);
+        d.am = idx1(1);
+        d.ak = idx1(c);
+        d.bk = idx1(1);
+        d.bn = idx1(c);
+        d.cm = idx1(1);
+        d.cn = idx1(c);
+        contract(Prec::F64, d, R1i, R2i, Ri, st, &ar);
+        sumsq((int64_t)c * c, Ri, part, rinv_fro2, st);
+    }
     ar.release(mark);
 }
 

@@ -187,7 +187,7 @@ size_t tt_svd_extra_bytes(int d, const int* n, const int* r) {
     // CholQR2's five), + the host read-back block (squared norm, flags,
     // per-bond singular values)
     return (sum + 6 * mx + 12 * rmax * rmax + 4096) * sizeof(double) + (size_t)(d + 1) * 64 +
-           (4 + (rmax + 1) * d) * sizeof(double) + 256;
+           (4 + (rmax + 2) * d) * sizeof(double) + 256;
 }
 
 double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vector<double*>& w,
@@ -214,7 +214,7 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
     // Values the host reads back, packed so that each synchronization point
     // costs one copy: [squared norm, spare, right-to-left CholQR flag] and,
     // per left-to-right bond, [singular values (maxr), CholQR flag].
-    const int64_t sbk = maxr + 1;
+    const int64_t sbk = maxr + 2;
     double* rb = ar.get<double>(4 + sbk * d);
     fill(4 + sbk * d, 0.0, rb, st);   // clears every flag
     double* scal = rb;
@@ -364,7 +364,30 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
                 std::copy(hr, hr + sbk, hb.begin());
                 hsig.assign(hb.begin(), hb.begin() + c);
             };
-            if (chol) {
+            // 65..128 columns: when 1 / ||R^{-1}||_F (a lower bound of the
+            // smallest singular value) is above the truncation threshold and the
+            // cap does not bind, no direction can be dropped (the tail of even
+            // one singular value exceeds delta): the bond keeps Q and passes R
+            // on, the same tensor without the SVD's gauge, and the Jacobi SVD
+            // (about a millisecond on one CU) is not run
+            bool keep_all = false;
+            if (chol && big && (maxrank <= 0 || c <= maxrank)) {
+                cholqr2(m, c, X, c, 1, Q, c, 1, Rm, bond_flag(mu), ar, st, QV, bond_blk(mu) + maxr + 1);
+                const double* hr =
+                    static_cast<const double*>(read_back(bond_blk(mu), sbk * sizeof(double), hb.data(), st));
+                std::copy(hr, hr + sbk, hb.begin());
+                int hflag = 0;
+                std::memcpy(&hflag, &hb[maxr], sizeof(int));
+                const double f2 = hb[maxr + 1];
+                if (hflag != 0) {
+                    stats_event(TTSG_ST_QR_REDO);
+                    chol = false;
+                } else if (std::isfinite(f2) && f2 > 0.0 && 1.0 / std::sqrt(f2) > 2.0 * delta) {
+                    keep_all = true;
+                } else {
+                    small_svd(true);
+                }
+            } else if (chol) {
                 cholqr2(m, c, X, c, 1, Q, c, 1, Rm, bond_flag(mu), ar, st, QV);   // QV = R^T
                 small_svd(true);
                 int hflag = 0;
@@ -374,70 +397,77 @@ double tt_svd_inplace(int d, const int* n, std::vector<int>& r, const std::vecto
                     chol = false;
                 }
             }
-            if (!chol) {
-                householder();
-                small_svd(false);
-            }
-            perm = argsort_desc(hsig);
-            std::vector<double> sd(c);
-            for (int t = 0; t < c; ++t) sd[t] = hsig[perm[t]];
-            k = trunc_rank(sd, delta, maxrank);
-            k = std::min(k, c);
-            // the LDS Jacobi returns its columns sorted by singular value, so
-            // the kept vectors are the leading columns; otherwise gather them
-            bool sorted = true;
-            for (int t = 0; t < c; ++t) sorted = sorted && perm[t] == t;
-            const double* Uk = V;
-            if (big) {
-                // U_k = B[:, :k] / s (zero for a zero singular value)
-                std::vector<int> pk(k);
-                std::vector<double> inv(k);
-                for (int t = 0; t < k; ++t) {
-                    pk[t] = t;
-                    inv[t] = sd[t] > 0.0 ? 1.0 / sd[t] : 0.0;
-                }
-                hold_i.push_back(pk);
-                hold_d.push_back(inv);
-                upload_perm(hold_i.back(), hold_d.back(), perm_dev, fac_dev, st);
-                gather_cols(c, k, Jb, c, V, c, perm_dev, fac_dev, st);
-                // QV (column-major c x k) = R^T U_k, i.e. S V_R^T read row-major
-                ContractDesc dr = cdesc(c, k, c);
-                dr.am = idx1(c);
-                dr.ak = idx1(1);
-                dr.bk = idx1(1);
-                dr.bn = idx1(c);
-                dr.cm = idx1(1);
-                dr.cn = idx1(c);
-                contract(Prec::F64, dr, Rm, V, QV, st, &ar);
-            } else if (!sorted) {
-                std::vector<int> pk(perm.begin(), perm.begin() + k);
-                hold_i.push_back(pk);
-                hold_d.push_back(std::vector<double>(k, 1.0));
-                upload_perm(hold_i.back(), hold_d.back(), perm_dev, fac_dev, st);
-                gather_cols(c, k, V, c, T, c, perm_dev, fac_dev, st);   // Uk (c x k, column-major) = V'[:, perm]
-                Uk = T;
-            }
-            // new core (row-major m x k) = Q (m x c) * Uk
-            if (chol) {
-                ContractDesc dq = cdesc(m, k, c);
-                dq.am = idx1(c);
-                dq.ak = idx1(1);
-                dq.bk = idx1(1);
-                dq.bn = idx1(c);
-                dq.cm = idx1(k);
-                dq.cn = idx1(1);
-                contract(Prec::F64, dq, Q, Uk, w[mu], st, &ar);
-            } else if (tsqr) {
-                plan.apply(k, Uk, c, w[mu], k, true, ar, st);
+            if (keep_all) {
+                // new core = Q (row-major m x c); S V^T read from QV = R^T
+                copy_f64((int64_t)m * c, Q, w[mu], st);
+                ar.release(mk);
+                k = c;
             } else {
-                gemm_cm_cm(m, k, c, Q, m, Uk, c, w[mu], k, st, &ar);
-            }
-            ar.release(mk);
-            // S V_R^T (row-major k x c == column-major c x k) = (U' S)[:, perm]:
-            // the leading k columns of QV when sorted
-            if (!sorted && !big) {
-                gather_cols(c, k, QV, c, Rm, c, perm_dev, fac_dev, st);
-                copy_f64((int64_t)c * k, Rm, QV, st);
+                if (!chol) {
+                    householder();
+                    small_svd(false);
+                }
+                perm = argsort_desc(hsig);
+                std::vector<double> sd(c);
+                for (int t = 0; t < c; ++t) sd[t] = hsig[perm[t]];
+                k = trunc_rank(sd, delta, maxrank);
+                k = std::min(k, c);
+                // the LDS Jacobi returns its columns sorted by singular value, so
+                // the kept vectors are the leading columns; otherwise gather them
+                bool sorted = true;
+                for (int t = 0; t < c; ++t) sorted = sorted && perm[t] == t;
+                const double* Uk = V;
+                if (big) {
+                    // U_k = B[:, :k] / s (zero for a zero singular value)
+                    std::vector<int> pk(k);
+                    std::vector<double> inv(k);
+                    for (int t = 0; t < k; ++t) {
+                        pk[t] = t;
+                        inv[t] = sd[t] > 0.0 ? 1.0 / sd[t] : 0.0;
+                    }
+                    hold_i.push_back(pk);
+                    hold_d.push_back(inv);
+                    upload_perm(hold_i.back(), hold_d.back(), perm_dev, fac_dev, st);
+                    gather_cols(c, k, Jb, c, V, c, perm_dev, fac_dev, st);
+                    // QV (column-major c x k) = R^T U_k, i.e. S V_R^T read row-major
+                    ContractDesc dr = cdesc(c, k, c);
+                    dr.am = idx1(c);
+                    dr.ak = idx1(1);
+                    dr.bk = idx1(1);
+                    dr.bn = idx1(c);
+                    dr.cm = idx1(1);
+                    dr.cn = idx1(c);
+                    contract(Prec::F64, dr, Rm, V, QV, st, &ar);
+                } else if (!sorted) {
+                    std::vector<int> pk(perm.begin(), perm.begin() + k);
+                    hold_i.push_back(pk);
+                    hold_d.push_back(std::vector<double>(k, 1.0));
+                    upload_perm(hold_i.back(), hold_d.back(), perm_dev, fac_dev, st);
+                    gather_cols(c, k, V, c, T, c, perm_dev, fac_dev, st);   // Uk (c x k, column-major) = V'[:, perm]
+                    Uk = T;
+                }
+                // new core (row-major m x k) = Q (m x c) * Uk
+                if (chol) {
+                    ContractDesc dq = cdesc(m, k, c);
+                    dq.am = idx1(c);
+                    dq.ak = idx1(1);
+                    dq.bk = idx1(1);
+                    dq.bn = idx1(c);
+                    dq.cm = idx1(k);
+                    dq.cn = idx1(1);
+                    contract(Prec::F64, dq, Q, Uk, w[mu], st, &ar);
+                } else if (tsqr) {
+                    plan.apply(k, Uk, c, w[mu], k, true, ar, st);
+                } else {
+                    gemm_cm_cm(m, k, c, Q, m, Uk, c, w[mu], k, st, &ar);
+                }
+                ar.release(mk);
+                // S V_R^T (row-major k x c == column-major c x k) = (U' S)[:, perm]:
+                // the leading k columns of QV when sorted
+                if (!sorted && !big) {
+                    gather_cols(c, k, QV, c, Rm, c, perm_dev, fac_dev, st);
+                    copy_f64((int64_t)c * k, Rm, QV, st);
+                }
             }
         } else {
             // wide unfolding: M^T (c x m) is the row-major core read column-major

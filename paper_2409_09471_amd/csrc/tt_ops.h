@@ -294,9 +294,11 @@ void tt_add_block(int d, const int* n, const std::vector<int>& ra, const std::ve
 // flag[0] = 1 on the device when the factorization is not trustworthy
 // (cholqr.hip); requires cholqr_fits(m, c).
 bool cholqr_fits(int m, int c);
-// RT != nullptr also receives R^T (c x c, column-major).
+// RT != nullptr also receives R^T (c x c, column-major).  rinv_fro2 !=
+// nullptr receives ||R^{-1}||_F^2 (device scalar): sigma_min(R) >=
+// 1 / ||R^{-1}||_F, so a caller can tell that no singular value is small.
 void cholqr2(int m, int c, const double* X, int64_t xr, int64_t xc, double* Q, int64_t qr, int64_t qc, double* R,
-             int* flag, Arena& ar, hipStream_t st, double* RT = nullptr);
+             int* flag, Arena& ar, hipStream_t st, double* RT = nullptr, double* rinv_fro2 = nullptr);
 void zero_flags(int n, int* f, hipStream_t st);
 
 // -<lambda, L_k x> for every mode k (grad.hip); result in out_dev[0..d-1].

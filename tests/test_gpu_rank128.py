@@ -60,6 +60,30 @@ def test_round_svd_rank_up_to_128(terms, rank_each, tol, maxrank):
         assert tt_rel(host(y), x) <= max(tol, 1e-12) * (1 + 1e-6)
 
 
+def test_round_svd_keeps_every_direction_above_the_threshold():
+    """Bonds of 65..128 columns whose smallest singular value is far above the
+    truncation threshold: the sweep keeps the QR factors without an SVD (the
+    bound 1 / ||R^{-1}||_F already exceeds it).  The ranks must be the oracle's
+    (nothing dropped) and the tensor unchanged to rounding; a second bond of
+    the same tensor that does truncate still goes through the SVD."""
+    n, d = 32, 4
+    rng = np.random.default_rng(83)
+    x = syn.gaussian_tt(rng, [n] * d, [1, 32, 110, 32, 1])
+    # gentle decay across the middle bond (smallest direction ~ 0.99^110 = 0.33
+    # of the largest), steep decay across the last one (0.5^32 ~ 2e-10)
+    x[1] = x[1] * (0.99 ** np.arange(110))[None, None, :]
+    x[2] = x[2] * (0.5 ** np.arange(32))[None, None, :]
+    tol = 1e-7
+    y = ttsg.round_svd(ttsg.to_device(x, DEV), tol, 0)
+    ref = ott.round_svd(x, tol, None)
+    print(f"ranks in {ott.ranks(x)} gpu {ttsg.ranks_of(y)} oracle {ott.ranks(ref)}", flush=True)
+    assert ttsg.ranks_of(y) == ott.ranks(ref)
+    assert ttsg.ranks_of(y)[2] == 110           # middle bond: nothing dropped
+    assert ttsg.ranks_of(y)[3] < 32             # last bond: truncated
+    assert tt_rel(host(y), ref) < 1e-9 + 1e-3 * tol
+    assert tt_rel(host(y), x) <= tol
+
+
 @pytest.mark.parametrize("ranks,tol,maxrank", [
     ([1, 32, 100, 32, 1], 1e-8, 0),      # rank 100 below rx = 128: Omega_2 (148 x 128) rank-deficient
     ([1, 32, 128, 32, 1], 1e-6, 0),      # full target rank
