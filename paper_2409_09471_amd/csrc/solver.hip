@@ -1134,7 +1134,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
                 for (int j = 0; j < in_.zeta; ++j) {
                     mode_product_tt(d, n, cr, cvec(slots_[fs]), Eterm(j), in_.alpha[j], zbuf_, st_, &scratch_);
                     stta_sketch(so_plain, cr, z64, (j == 0 ? pa : pt).data(), (j == 0 ? oa : ot).data(), scratch_,
-                                st_);
+                                st_, &sk_side);
                     if (j > 0) axpby(sk_len_, 1.0, skT_, 1.0, skA_, st_);
                 }
                 std::vector<const double*> ppsi(pa.begin(), pa.end()), pom(oa.begin(), oa.end());
