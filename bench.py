@@ -70,6 +70,9 @@ def parse():
                     help="use the default contraction tiles (no tuned table, no tuning)")
     ap.add_argument("--no-rounding", action="store_true",
                     help="skip the standalone rounding GFLOP/s legs (profiling runs of the solve alone)")
+    ap.add_argument("--single-stream", action="store_true",
+                    help="every solve with all launches on one stream, no overlapped measurement solve "
+                         "(profiling runs whose per-launch trace is compared with the measurement solve's)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer with a plain device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -92,40 +95,47 @@ def build_inputs(name, dev):
     return w, t
 
 
-def solve(w, t, precision, phase_timing=False):
+def solve(w, t, precision, phase_timing=False, single_stream=False):
     from paper_2409_09471_amd import ttsg
     return ttsg.sgmres_solve(t["A"], t["b"], t["S"], t["X"], t["Y"], w.rx, w.rho, maxit=w.maxit, tol=w.tol,
                              q=w.q, round_tol=w.round_tol, maxrank=w.cap, stop_safety=w.stop_safety,
-                             restart=w.restart, precision=precision, precond=t["pre"], phase_timing=phase_timing)
+                             restart=w.restart, precision=precision, precond=t["pre"], phase_timing=phase_timing,
+                             single_stream=single_stream)
 
 
-def timed_solves(w, t, precision, steps, warmup, measure=True, tune=False, tag=""):
+def timed_solves(w, t, precision, steps, warmup, measure=True, tune=False, tag="", single_stream=False):
     """Wall-clock time of `steps` solves (measurement off), then (measure=True)
-    one more solve with the per-launch device timers on for the kernel figures.
-    With tune=True the first warmup solve runs with the tile autotuner on."""
+    two more solves with the per-launch device timers on: one with every launch
+    on one stream (each launch has the GPU to itself: the per-launch kernel
+    figures) and, unless every solve is single-stream, one as timed, with the
+    solver's side streams (the classes' busy time and concurrency).  With
+    tune=True the first warmup solve runs with the tile autotuner on."""
     import torch
     from paper_2409_09471_amd import ttsg
     for i in range(warmup):
         ttsg.autotune(tune and i == 0)
-        r = solve(w, t, precision)
+        r = solve(w, t, precision, single_stream=single_stream)
         ttsg.autotune(False)
         print(f"# {tag}warmup {i}: its={r.iterations} true_res={r.true_residual:.3e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
     for i in range(steps):
-        results.append(solve(w, t, precision))
+        results.append(solve(w, t, precision, single_stream=single_stream))
         print(f"# {tag}step {i}: its={results[-1].iterations} true_res={results[-1].true_residual:.3e}",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    stats = {}
+    stats, stats_ov = {}, {}
     if measure:
         ttsg.stats_enable(True)
-        solve(w, t, precision)
+        solve(w, t, precision, single_stream=True)
         stats = ttsg.stats_read()
+        if not single_stream:
+            solve(w, t, precision)
+            stats_ov = ttsg.stats_read()
         ttsg.stats_enable(False)
-    return elapsed, results, stats
+    return elapsed, results, stats, stats_ov
 
 
 def rounding_gflops(w, t, precision):
@@ -304,7 +314,8 @@ def main():
             ttsg.autotune_load(TILE_TABLE)
         else:
             tune = True
-    el, results, stats = timed_solves(w, t, prec, args.steps, max(args.warmup, 1 if tune else 0), tune=tune)
+    el, results, stats, stats_ov = timed_solves(w, t, prec, args.steps, max(args.warmup, 1 if tune else 0), tune=tune,
+                                                single_stream=args.single_stream)
     per = el / args.steps
     last = results[-1]
     converged = all(r.status == ttsg.OK for r in results)
@@ -322,16 +333,30 @@ def main():
         "true_residual_is_bound": last.true_residual_is_bound,
         "sketched_residual": last.sketched_residual, "max_rank": last.max_rank,
     }
-    # per-class kernel figures of one measured solve (device wall-clock per launch)
+    # Per-class kernel figures of the measurement solves.  `kernels`: the
+    # single-stream solve, where each launch has the GPU to itself, so a
+    # launch's duration is its own.  `kernels_overlapped`: the solve as timed,
+    # whose side streams run independent launches at once; there `seconds`
+    # sums the launches' (stretched) durations and `busy_seconds` is the time
+    # during which at least one launch of the class ran, so `concurrency` =
+    # seconds / busy and `tflops_busy` is the class's throughput while it runs.
     kern = {}
     for k, v in stats.items():
         kern[k] = dict(launches=v["launches"], seconds=round(v["seconds"], 6),
                        tflops=round(v["flops"] / max(v["seconds"], 1e-12) / 1e12, 4),
                        gbs=round(v["bytes"] / max(v["seconds"], 1e-12) / 1e9, 2))
     out["kernels"] = kern
+    kov = {}
+    for k, v in stats_ov.items():
+        busy = v["busy"]
+        kov[k] = dict(launches=v["launches"], seconds=round(v["seconds"], 6), busy_seconds=round(busy, 6),
+                      concurrency=round(v["seconds"] / busy, 3) if busy > 0 else None,
+                      tflops_busy=round(v["flops"] / busy / 1e12, 4) if busy > 0 else None)
+    out["kernels_overlapped"] = kov
 
-    # Roofline of the dominant kernel class (summed device time of the measured
-    # solve).  A contraction class is placed by its algorithmic intensity
+    # Roofline of the dominant kernel class (summed device time of the
+    # single-stream measurement solve: durations of launches that had the GPU
+    # to themselves).  A contraction class is placed by its algorithmic intensity
     # (flops / operand bytes): below the dtype's ridge (peak flops / 8 TB/s) the
     # bound is HBM and `achieved` is GB/s, above it the matrix cores and
     # TFLOP/s.  The single-workgroup factorizations are priced against the FP64
@@ -356,6 +381,11 @@ def main():
                  "bytes_per_launch": by, "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
                  "avg_launch_us": per_launch_s * 1e6, "tflops": fl / per_launch_s / 1e12,
                  "gbs": by / per_launch_s / 1e9}
+            ov = stats_ov.get(cls)
+            if ov and ov["busy"] > 0:
+                r["overlapped"] = {"avg_launch_us": ov["seconds"] / ov["launches"] * 1e6,
+                                   "busy_seconds": ov["busy"], "concurrency": ov["seconds"] / ov["busy"],
+                                   "tflops_over_busy_time": ov["flops"] / ov["busy"] / 1e12}
             mu = counter_value(cls, "mfma_util", wl)
             if mu is not None:
                 r["mfma_util"] = mu
@@ -382,7 +412,7 @@ def main():
         n2 = max(1, min(args.steps, 10))
         legs = {}
         for name, p in (("mixed", ttsg.PREC_MIXED), ("f64", ttsg.PREC_F64)):
-            e2, r2, _ = timed_solves(w2, t2, p, n2, 1, measure=False, tag=f"c2 {name} ")
+            e2, r2, _, _ = timed_solves(w2, t2, p, n2, 1, measure=False, tag=f"c2 {name} ")
             legs[name] = dict(seconds=e2 / n2, iterations=r2[-1].iterations, true_residual=r2[-1].true_residual,
                               converged=all(r.status == ttsg.OK for r in r2))
         out["precision_legs"] = {"workload": WORKLOAD_TEXT["c2"], "solves_each": n2, **legs,

@@ -287,6 +287,13 @@ typedef struct {
        TTSG_VARIANT_VANILLA (Alg. 3: every basis vector of the cycle is kept and
        x = Round(x + y_i v_i, final_tol) term by term) */
     int32_t variant;
+    /* 0 (default): independent steps of an iteration (the Khatri-Rao column,
+       the coefficients h, the two halves of the STTA sketch) run on three
+       streams of the library's own beside the caller's, joined by events;
+       1: every launch goes to the caller's stream, in program order (same
+       results bit for bit; slower, but each launch has the GPU to itself,
+       which is what per-launch timing and profiling want) */
+    int32_t single_stream;
 } ttsg_sgmres_ext;
 
 /* ttsg_sgmres_solve with the options above (ext == NULL: plain Alg. 4).
@@ -480,7 +487,10 @@ typedef struct {
     int64_t launches[TTSG_ST_CLASSES];
     double flops[TTSG_ST_CLASSES];
     double bytes[TTSG_ST_CLASSES];
-    double seconds[TTSG_ST_CLASSES];
+    double seconds[TTSG_ST_CLASSES];   /* sum of the launches' durations */
+    double busy[TTSG_ST_CLASSES];      /* time during which at least one launch of the
+                                          class ran (union of their intervals): below
+                                          `seconds` when launches overlap on streams */
 } ttsg_stats;
 
 /* on != 0: clear the counters and start recording; on == 0: stop recording. */

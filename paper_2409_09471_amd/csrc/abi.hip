@@ -600,6 +600,9 @@ ttsg::SolverInputs solver_inputs(int32_t d, const int32_t* n, const int32_t* R, 
         TTSG_CHECK(ext->variant == TTSG_VARIANT_ENHANCED || ext->variant == TTSG_VARIANT_VANILLA, TTSG_ERR_ARG,
                    "sgmres: variant must be TTSG_VARIANT_ENHANCED or TTSG_VARIANT_VANILLA");
         in.variant = ext->variant;
+        TTSG_CHECK(ext->single_stream == 0 || ext->single_stream == 1, TTSG_ERR_ARG,
+                   "sgmres: single_stream must be 0 or 1");
+        in.single_stream = ext->single_stream != 0;
         if (ext->x0 != nullptr || ext->x0_r != nullptr) {
             TTSG_CHECK(ext->x0 != nullptr && ext->x0_r != nullptr, TTSG_ERR_ARG, "sgmres: x0 needs cores and ranks");
             check_shape(d, n, ext->x0_r, "sgmres x0");

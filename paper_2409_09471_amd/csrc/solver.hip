@@ -526,8 +526,11 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     // while the main stream sketches A v_k, each with its own scratch.
     // The STTA sketch of A v_k itself runs on two streams: its right sweep and
     // Omega sketches on side stream R, its left sweep and Psi sketches here.
+    // With single_stream the three are the caller's stream itself: the events
+    // then order nothing that program order does not already order.
     struct SideStreams {
         hipStream_t k = nullptr, h = nullptr, r = nullptr;
+        bool own = true;
         hipEvent_t v = nullptr, hd = nullptr;
         hipEvent_t zr = nullptr, kd = nullptr;   // a preconditioner term is in place / read by stream K
         hipEvent_t hz = nullptr;                 // ... / read by stream H
@@ -543,14 +546,19 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
             if (hz) (void)hipEventDestroy(hz);
             for (hipEvent_t e : ev)
                 if (e) (void)hipEventDestroy(e);
-            if (k) (void)hipStreamDestroy(k);
-            if (h) (void)hipStreamDestroy(h);
-            if (r) (void)hipStreamDestroy(r);
+            if (own && k) (void)hipStreamDestroy(k);
+            if (own && h) (void)hipStreamDestroy(h);
+            if (own && r) (void)hipStreamDestroy(r);
         }
     } side;
-    TTSG_HIP(hipStreamCreateWithFlags(&side.k, hipStreamNonBlocking));
-    TTSG_HIP(hipStreamCreateWithFlags(&side.h, hipStreamNonBlocking));
-    TTSG_HIP(hipStreamCreateWithFlags(&side.r, hipStreamNonBlocking));
+    if (in_.single_stream) {
+        side.own = false;
+        side.k = side.h = side.r = st_;
+    } else {
+        TTSG_HIP(hipStreamCreateWithFlags(&side.k, hipStreamNonBlocking));
+        TTSG_HIP(hipStreamCreateWithFlags(&side.h, hipStreamNonBlocking));
+        TTSG_HIP(hipStreamCreateWithFlags(&side.r, hipStreamNonBlocking));
+    }
     TTSG_HIP(hipEventCreateWithFlags(&side.v, hipEventDisableTiming));
     TTSG_HIP(hipEventCreateWithFlags(&side.hd, hipEventDisableTiming));
     TTSG_HIP(hipEventCreateWithFlags(&side.zr, hipEventDisableTiming));

@@ -90,8 +90,9 @@ int ttsg_stats_read(ttsg_stats* out) {
     std::lock_guard<std::mutex> lk(ttsg::g_mu);
     for (int c = 0; c < TTSG_ST_CLASSES; ++c) {
         out->launches[c] = 0;
-        out->flops[c] = out->bytes[c] = out->seconds[c] = 0.0;
+        out->flops[c] = out->bytes[c] = out->seconds[c] = out->busy[c] = 0.0;
     }
+    std::vector<std::vector<std::pair<unsigned long long, unsigned long long>>> spans(TTSG_ST_CLASSES);
     if (hipDeviceSynchronize() != hipSuccess) return -TTSG_ERR_HIP;
     int rate_khz = 0;
     int dev = 0;
@@ -122,9 +123,28 @@ int ttsg_stats_read(ttsg_stats* out) {
         out->flops[c] += (c == TTSG_ST_SVD && s.aux > 0) ? r.flops * (double)s.aux : r.flops;
         out->bytes[c] += r.bytes;
         out->seconds[c] += sec;
+        if (t1 > t0) spans[c].emplace_back(t0, t1);
         if (c == TTSG_ST_SVD && s.aux > (unsigned long long)out->flops[7]) out->flops[7] = (double)s.aux;
     }
     if (log != nullptr) std::fclose(log);
+    for (int c = 0; c < TTSG_ST_CLASSES; ++c) {
+        auto& v = spans[c];
+        std::sort(v.begin(), v.end());
+        unsigned long long cov = 0, a = 0, b = 0;
+        bool open = false;
+        for (const auto& iv : v) {
+            if (!open || iv.first > b) {
+                if (open) cov += b - a;
+                a = iv.first;
+                b = iv.second;
+                open = true;
+            } else if (iv.second > b) {
+                b = iv.second;
+            }
+        }
+        if (open) cov += b - a;
+        out->busy[c] = (double)cov / (1e3 * rate_khz);
+    }
     for (int c = 0; c < TTSG_ST_CLASSES; ++c) {
         out->launches[c] += ttsg::g_events[c];
         ttsg::g_events[c] = 0;

@@ -256,6 +256,7 @@ struct SolverInputs {
     std::vector<const double*> M;     // d mode matrices n_k x n_k
     int ls_mode = TTSG_LS_PINV;
     int variant = TTSG_VARIANT_ENHANCED;
+    bool single_stream = false;
 };
 
 // TT-GMRES (Alg. 2; gmres.hip): full modified Gram-Schmidt, TT-SVD rounding

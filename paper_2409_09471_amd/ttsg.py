@@ -76,7 +76,7 @@ STAT_CLASSES = {0: "contract_f64", 1: "contract_f32", 2: "contract_bf16", 3: "qr
 
 class Stats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 8), ("flops", ctypes.c_double * 8),
-                ("bytes", ctypes.c_double * 8), ("seconds", ctypes.c_double * 8)]
+                ("bytes", ctypes.c_double * 8), ("seconds", ctypes.c_double * 8), ("busy", ctypes.c_double * 8)]
 
 
 def autotune(on: bool = True) -> bool:
@@ -107,7 +107,7 @@ def stats_read() -> dict:
     for c, name in STAT_CLASSES.items():
         if st.launches[c]:
             out[name] = dict(launches=int(st.launches[c]), flops=st.flops[c], bytes=st.bytes[c],
-                             seconds=st.seconds[c])
+                             seconds=st.seconds[c], busy=st.busy[c])
     return out
 
 
@@ -137,7 +137,7 @@ class SgmresExt(ctypes.Structure):
     _fields_ = [
         ("x0_r", ctypes.c_void_p), ("x0", ctypes.c_void_p),
         ("zeta", ctypes.c_int32), ("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p), ("M", ctypes.c_void_p),
-        ("ls_mode", ctypes.c_int32), ("variant", ctypes.c_int32),
+        ("ls_mode", ctypes.c_int32), ("variant", ctypes.c_int32), ("single_stream", ctypes.c_int32),
     ]
 
 
@@ -461,9 +461,11 @@ def sgmres_solve(A, b, S, X, Y, rx, rho, *, maxit: int, tol: float, q: int = 1, 
                  rcond: float = 1e-12, precision: int = PREC_F64, max_cycles: int = 50,
                  phase_timing: bool = False, x0: Optional[Sequence[torch.Tensor]] = None,
                  precond: Optional[Preconditioner] = None, ls: int = LS_PINV, variant: int = VARIANT_ENHANCED,
-                 workspace: Optional[torch.Tensor] = None, raise_on_error: bool = True) -> SolveResult:
+                 single_stream: bool = False, workspace: Optional[torch.Tensor] = None,
+                 raise_on_error: bool = True) -> SolveResult:
     """Alg. 4 (Alg. 5 with `precond`).  The workspace is queried and allocated
-    here (or passed in), so the library allocates no device memory."""
+    here (or passed in), so the library allocates no device memory.  With
+    `single_stream` every launch goes to torch's current stream in order."""
     d = len(b)
     n = sizes_of(b)
     dev = b[0].device
@@ -471,7 +473,7 @@ def sgmres_solve(A, b, S, X, Y, rx, rho, *, maxit: int, tol: float, q: int = 1, 
                       max_cycles=max_cycles, tol=tol, round_tol=round_tol, final_tol=final_tol,
                       stop_safety=stop_safety, rcond=rcond)
     keep = []
-    ext = SgmresExt(ls_mode=int(ls), variant=int(variant))
+    ext = SgmresExt(ls_mode=int(ls), variant=int(variant), single_stream=int(bool(single_stream)))
     if x0 is not None:
         r0a, p0a = _i32(ranks_of(x0)), _ptrs(x0)
         keep += [r0a, p0a]
