@@ -139,20 +139,19 @@ __global__ __launch_bounds__(1024) void k_jacobi(int m, int c, double* __restric
     for (int l = 0; l < c; ++l)
         for (int i = tid; i < c; i += blockDim.x) V[(int64_t)l * ldv + i] = (i == l) ? 1.0 : 0.0;
     __shared__ int s_rot;
-    __shared__ double s_fro;
-    if (tid == 0) {
-        s_rot = 0;
-        s_fro = 0.0;
-    }
-    __syncthreads();
+    __shared__ double s_fpart[1024 / G];
+    if (tid == 0) s_rot = 0;
+    double s_fro = 0.0;
     {
+        // group partials summed in group order (the same bits every run)
         double f = 0.0;
         for (int l = grp; l < c; l += ngrp)
             for (int i = lt; i < m; i += G) f += A[(int64_t)l * lda + i] * A[(int64_t)l * lda + i];
         f = gsum_g<G>(f);
-        if (lt == 0) atomicAdd(&s_fro, f);
+        if (lt == 0) s_fpart[grp] = f;
+        __syncthreads();
+        for (int g = 0; g < ngrp; ++g) s_fro += s_fpart[g];
     }
-    __syncthreads();
     // columns below 2 m eps ||A||_F carry only rounding noise (null space of a
     // rank-deficient matrix); their mutual dot products never look orthogonal,
     // so they are treated as converged

@@ -43,14 +43,6 @@ struct JacobiBatch {
     int* meta[32];
 };
 
-// Wave leaders add their partial into an LDS scalar (thread 0 first zeroes it
-// through the initial value of its own contribution order: the caller runs
-// this after a barrier, so a plain atomic add is enough).
-__device__ __forceinline__ void tab_partial_add(double* dst, double v, bool first) {
-    (void)first;
-    atomicAdd(dst, v);
-}
-
 
 // One-sided Jacobi with one lane group of JG lanes per column pair: the group
 // forms the pair's three dot products over its strided rows, reduces them in
@@ -102,24 +94,25 @@ __global__ __launch_bounds__(JT) void k_jacobi_lds(JacobiBatch jb, int maxsweeps
     }
     const int grp = tid / JG, lt = tid - grp * JG;
     const int ngrp = JT / JG;
-    __shared__ double s_fro;
+    __shared__ double s_fpart[JT / 64];
     if (tid == 0) {
         s_rot = 0;
         s_moff = 0ull;
-        s_fro = 0.0;
     }
-    __syncthreads();
+    double s_fro = 0.0;
     {
-        // squared Frobenius norm: columns below eps ||A||_F are rounding noise
+        // squared Frobenius norm: columns below eps ||A||_F are rounding noise.
+        // Wave partials are summed in wave order (the same bits every run).
         double f = 0.0;
         for (int e = tid; e < m * c; e += blockDim.x) {
             int j = e / m, i = e - j * m;
             f += A[j * ldm + i] * A[j * ldm + i];
         }
         f = wave_sum64(f);
-        if ((tid & 63) == 0) tab_partial_add(&s_fro, f, tid == 0);
+        if ((tid & 63) == 0) s_fpart[tid >> 6] = f;
+        __syncthreads();
+        for (int w = 0; w < JT / 64; ++w) s_fro += s_fpart[w];
     }
-    __syncthreads();
     // columns below 2 m eps ||A||_F carry only rounding noise (null space of a
     // rank-deficient matrix); their mutual dot products never look orthogonal,
     // so they are treated as converged

@@ -651,7 +651,7 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     // zero and identity blocks of the operator cores (exact; the float32
     // copies keep them) are copied or skipped in the operator steps
     const std::vector<std::vector<uint8_t>> blocks =
-        operator_blocks(d, n, in_.R, std::vector<const void*>(in_.A.begin(), in_.A.end()), st_);
+        operator_blocks(d, n, in_.R, std::vector<const void*>(in_.A.begin(), in_.A.end()), st_, scratchR_);
     const std::vector<const uint8_t*> blk = block_ptrs(blocks);
     so_op.blk = blk;
     // FP64 sketches of A x for the restart residual

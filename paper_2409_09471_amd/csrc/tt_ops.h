@@ -24,8 +24,10 @@ struct LeftDims {
 enum : uint8_t { kBlkZero = 0, kBlkIdentity = 1, kBlkDense = 2 };
 // Classify every block of the d float64 operator cores D[mu] (R[mu] x n x n x
 // R[mu+1]); synchronizes st once.  Result: per core, R[mu] * R[mu+1] kinds.
+// The device table (sum of R[mu] * R[mu+1] bytes) is carved from `ar` and
+// released before returning.
 std::vector<std::vector<uint8_t>> operator_blocks(int d, const int* n, const std::vector<int>& R,
-                                                  const std::vector<const void*>& D, hipStream_t st);
+                                                  const std::vector<const void*>& D, hipStream_t st, Arena& ar);
 // Host pointers into operator_blocks' result (empty when it is empty).
 std::vector<const uint8_t*> block_ptrs(const std::vector<std::vector<uint8_t>>& kinds);
 

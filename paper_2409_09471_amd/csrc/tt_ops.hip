@@ -135,15 +135,15 @@ void block_zero(Prec p, int B, int I, int Cn, void* out, int64_t sbo, int64_t si
 }  // namespace
 
 std::vector<std::vector<uint8_t>> operator_blocks(int d, const int* n, const std::vector<int>& R,
-                                                  const std::vector<const void*>& D, hipStream_t st) {
+                                                  const std::vector<const void*>& D, hipStream_t st, Arena& ar) {
     std::vector<std::vector<uint8_t>> out(d);
     if (D.empty()) return {};
     int64_t tot = 0;
     std::vector<int64_t> off(d + 1, 0);
     for (int mu = 0; mu < d; ++mu) off[mu + 1] = off[mu] + (int64_t)R[mu] * R[mu + 1];
     tot = off[d];
-    uint8_t* dev = nullptr;
-    TTSG_HIP(hipMallocAsync(reinterpret_cast<void**>(&dev), (size_t)std::max<int64_t>(tot, 1), st));
+    const size_t mk = ar.mark();
+    uint8_t* dev = ar.get<uint8_t>((size_t)std::max<int64_t>(tot, 1));
     for (int mu = 0; mu < d; ++mu) {
         hipLaunchKernelGGL(k_block_kinds, dim3(R[mu] * R[mu + 1]), dim3(256), 0, st, n[mu], R[mu + 1],
                            static_cast<const double*>(D[mu]), dev + off[mu]);
@@ -151,8 +151,8 @@ std::vector<std::vector<uint8_t>> operator_blocks(int d, const int* n, const std
     }
     std::vector<uint8_t> h((size_t)tot);
     TTSG_HIP(hipMemcpyAsync(h.data(), dev, (size_t)tot, hipMemcpyDeviceToHost, st));
-    TTSG_HIP(hipFreeAsync(dev, st));
     TTSG_HIP(hipStreamSynchronize(st));
+    ar.release(mk);
     for (int mu = 0; mu < d; ++mu) out[mu].assign(h.begin() + off[mu], h.begin() + off[mu + 1]);
     return out;
 }
