@@ -21,6 +21,10 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # packed FP32 instructions stay disabled in every device compilation
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs (gfx90a and later allow it): without
+    # this the contraction loops copy every accumulator into the AGPRs and back
+    # around each k-slab's MFMAs, draining the matrix pipeline every slab
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
 ]
 

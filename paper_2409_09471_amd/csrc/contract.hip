@@ -260,12 +260,15 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
         const uint64_t q = total / kXcds, r = total % kXcds;
         const uint64_t xcd = hw % kXcds, pos = hw / kXcds;
         const uint64_t t = xcd * q + (xcd < r ? xcd : r) + pos;
-        tx = (int)(t % gx);
-        ty = (int)((t / gx) % gy);
-        tz = (int)(t / (gx * gy));
+        // The divisions run on the vector ALU, so the compiler cannot tell that
+        // the tile is the same for every lane; saying so keeps the k-loop
+        // uniform (a scalar trip count, no exec-masked loop around the MFMAs).
+        tx = __builtin_amdgcn_readfirstlane((int)(t % gx));
+        ty = __builtin_amdgcn_readfirstlane((int)((t / gx) % gy));
+        tz = __builtin_amdgcn_readfirstlane((int)(t / (gx * gy)));
     }
     const int zz = batch0 + tz;
-    const int bidx = zz / splits;
+    const int bidx = __builtin_amdgcn_readfirstlane(zz / splits);
     const int split = zz - bidx * splits;
     const int kbeg = split * kchunk;
     const int kend = min(d.K, kbeg + kchunk);
