@@ -98,8 +98,10 @@ struct SlabLoader {
     Idx2 kix;
     int kend;
     bool k_fast;
+    bool k1;              // one-level k index (idx1: n0 at its sentinel): offsets advance linearly
     int fixed;            // kk (k-fast) or the row within the tile (row-fast)
     int64_t ro[PER];      // row offsets (k-fast: per element; row-fast: ro[0]); -1 = outside
+    int64_t kthr;         // row-fast, one-level: this thread's first k offset past k0
     in_t buf[PER];
 
     __device__ __forceinline__ void init(const in_t* G_, const Idx2& rowix, const Idx2& kix_, int row0, int nrows,
@@ -108,7 +110,9 @@ struct SlabLoader {
         kix = kix_;
         kend = kend_;
         k_fast = kf;
+        k1 = kix_.n0 == 0x7fffffff;
         const int tid = threadIdx.x;
+        kthr = (int64_t)(tid / ROWS) * kix_.s0;
         if (kf) {
             fixed = tid % BK;
 #pragma unroll
@@ -129,9 +133,17 @@ struct SlabLoader {
         if (k_fast) {
             const int gk = k0 + fixed;
             const bool kin = gk < kend;
-            const int64_t ko = kin ? idx_off(kix, gk) : 0;
+            const int64_t ko = kin ? (k1 ? (int64_t)gk * kix.s0 : idx_off(kix, gk)) : 0;
 #pragma unroll
             for (int t = 0; t < PER; ++t) buf[t] = (kin && ro[t] >= 0) ? G[ro[t] + ko] : in_t(0);
+        } else if (k1) {
+            // one-level k index: element t sits (256 / ROWS) t k-steps past the first
+            const in_t* g = G + ro[0] + (int64_t)k0 * kix.s0 + kthr;
+            const int64_t step = (int64_t)(256 / ROWS) * kix.s0;
+            const int gk0 = k0 + tid / ROWS;
+#pragma unroll
+            for (int t = 0; t < PER; ++t)
+                buf[t] = (gk0 + (256 / ROWS) * t < kend && ro[0] >= 0) ? g[t * step] : in_t(0);
         } else {
 #pragma unroll
             for (int t = 0; t < PER; ++t) {
