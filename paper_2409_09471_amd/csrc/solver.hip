@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 
 #include "tt_ops.h"
 #include "xlane.h"
@@ -234,6 +235,45 @@ void tt_add_block(int d, const int* n, const std::vector<int>& ra, const std::ve
                            rb[mu + 1], n[mu], first, last, a[mu], b[mu], out[mu], bscale, ascale);
     }
     TTSG_HIP(hipGetLastError());
+}
+
+// Side streams (non-blocking, default priority) and events of one solve.
+// Sets are created on first use per device and kept for the process; a solve
+// takes one from the pool and returns it after draining its streams, so
+// concurrent solves (the batched entry point's workers) each hold their own.
+struct StreamSet {
+    int dev = -1;
+    hipStream_t k = nullptr, h = nullptr, r = nullptr;
+    hipEvent_t ev[9] = {};
+};
+
+std::mutex g_set_mu;
+std::vector<StreamSet> g_sets;
+
+StreamSet acquire_stream_set() {
+    int dev = 0;
+    TTSG_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_set_mu);
+        for (size_t i = 0; i < g_sets.size(); ++i)
+            if (g_sets[i].dev == dev) {
+                StreamSet s = g_sets[i];
+                g_sets.erase(g_sets.begin() + (ptrdiff_t)i);
+                return s;
+            }
+    }
+    StreamSet s;
+    s.dev = dev;
+    TTSG_HIP(hipStreamCreateWithFlags(&s.k, hipStreamNonBlocking));
+    TTSG_HIP(hipStreamCreateWithFlags(&s.h, hipStreamNonBlocking));
+    TTSG_HIP(hipStreamCreateWithFlags(&s.r, hipStreamNonBlocking));
+    for (hipEvent_t& e : s.ev) TTSG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return s;
+}
+
+void release_stream_set(const StreamSet& s) {
+    std::lock_guard<std::mutex> lk(g_set_mu);
+    g_sets.push_back(s);
 }
 
 class SgmresSolver {
@@ -528,45 +568,44 @@ int SgmresSolver::run(double* const* x_out, int32_t* x_r, ttsg_sgmres_info* info
     // Omega sketches on side stream R, its left sweep and Psi sketches here.
     // With single_stream the three are the caller's stream itself: the events
     // then order nothing that program order does not already order.
+    // The streams and events come from a per-process pool (created once per
+    // device and reused by later solves) instead of being created and
+    // destroyed by every solve.
     struct SideStreams {
+        StreamSet set;
         hipStream_t k = nullptr, h = nullptr, r = nullptr;
-        bool own = true;
         hipEvent_t v = nullptr, hd = nullptr;
         hipEvent_t zr = nullptr, kd = nullptr;   // a preconditioner term is in place / read by stream K
         hipEvent_t hz = nullptr;                 // ... / read by stream H
         hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+        bool held = false;
         ~SideStreams() {
-            if (k) (void)hipStreamSynchronize(k);
-            if (h) (void)hipStreamSynchronize(h);
-            if (r) (void)hipStreamSynchronize(r);
-            if (v) (void)hipEventDestroy(v);
-            if (hd) (void)hipEventDestroy(hd);
-            if (zr) (void)hipEventDestroy(zr);
-            if (kd) (void)hipEventDestroy(kd);
-            if (hz) (void)hipEventDestroy(hz);
-            for (hipEvent_t e : ev)
-                if (e) (void)hipEventDestroy(e);
-            if (own && k) (void)hipStreamDestroy(k);
-            if (own && h) (void)hipStreamDestroy(h);
-            if (own && r) (void)hipStreamDestroy(r);
+            if (!held) return;
+            // every side stream drained before the set (and this solve's
+            // workspace) can be used again
+            (void)hipStreamSynchronize(k);
+            (void)hipStreamSynchronize(h);
+            (void)hipStreamSynchronize(r);
+            release_stream_set(set);
         }
     } side;
+    side.set = acquire_stream_set();
+    side.held = true;
     if (in_.single_stream) {
-        side.own = false;
         side.k = side.h = side.r = st_;
     } else {
-        TTSG_HIP(hipStreamCreateWithFlags(&side.k, hipStreamNonBlocking));
-        TTSG_HIP(hipStreamCreateWithFlags(&side.h, hipStreamNonBlocking));
-        TTSG_HIP(hipStreamCreateWithFlags(&side.r, hipStreamNonBlocking));
+        side.k = side.set.k;
+        side.h = side.set.h;
+        side.r = side.set.r;
     }
-    TTSG_HIP(hipEventCreateWithFlags(&side.v, hipEventDisableTiming));
-    TTSG_HIP(hipEventCreateWithFlags(&side.hd, hipEventDisableTiming));
-    TTSG_HIP(hipEventCreateWithFlags(&side.zr, hipEventDisableTiming));
-    TTSG_HIP(hipEventCreateWithFlags(&side.kd, hipEventDisableTiming));
+    side.v = side.set.ev[0];
+    side.hd = side.set.ev[1];
+    side.zr = side.set.ev[2];
+    side.kd = side.set.ev[3];
+    side.hz = side.set.ev[4];
+    for (int i = 0; i < 4; ++i) side.ev[i] = side.set.ev[5 + i];
     TTSG_HIP(hipEventRecord(side.kd, side.k));
-    TTSG_HIP(hipEventCreateWithFlags(&side.hz, hipEventDisableTiming));
     TTSG_HIP(hipEventRecord(side.hz, side.h));
-    for (hipEvent_t& e : side.ev) TTSG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     SketchSide sk_side;
     sk_side.st = side.r;
     sk_side.ar = &scratchR_;
