@@ -77,58 +77,58 @@ __global__ __launch_bounds__(256) void k_block_kinds(int n, int Rr, const double
     if (threadIdx.x == 0) out[blockIdx.x] = (flags & 1) == 0 ? kBlkZero : ((flags & 2) == 0 ? kBlkIdentity : kBlkDense);
 }
 
-// out[b][i][c] = in[b][i][c] (+ out[b][i][c] when acc) for b < B, i < I, c < Cn
+// out[b][i][c] = in[b][i][c] (+ out[b][i][c] when acc), or 0, for b < B,
+// i < I, c < Cn (c contiguous): a workgroup of 64 x 4 lanes covers 64
+// consecutive c of 4 rows i of one b, so every index comes from the grid
+// without a division.
+constexpr int BLK_C = 64, BLK_I = 4;
+
 template <typename T>
-__global__ void k_block_copy(int64_t total, int I, int Cn, const T* __restrict__ in, int64_t sbi, int64_t sii,
-                             T* __restrict__ out, int64_t sbo, int64_t sio, int acc) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t bi = e / Cn;
-        const int c = (int)(e - bi * Cn);
-        const int64_t b = bi / I;
-        const int i = (int)(bi - b * I);
-        const T v = in[b * sbi + i * sii + c];
-        T* o = out + b * sbo + i * sio + c;
-        *o = acc ? *o + v : v;
-    }
+__global__ __launch_bounds__(256) void k_block_copy(int I, int Cn, const T* __restrict__ in, int64_t sbi, int64_t sii,
+                                                    T* __restrict__ out, int64_t sbo, int64_t sio, int acc) {
+    const int c = blockIdx.x * BLK_C + (int)(threadIdx.x % BLK_C);
+    const int i = blockIdx.y * BLK_I + (int)(threadIdx.x / BLK_C);
+    const int64_t b = blockIdx.z;
+    if (c >= Cn || i >= I) return;
+    const T v = in[b * sbi + i * sii + c];
+    T* o = out + b * sbo + i * sio + c;
+    *o = acc ? *o + v : v;
 }
 
 template <typename T>
-__global__ void k_block_zero(int64_t total, int I, int Cn, T* __restrict__ out, int64_t sbo, int64_t sio) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t bi = e / Cn;
-        const int c = (int)(e - bi * Cn);
-        const int64_t b = bi / I;
-        const int i = (int)(bi - b * I);
-        out[b * sbo + i * sio + c] = T(0);
-    }
+__global__ __launch_bounds__(256) void k_block_zero(int I, int Cn, T* __restrict__ out, int64_t sbo, int64_t sio) {
+    const int c = blockIdx.x * BLK_C + (int)(threadIdx.x % BLK_C);
+    const int i = blockIdx.y * BLK_I + (int)(threadIdx.x / BLK_C);
+    const int64_t b = blockIdx.z;
+    if (c >= Cn || i >= I) return;
+    out[b * sbo + i * sio + c] = T(0);
+}
+
+dim3 block_grid(int B, int I, int Cn) {
+    TTSG_CHECK(B <= 65535 && (I + BLK_I - 1) / BLK_I <= 65535, TTSG_ERR_ARG, "block copy: extent too large");
+    return dim3((unsigned)((Cn + BLK_C - 1) / BLK_C), (unsigned)((I + BLK_I - 1) / BLK_I), (unsigned)B);
 }
 
 void block_copy(Prec p, int B, int I, int Cn, const void* in, int64_t sbi, int64_t sii, void* out, int64_t sbo,
                 int64_t sio, bool acc, hipStream_t st) {
-    const int64_t total = (int64_t)B * I * Cn;
-    if (total <= 0) return;
-    const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 16384);
+    if (B <= 0 || I <= 0 || Cn <= 0) return;
+    const dim3 g = block_grid(B, I, Cn);
     if (p == Prec::F64)
-        hipLaunchKernelGGL(k_block_copy<double>, dim3(g), dim3(256), 0, st, total, I, Cn,
-                           static_cast<const double*>(in), sbi, sii, static_cast<double*>(out), sbo, sio, acc ? 1 : 0);
+        hipLaunchKernelGGL(k_block_copy<double>, g, dim3(256), 0, st, I, Cn, static_cast<const double*>(in), sbi, sii,
+                           static_cast<double*>(out), sbo, sio, acc ? 1 : 0);
     else
-        hipLaunchKernelGGL(k_block_copy<float>, dim3(g), dim3(256), 0, st, total, I, Cn,
-                           static_cast<const float*>(in), sbi, sii, static_cast<float*>(out), sbo, sio, acc ? 1 : 0);
+        hipLaunchKernelGGL(k_block_copy<float>, g, dim3(256), 0, st, I, Cn, static_cast<const float*>(in), sbi, sii,
+                           static_cast<float*>(out), sbo, sio, acc ? 1 : 0);
     TTSG_HIP(hipGetLastError());
 }
 
 void block_zero(Prec p, int B, int I, int Cn, void* out, int64_t sbo, int64_t sio, hipStream_t st) {
-    const int64_t total = (int64_t)B * I * Cn;
-    if (total <= 0) return;
-    const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 16384);
+    if (B <= 0 || I <= 0 || Cn <= 0) return;
+    const dim3 g = block_grid(B, I, Cn);
     if (p == Prec::F64)
-        hipLaunchKernelGGL(k_block_zero<double>, dim3(g), dim3(256), 0, st, total, I, Cn, static_cast<double*>(out),
-                           sbo, sio);
+        hipLaunchKernelGGL(k_block_zero<double>, g, dim3(256), 0, st, I, Cn, static_cast<double*>(out), sbo, sio);
     else
-        hipLaunchKernelGGL(k_block_zero<float>, dim3(g), dim3(256), 0, st, total, I, Cn, static_cast<float*>(out),
-                           sbo, sio);
+        hipLaunchKernelGGL(k_block_zero<float>, g, dim3(256), 0, st, I, Cn, static_cast<float*>(out), sbo, sio);
     TTSG_HIP(hipGetLastError());
 }
 
