@@ -409,9 +409,23 @@ __global__ __launch_bounds__(256) void reduce_splits(ContractDesc d, int splits,
 #pragma unroll
         for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
         if (g == 0) {
-            const int b = (int)(e / per);
-            const int64_t mn = e - (int64_t)b * per;
-            const int m = (int)(mn / d.N), n = (int)(mn - (int64_t)m * d.N);
+            // element -> (b, m, n): 32-bit divisions when the indices fit
+            // (64-bit ones expand into long vector-ALU sequences)
+            int b, m, n;
+            if (total < ((int64_t)1 << 31)) {
+                const unsigned e32 = (unsigned)e, pr = (unsigned)per;
+                const unsigned bb = d.batch == 1 ? 0u : e32 / pr;
+                const unsigned mn = e32 - bb * pr;
+                const unsigned mm = mn / (unsigned)d.N;
+                b = (int)bb;
+                m = (int)mm;
+                n = (int)(mn - mm * (unsigned)d.N);
+            } else {
+                b = (int)(e / per);
+                const int64_t mn = e - (int64_t)b * per;
+                m = (int)(mn / d.N);
+                n = (int)(mn - (int64_t)m * d.N);
+            }
             const int64_t off = idx_off(d.cb, b) + idx_off(d.cm, m) + idx_off(d.cn, n);
             if (sizeof(O) == 4 && d.c_f64 != 0) {
                 double* Cw = reinterpret_cast<double*>(C);
