@@ -138,3 +138,31 @@ def test_preconditioned_batch_equals_one_by_one():
         its.append(b.iterations)
     print("preconditioned batch iterations", its, flush=True)
     assert max(its) <= 12
+
+
+def test_batched_full_size_systems_match_oracle_first_iterations():
+    """Three systems of the 64-system batched workload at their full size (caps
+    32, s = 1000: d = 6 and 7 with n = 32, d = 7 with n = 128), solved in one
+    batch in FP64: the first three sketched residuals of each agree with the
+    oracle's sketched TT-GMRES run for three iterations on the same inputs (to
+    1e-5 relative: both round every basis vector at 1e-7, with different QR and
+    SVD algorithms)."""
+    ttsg = _ttsg()
+    table = syn.config_c3_systems(64)
+    systems, ws = [], []
+    for i in (30, 62, 3):
+        d, n, rb = table[i]
+        w = syn.config_c3_system(i, d, n, rb, maxit=40)
+        ws.append(w)
+        systems.append(ttsg.BatchSystem(
+            A=ttsg.kron_sum_operator(w.terms, DEV), b=ttsg.to_device(w.b, DEV), S=ttsg.to_device(w.S, DEV),
+            X=ttsg.to_device(w.X, DEV), Y=ttsg.to_device(w.Y, DEV), rx=w.rx, rho=w.rho, maxit=w.maxit, tol=w.tol,
+            q=w.q, round_tol=w.round_tol, maxrank=w.cap, stop_safety=w.stop_safety, precision=ttsg.PREC_F64))
+    res = ttsg.sgmres_solve_batched(systems, concurrency=3)
+    for w, r in zip(ws, res):
+        assert r.status >= 0 and len(r.sketched_history) >= 3
+        _, info = osol.tt_sgmres(oops.tt_kron_sum(w.terms), w.b, w.S, w.X, w.Y, maxit=3, tol=w.tol, q=w.q,
+                                 round_tol=w.round_tol, maxrank=w.cap, stop_safety=w.stop_safety)
+        ko = info["sketched_residuals"]
+        for k in range(3):
+            assert abs(r.sketched_history[k] - ko[k]) <= 1e-5 * ko[k], (w.name, k, r.sketched_history[k], ko[k])
