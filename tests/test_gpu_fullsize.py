@@ -15,7 +15,9 @@ iteration on the host), so it checks what it can compute at this size:
   library's own figure comes from ||b||^2 - 2 <A x, b> + ||A x||^2 in FP64,
   whose cancellation at a residual of 5e-7 leaves about 1e-15 / 2.5e-13 of
   relative error in the square, a few 1e-3 in the residual: the two agree to
-  2e-2 relative."""
+  2e-2 relative;
+* the STTA and Khatri-Rao sketches of A x for a rank-64 x in FP64, FP32 and
+  BF16, array by array against the oracle's (the Khatri-Rao rows sampled)."""
 import pytest
 
 import synthetic as syn
@@ -73,3 +75,40 @@ def test_fullsize_solution_true_residual(workload, precision):
     else:
         assert abs(res - r.true_residual) <= 2e-2 * res, (res, r.true_residual)
     assert all(int(c.shape[0]) <= w.cap and int(c.shape[2]) <= w.cap for c in r.x)
+
+
+@pytest.fixture(scope="module")
+def fullsize_vector(workload):
+    """A rank-64 Gaussian TT vector at the d = 10, n = 64 shape and the
+    oracle's A x (rank 192, formed explicitly)."""
+    import numpy as np
+    from oracle import tt as ott
+    w, _, A = workload
+    rng = np.random.default_rng(21)
+    x = syn.gaussian_tt(rng, w.ns, [1] + [w.cap] * (w.d - 1) + [1])
+    return x, ott.matvec(A, x)
+
+
+# The sketches of A x at the benchmarked shape in each arithmetic, against the
+# oracle array by array (relative norm per array).  FP32: unit roundoff 6e-8 per
+# stage, 2e-5 as in the small parity tests.  BF16 rounds the operands of every
+# stage to 8 significant bits: a chain of d = 10 stages errs by up to about
+# d 2^-8 = 0.04 norm-wise, so 2 d 2^-8 bounds it, far below a wrong result's O(1).
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5), (2, 2 * 10 * 2.0 ** -8)])
+def test_fullsize_sketches_match_oracle(workload, fullsize_vector, precision, tol):
+    import numpy as np
+    from oracle import sketch as osk
+    from paper_2409_09471_amd import ttsg
+    w, t, _ = workload
+    x, Ax = fullsize_vector
+    xs = ttsg.to_device(x, DEV)
+    Psi, Om = ttsg.stta_sketch(xs, t["X"], t["Y"], w.rx, w.rho, A=t["A"], precision=precision)
+    Po, Oo = osk.stta_sketch(Ax, w.X, w.Y)
+    for a, b in list(zip(Psi, Po)) + list(zip(Om, Oo)):
+        a = a.double().cpu().numpy()
+        assert np.linalg.norm(a - b.reshape(a.shape)) <= tol * np.linalg.norm(b)
+    # Khatri-Rao sketch: its rows are independent, so the oracle computes the
+    # first 100 of the s = 1000 (its full sketch takes half a minute on the host)
+    kr = ttsg.kr_sketch(t["S"], xs, A=t["A"], precision=precision).double().cpu().numpy()
+    ko = osk.kr_sketch([S[:100] for S in w.S], Ax)
+    assert np.linalg.norm(kr[:100] - ko) <= tol * np.linalg.norm(ko)
