@@ -4,11 +4,15 @@
 // record the earliest start and latest end of the GPU wall clock.  The
 // duration of a launch is therefore the time its kernel actually ran, not the
 // gap between host-side events (which would include submission latency
-// whenever the stream had drained).
+// whenever the stream had drained).  A class's busy time is the union of its
+// launches' intervals: below the summed durations when launches of the class
+// overlap on several streams.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
+#include <utility>
+#include <vector>
 
 #include "ttsg_internal.h"
 
