@@ -166,10 +166,11 @@ struct SlabLoader {
 
 // A operand of a Khatri-Rao step formed while it is staged: row m = (j, be),
 // column k = (a, i), value sum_al P[j][al][a] SA[j][al][be][i], the RL terms
-// added in order.  Each thread owns two consecutive k of its rows, so (for even
-// n) the two S A values come in one 16-byte load and the P value, the same for
-// both, in one: half the load instructions of one k per thread, which is what
-// the loader's time went on.  fetch() only issues the loads (they complete
+// added in order.  Each thread owns KG consecutive k of its rows (two for
+// 32-row tiles, four for taller ones), so (for n a multiple of KG) the S A
+// values come in 16-byte loads of two and the P value, the same for the whole
+// group, in one: a half to a quarter of the load instructions of one k per
+// thread, which is what the loader's time went on.  fetch() only issues the loads (they complete
 // while the matrix cores work on the current slab); commit() forms the sums as
 // it writes the LDS slab.  The s R r n intermediate is never stored.
 template <typename T>
@@ -182,16 +183,17 @@ struct KrLoader {
     using in_t = typename Traits<T>::in_t;
     using lds_t = typename Traits<T>::lds_t;
     static constexpr int BK = Traits<T>::BK;
-    static constexpr int KP = BK / 2;             // k pairs per slab
-    static constexpr int RP = 256 / KP;           // rows per pass
-    static constexpr int PER = ROWS / RP;         // passes (rows per thread)
+    static constexpr int KG = ROWS >= 64 ? 4 : 2;  // consecutive k per thread
+    static constexpr int NG = BK / KG;             // k groups per slab
+    static constexpr int RP = 256 / NG;            // rows per pass
+    static constexpr int PER = ROWS / RP;          // passes (rows per thread)
     static_assert(ROWS % RP == 0, "tile rows");
     const in_t* P;
     const in_t* SA;
     int rl, n, Rr, kend;
-    bool even;                  // n even: a thread's two k share a and the S A pair is one aligned load
+    bool grp;                   // n % KG == 0: a thread's k share a, and the S A run is aligned loads
     int64_t pb[PER], sb[PER];   // per row: P offset of (j, 0, 0), SA offset of (j, 0, be, 0); pb < 0: outside
-    in_t pv[PER][2][RL], sv[PER][2][RL];
+    in_t pv[PER][KG][RL], sv[PER][KG][RL];
 
     __device__ __forceinline__ void init(const ContractDesc& d, int row0, int kend_) {
         P = static_cast<const in_t*>(d.kr_P);
@@ -200,11 +202,11 @@ struct KrLoader {
         n = d.kr_n;
         Rr = d.kr_Rr;
         kend = kend_;
-        even = (n & 1) == 0;
+        grp = n % KG == 0;
         const int tid = threadIdx.x;
 #pragma unroll
         for (int t = 0; t < PER; ++t) {
-            const int gr = row0 + tid / KP + RP * t;
+            const int gr = row0 + tid / NG + RP * t;
             if (gr < d.M) {
                 const int64_t j = gr / Rr;
                 const int be = gr - (int)(j * Rr);
@@ -216,13 +218,13 @@ struct KrLoader {
             }
         }
     }
-    // thread tid owns k = k0 + 2 (tid % KP) + {0, 1} of rows tid / KP + RP t
+    // thread tid owns k = k0 + KG (tid % NG) + {0 .. KG-1} of rows tid / NG + RP t
     __device__ __forceinline__ void fetch(int k0) {
-        const int gk = k0 + 2 * (int)(threadIdx.x % KP);
+        const int gk = k0 + KG * (int)(threadIdx.x % NG);
         const int64_t nR = (int64_t)n * Rr;
-        if (even) {
-            // k even, n even: i even, i + 1 < n, the same a for both k; the
-            // S A offset is even, so the pair is one aligned load (kend is even)
+        if (grp) {
+            // gk and n multiples of KG: i + KG - 1 < n, one a for the group, the
+            // S A run starts at an offset that is a multiple of KG (kend is too)
             const bool kin = gk < kend;
             const int a = kin ? gk / n : 0;
             const int i = kin ? gk - a * n : 0;
@@ -232,17 +234,20 @@ struct KrLoader {
 #pragma unroll
                 for (int al = 0; al < RL; ++al) {
                     const in_t p = on ? P[pb[t] + a + (int64_t)al * rl] : in_t(0);
-                    Pair2<in_t> q{in_t(0), in_t(0)};
-                    if (on) q = *reinterpret_cast<const Pair2<in_t>*>(SA + sb[t] + i + al * nR);
-                    pv[t][0][al] = p;
-                    pv[t][1][al] = p;
-                    sv[t][0][al] = q.x;
-                    sv[t][1][al] = q.y;
+#pragma unroll
+                    for (int h = 0; h < KG / 2; ++h) {
+                        Pair2<in_t> q{in_t(0), in_t(0)};
+                        if (on) q = *reinterpret_cast<const Pair2<in_t>*>(SA + sb[t] + i + 2 * h + al * nR);
+                        pv[t][2 * h][al] = p;
+                        pv[t][2 * h + 1][al] = p;
+                        sv[t][2 * h][al] = q.x;
+                        sv[t][2 * h + 1][al] = q.y;
+                    }
                 }
             }
         } else {
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
+            for (int e = 0; e < KG; ++e) {
                 const int g = gk + e;
                 const bool kin = g < kend;
                 const int a = kin ? g / n : 0;
@@ -261,15 +266,15 @@ struct KrLoader {
     }
     __device__ __forceinline__ void commit(lds_t (*S)[ROWS + 1]) const {
         const int tid = threadIdx.x;
-        const int kp = tid % KP;
+        const int kg = tid % NG;
 #pragma unroll
         for (int t = 0; t < PER; ++t)
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
+            for (int e = 0; e < KG; ++e) {
                 in_t acc = in_t(0);
 #pragma unroll
                 for (int al = 0; al < RL; ++al) acc += pv[t][e][al] * sv[t][e][al];
-                S[2 * kp + e][tid / KP + RP * t] = Traits<T>::stage(acc);
+                S[KG * kg + e][tid / NG + RP * t] = Traits<T>::stage(acc);
             }
     }
 };
