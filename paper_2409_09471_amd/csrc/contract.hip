@@ -412,6 +412,7 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
     // float32 arithmetic may write a float64 output (its strides count doubles)
     const bool wide = sizeof(out_t) == 4 && d.c_f64 != 0;
     double* Cw = reinterpret_cast<double*>(C) + idx_off(d.cb, bidx);
+    const out_t* Xb = d.c_add != nullptr ? static_cast<const out_t*>(d.c_add) + idx_off(d.xb, bidx) : nullptr;
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -432,6 +433,7 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractDesc d, const typ
                         int64_t off = idx_off(d.cm, row) + idx_off(d.cn, col);
                         out_t v = alpha * (out_t)acc[i][j][r];
                         if (beta != out_t(0)) v += beta * Cb[off];
+                        if (Xb != nullptr) v += Xb[idx_off(d.xm, row) + idx_off(d.xn, col)];
                         Cb[off] = v;
                     }
                 }
@@ -482,6 +484,8 @@ __global__ __launch_bounds__(256) void reduce_splits(ContractDesc d, int splits,
             } else {
                 O v = alpha * acc;
                 if (beta != O(0)) v += beta * C[off];
+                if (d.c_add != nullptr)
+                    v += static_cast<const O*>(d.c_add)[idx_off(d.xb, b) + idx_off(d.xm, m) + idx_off(d.xn, n)];
                 C[off] = v;
             }
         }
@@ -635,6 +639,7 @@ int tune(const TuneKey& key, const ContractDesc& d, const void* A, const void* B
     ContractDesc dc = d;
     dc.beta = 0.0;
     dc.c_f64 = 0;   // timed into a scratch of the arithmetic's type
+    dc.c_add = nullptr;
     dc.cb = idx1((int64_t)d.M * d.N);
     dc.cm = idx1(d.N);
     dc.cn = idx1(1);
@@ -673,6 +678,7 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
     if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
     TTSG_CHECK(d.c_f64 == 0 || sizeof(typename Traits<T>::out_t) == 4, TTSG_ERR_ARG,
                "contraction: a float64 output needs float32 arithmetic");
+    TTSG_CHECK(d.c_add == nullptr || d.c_f64 == 0, TTSG_ERR_ARG, "contraction: an addend needs C in the arithmetic's type");
     using in_t = typename Traits<T>::in_t;
     if (bounds_checking()) {
         using out_t = typename Traits<T>::out_t;
@@ -690,6 +696,10 @@ void launch(const ContractDesc& d, const void* A, const void* B, void* C, hipStr
         }
         check_range(B, eb * sizeof(in_t), "contract B");
         check_range(C, ec * (d.c_f64 ? sizeof(double) : sizeof(out_t)), "contract C");
+        if (d.c_add != nullptr) {
+            const int64_t ex = idx_max(d.xb, d.batch) + idx_max(d.xm, d.M) + idx_max(d.xn, d.N) + 1;
+            check_range(d.c_add, ex * sizeof(out_t), "contract addend");
+        }
     }
     const int cls = sizeof(typename Traits<T>::lds_t) == 8
                         ? TTSG_ST_CONTRACT_F64

@@ -190,9 +190,22 @@ void left_step(Prec p, const LeftDims& s, const void* E, const void* C, const vo
         const size_t es = elem_size(p);
         for (int be = 0; be < Rr; ++be) {
             bool first = true;
+            // the sum runs over the nonzero blocks in ascending al; when its first
+            // two are one identity and one dense block, the dense block's
+            // contraction adds the identity's slice of T1 in its epilogue (the
+            // same sum, one launch instead of two)
+            int nz[8], nn = 0;
+            for (int al = 0; al < Rl && nn < 8; ++al)
+                if (s.blk[al * Rr + be] != kBlkZero) nz[nn++] = al;
+            int skip = -1, add = -1;
+            if (nn >= 2 && Rl <= 8) {
+                const uint8_t k0 = s.blk[nz[0] * Rr + be], k1 = s.blk[nz[1] * Rr + be];
+                if (k0 == kBlkIdentity && k1 == kBlkDense) skip = nz[0], add = nz[0];
+                if (k0 == kBlkDense && k1 == kBlkIdentity) skip = nz[1], add = nz[1];
+            }
             for (int al = 0; al < Rl; ++al) {
                 const uint8_t kind = s.blk[al * Rr + be];
-                if (kind == kBlkZero) continue;
+                if (kind == kBlkZero || al == skip) continue;
                 void* Cb = static_cast<char*>(T2) + (size_t)be * rr * es;
                 const void* Bb = static_cast<const char*>(T1) + (size_t)al * n * rr * es;
                 if (kind == kBlkIdentity) {
@@ -210,6 +223,12 @@ void left_step(Prec p, const LeftDims& s, const void* E, const void* C, const vo
                     d.cm = idx1((int64_t)Rr * rr);
                     d.cn = idx1(1);
                     d.beta = first ? 0.0 : 1.0;
+                    if (first && add >= 0) {
+                        d.c_add = static_cast<const char*>(T1) + (size_t)add * n * rr * es;
+                        d.xb = idx1((int64_t)Rl * n * rr);
+                        d.xm = idx1(rr);
+                        d.xn = idx1(1);
+                    }
                     contract(p, d, static_cast<const char*>(D) + ((size_t)al * n * n * Rr + be) * es, Bb, Cb, st, ar);
                 }
                 first = false;
@@ -271,9 +290,20 @@ void right_step(Prec p, const LeftDims& s, const void* F, const void* C, const v
         for (int al = 0; al < Rl; ++al) {
             bool first = true;
             void* Cb = static_cast<char*>(U2) + (size_t)al * n * pr * es;
+            // as in left_step: a leading (identity, dense) pair in ascending be
+            // is one contraction whose epilogue adds the identity's slice of U1
+            int nz[8], nn = 0;
+            for (int be = 0; be < Rr && nn < 8; ++be)
+                if (s.blk[al * Rr + be] != kBlkZero) nz[nn++] = be;
+            int skip = -1, add = -1;
+            if (nn >= 2 && Rr <= 8) {
+                const uint8_t k0 = s.blk[al * Rr + nz[0]], k1 = s.blk[al * Rr + nz[1]];
+                if (k0 == kBlkIdentity && k1 == kBlkDense) skip = nz[0], add = nz[0];
+                if (k0 == kBlkDense && k1 == kBlkIdentity) skip = nz[1], add = nz[1];
+            }
             for (int be = 0; be < Rr; ++be) {
                 const uint8_t kind = s.blk[al * Rr + be];
-                if (kind == kBlkZero) continue;
+                if (kind == kBlkZero || be == skip) continue;
                 const void* Bb = static_cast<const char*>(U1) + (size_t)be * pr * es;
                 if (kind == kBlkIdentity) {
                     block_copy(p, rl, n, pr, Bb, (int64_t)n * Rr * pr, (int64_t)Rr * pr, Cb, (int64_t)Rl * n * pr, pr,
@@ -290,6 +320,12 @@ void right_step(Prec p, const LeftDims& s, const void* F, const void* C, const v
                     d.cm = idx1(pr);
                     d.cn = idx1(1);
                     d.beta = first ? 0.0 : 1.0;
+                    if (first && add >= 0) {
+                        d.c_add = static_cast<const char*>(U1) + (size_t)add * pr * es;
+                        d.xb = idx1((int64_t)n * Rr * pr);
+                        d.xm = idx1((int64_t)Rr * pr);
+                        d.xn = idx1(1);
+                    }
                     contract(p, d, static_cast<const char*>(D) + ((size_t)al * n * n * Rr + be) * es, Bb, Cb, st, ar);
                 }
                 first = false;

@@ -131,6 +131,11 @@ struct ContractDesc {
     const void* kr_P;
     const void* kr_SA;
     int32_t kr_rl, kr_n, kr_Rl, kr_Rr;
+    // Optional addend (c_add != nullptr, C's element type, c_f64 == 0):
+    // C = alpha A B + beta C + X with X[b][m][n] at strides xb/xm/xn, added
+    // last (the identity block of an operator step summed with a dense one).
+    const void* c_add;
+    Idx2 xb, xm, xn;
 };
 
 // Arithmetic of the contraction kernels.  F32 and BF16 share float32
